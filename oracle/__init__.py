@@ -1,0 +1,207 @@
+"""Serial FP64 CPU oracle for the regularised correlation-clustering LP.
+
+Test infrastructure only: the tests, the smoke check and the CPU-baseline leg
+of the benchmark use it to check and time the GPU library; the GPU library
+never loads it and it never loads the GPU library.  The arithmetic lives in
+``ccoracle.c`` (Algorithm 1 taken literally, in the tiled schedule order of
+Sec. III); this file only marshals numpy arrays, plus a float64 reference of
+the warm-start network in ``mlp_ref``.
+
+Layouts: pairs packed column-major, p(i, j) = j (j - 1) / 2 + i; metric duals
+in colex triplet order y[3 t + o], t = C(k,3) + C(j,2) + i; pair duals
+y_pair[2 p + c].
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "ccoracle.c")
+_LIB = os.environ.get("CCORACLE_LIB") or os.path.join(_HERE, "libccoracle.so")
+
+_i64 = ctypes.c_int64
+_i32 = ctypes.c_int32
+_dbl = ctypes.c_double
+_p = ctypes.c_void_p
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle with gcc (plain IEEE FP64, no contraction)."""
+    if force or not os.path.exists(_LIB):
+        tmp = _LIB + ".tmp"
+        subprocess.check_call(["gcc", "-O2", "-ffp-contract=off", "-fno-fast-math",
+                               "-std=c99", "-Wall", "-fPIC", "-shared", "-o", tmp, _SRC,
+                               "-lm"])
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+class Resid(ctypes.Structure):
+    _fields_ = [(k, _dbl) for k in ("max_viol_metric", "max_viol_pair", "primal_qp",
+                                     "dual_qp", "gap", "lp_cost", "cs_max", "stat_resid")]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.environ.get("CCORACLE_LIB") and (
+                not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC)):
+            build()
+        L = ctypes.CDLL(_LIB)
+        L.orc_schedule.argtypes = [_i64, _i64, _p, _i64]
+        L.orc_schedule.restype = _i64
+        L.orc_init_cold.argtypes = [_i64, _dbl, _p, _p, _p, _p, _p]
+        L.orc_init_cold.restype = None
+        L.orc_sweeps.argtypes = [_i64, _i64, _dbl, _p, _p, _p, _p, _p, _p, _i32, _i32]
+        L.orc_sweeps.restype = ctypes.c_int
+        L.orc_pair_pass.argtypes = [_i64, _dbl, _p, _p, _p, _p, _p]
+        L.orc_pair_pass.restype = ctypes.c_int
+        L.orc_round_prefix.argtypes = [_i64, _i64, _dbl, _p, _p, _i64, _p, _p, _p, _i64]
+        L.orc_round_prefix.restype = _i64
+        L.orc_x_from_y.argtypes = [_i64, _dbl, _p, _p, _p, _p, _p]
+        L.orc_x_from_y.restype = ctypes.c_int
+        L.orc_residuals.argtypes = [_i64, _dbl, _p, _p, _p, _p, _p, _p, ctypes.POINTER(Resid)]
+        L.orc_residuals.restype = ctypes.c_int
+        L.orc_dual_objective.argtypes = [_i64, _dbl, _p, _p, _p, _p]
+        L.orc_dual_objective.restype = _dbl
+        _lib = L
+    return _lib
+
+
+def _ptr(a):
+    return None if a is None else a.ctypes.data
+
+
+def _f64(a):
+    a = np.ascontiguousarray(a, dtype=np.float64)
+    return a
+
+
+def num_pairs(n):
+    return n * (n - 1) // 2
+
+
+def num_triplets(n):
+    return n * (n - 1) * (n - 2) // 6
+
+
+class State:
+    """Oracle iterate: x, f (per pair), y (colex metric duals), y_pair."""
+
+    def __init__(self, n, gamma, w, d, dense_duals=True):
+        self.n = int(n)
+        self.gamma = float(gamma)
+        self.w = _f64(w)
+        self.d = np.ascontiguousarray(d, dtype=np.uint8)
+        npairs = num_pairs(self.n)
+        assert self.w.shape == (npairs,) and self.d.shape == (npairs,)
+        self.x = np.zeros(npairs)
+        self.f = np.zeros(npairs)
+        self.y = np.zeros(3 * num_triplets(self.n)) if dense_duals else None
+        self.y_pair = np.zeros(2 * npairs)
+        self.sweeps = 0
+        self.init_cold()
+
+    @classmethod
+    def from_instance(cls, inst, **kw):
+        return cls(inst.n, inst.gamma, inst.w, inst.d, **kw)
+
+    def init_cold(self):
+        lib().orc_init_cold(self.n, self.gamma, _ptr(self.w), _ptr(self.x), _ptr(self.f),
+                            _ptr(self.y), _ptr(self.y_pair))
+        self.sweeps = 0
+
+    def sweep(self, nsweeps=1, b=8, order="schedule"):
+        assert self.y is not None
+        rc = lib().orc_sweeps(self.n, int(b), self.gamma, _ptr(self.w), _ptr(self.d),
+                              _ptr(self.x), _ptr(self.f), _ptr(self.y), _ptr(self.y_pair),
+                              int(nsweeps), 0 if order == "schedule" else 1)
+        if rc != 0:
+            raise ValueError("oracle sweep rejected its input")
+        self.sweeps += nsweeps
+
+    def residuals(self) -> dict:
+        out = Resid()
+        rc = lib().orc_residuals(self.n, self.gamma, _ptr(self.w), _ptr(self.d),
+                                 _ptr(self.x), _ptr(self.f), _ptr(self.y),
+                                 _ptr(self.y_pair), ctypes.byref(out))
+        if rc != 0:
+            raise MemoryError
+        return out.as_dict()
+
+    def dual_objective(self) -> float:
+        return lib().orc_dual_objective(self.n, self.gamma, _ptr(self.w), _ptr(self.d),
+                                        _ptr(self.y), _ptr(self.y_pair))
+
+    def x_from_y(self):
+        x = np.zeros_like(self.x)
+        f = np.zeros_like(self.f)
+        lib().orc_x_from_y(self.n, self.gamma, _ptr(self.w), _ptr(self.y),
+                           _ptr(self.y_pair), _ptr(x), _ptr(f))
+        return x, f
+
+    def solve(self, tol=1e-6, b=8, max_sweeps=100000, check_every=1, order="schedule"):
+        """Sweep until the max constraint violation is at most tol."""
+        while self.sweeps < max_sweeps:
+            self.sweep(check_every, b=b, order=order)
+            r = self.residuals()
+            if max(r["max_viol_metric"], r["max_viol_pair"]) <= tol:
+                return r
+        return self.residuals()
+
+
+def schedule(n: int, b: int) -> np.ndarray:
+    """Visiting order as rows (i, j, k, round, P, J, t)."""
+    cnt = num_triplets(n)
+    out = np.zeros((max(cnt, 1), 7), dtype=np.int64)
+    got = lib().orc_schedule(n, b, _ptr(out), cnt)
+    assert got == cnt, (got, cnt)
+    return out[:cnt]
+
+
+def pair_pass(n, gamma, w, d, x, f, y_pair):
+    """One pass over the pair constraints, in place."""
+    rc = lib().orc_pair_pass(int(n), float(gamma), _ptr(_f64(w)),
+                             _ptr(np.ascontiguousarray(d, dtype=np.uint8)),
+                             _ptr(x), _ptr(f), _ptr(y_pair))
+    if rc != 0:
+        raise MemoryError
+
+
+def second_sweep_prefix(n, b, gamma, w, d, rounds, cap=None):
+    """Cold start, one pair pass, then the first `rounds` metric rounds.
+
+    This is the state after sweep 1 plus a prefix of sweep 2 (a cold-start
+    sweep changes no metric dual), without dense dual storage.  Returns
+    (x, f, y_pair, t, o, y) with the nonzero metric duals in visit order.
+    """
+    w = _f64(w)
+    npairs = num_pairs(n)
+    x0 = np.zeros(npairs)
+    f = np.full(npairs, -float(gamma))
+    y_pair = np.zeros(2 * npairs)
+    pair_pass(n, gamma, w, d, x0, f, y_pair)
+    if cap is None:
+        cap = 1 << 20
+    while True:
+        x = x0.copy()
+        t = np.zeros(cap, dtype=np.int64)
+        o = np.zeros(cap, dtype=np.int8)
+        y = np.zeros(cap)
+        cnt = lib().orc_round_prefix(n, b, float(gamma), _ptr(w), _ptr(x), int(rounds),
+                                     _ptr(t), _ptr(o), _ptr(y), cap)
+        if cnt < 0:
+            raise MemoryError
+        if cnt <= cap:
+            return x, f, y_pair, t[:cnt], o[:cnt], y[:cnt]
+        cap = int(cnt)
