@@ -1,0 +1,170 @@
+#!/usr/bin/env python3
+"""Benchmark: constraint projections per second of the projection sweep.
+
+One step = one full sweep (every metric round of the tiled schedule, then the
+pair pass) over a synthetic instance resident in HBM.  Default workload: the
+n = 500 planted-partition instance (10 blocks of 50, p_in = 0.3,
+p_out = 0.02, unit weights, gamma = 5, 62,125,500 metric rows), FP64.
+
+Prints one JSON line on stdout; progress goes to stderr.
+"""
+import argparse
+import json
+import os
+import platform
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0   # MI355X HBM3E
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return platform.processor()
+
+
+def metric_sweep_bytes(inst, elem):
+    """Algorithmic bytes of one metric sweep: every metric dual read and
+    written once, x read and written once, g read once."""
+    return 2 * inst.num_constraints * elem + inst.num_pairs * 3 * elem
+
+
+def cpu_baseline(inst, b, budget_s):
+    import oracle
+    s = oracle.State.from_instance(inst)
+    t0 = time.perf_counter()
+    s.sweep(1, b=b)
+    one = time.perf_counter() - t0
+    k = max(1, min(50, int(budget_s / max(one, 1e-6))))
+    t0 = time.perf_counter()
+    s.sweep(k, b=b)
+    dt = time.perf_counter() - t0
+    return {"value": inst.num_constraints * k / dt, "unit": "constraint-projections/s",
+            "cores": 1, "kind": "oracle",
+            "sample": f"{k} FP64 sweeps of the same instance (after 1 untimed), serial C oracle, "
+                      f"{dt:.1f} s, host {cpu_model()}, nproc {os.cpu_count()}"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--config", type=int, default=1, help="workload index 0..4")
+    ap.add_argument("--b", type=int, default=16, help="tile size")
+    ap.add_argument("--prec", default="f64", choices=["f64", "f32"])
+    ap.add_argument("--exec", default="rounds", choices=["rounds", "dataflow"])
+    ap.add_argument("--cpu-budget", type=float, default=12.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-solve", action="store_true")
+    args = ap.parse_args()
+
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py runs on one GPU only: the solver has no multi-GPU path "
+              "(see DESIGN.md for how it would shard); use --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_1901_10084_amd import ccproj as C
+    from paper_1901_10084_amd import instances as I
+
+    torch.cuda.set_device(0)
+    inst = I.workload(args.config)
+    elem = 8 if args.prec == "f64" else 4
+    executor = C.CC_EXEC_ROUNDS if args.exec == "rounds" else C.CC_EXEC_DATAFLOW
+    log(f"workload {inst.name}: n={inst.n} rows={inst.num_constraints} b={args.b} "
+        f"prec={args.prec} exec={args.exec}")
+
+    g = C.Solver.from_instance(inst, b=args.b, prec=args.prec)
+    stream = torch.cuda.current_stream()
+    for _ in range(args.warmup):
+        g.sweep(1, executor)
+    torch.cuda.synchronize()
+
+    ev_m0 = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps)]
+    ev_m1 = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps)]
+    t0 = time.perf_counter()
+    for s in range(args.steps):
+        if executor == C.CC_EXEC_ROUNDS:
+            ev_m0[s].record(stream)
+            g.sweep_rounds(0, g.ctx.rounds)
+            ev_m1[s].record(stream)
+            g.pair_pass()
+            g.sweeps += 1
+        else:
+            ev_m0[s].record(stream)
+            g.sweep(1, executor)
+            ev_m1[s].record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    metric_ms = sum(a.elapsed_time(b) for a, b in zip(ev_m0, ev_m1))
+    launches_per_sweep = g.ctx.rounds if executor == C.CC_EXEC_ROUNDS else 1
+    n_launch = launches_per_sweep * args.steps
+    avg_launch_s = metric_ms / 1e3 / n_launch
+    bytes_sweep = metric_sweep_bytes(inst, elem)
+    achieved = bytes_sweep * args.steps / (metric_ms / 1e3) / 1e9
+    r = g.residuals()
+    log(f"timed {args.steps} sweeps: {wall*1e3/args.steps:.3f} ms/sweep, metric kernels "
+        f"{metric_ms/args.steps:.3f} ms/sweep, {achieved:.1f} GB/s, viol {r['max_viol_metric']:.2e}")
+
+    value = inst.num_constraints * args.steps / wall
+    out = {
+        "metric": "triplet-projections/s + time-to-1e-4 max violation, FP64 plain vs FP32+MLP warm start",
+        "value": value,
+        "unit": "triplet-projections/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": wall * 1e3 / args.steps,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": args.prec, "data": "synthetic",
+        "config": {"workload": inst.name, "n": inst.n, "model": inst.meta.get("model"),
+                   "gamma": inst.gamma, "metric_rows": inst.num_constraints, "b": args.b,
+                   "executor": args.exec, "step": "one full sweep (metric rounds + pair pass)"},
+        "triplets_per_s": value / 3,
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "kernel": "k_sweep_round" if executor == C.CC_EXEC_ROUNDS else "k_sweep_dataflow",
+                     "avg_launch_us": avg_launch_s * 1e6,
+                     "algorithmic_bytes_per_launch": bytes_sweep / launches_per_sweep,
+                     "launches_per_step": launches_per_sweep},
+    }
+
+    if not args.no_solve:
+        g2 = C.Solver.from_instance(inst, b=args.b, prec=args.prec)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        tt = {}
+        for tol in (1e-4, 1e-6):
+            rr, conv, _ = g2.solve(tol=tol, max_sweeps=20000, executor=executor)
+            tt[f"{tol:g}"] = {"seconds": time.perf_counter() - t0, "sweeps": g2.sweeps,
+                              "converged": conv, "max_viol": max(rr["max_viol_metric"],
+                                                                 rr["max_viol_pair"]),
+                              "lp_cost": rr["lp_cost"], "primal_qp": rr["primal_qp"],
+                              "gap": rr["gap"]}
+            log(f"tol {tol:g}: {tt[f'{tol:g}']}")
+        out["time_to_tol"] = tt
+
+    if not args.no_cpu_baseline:
+        log("timing the oracle ...")
+        out["cpu_baseline"] = cpu_baseline(inst, args.b, args.cpu_budget)
+        log(f"oracle: {out['cpu_baseline']}")
+
+    out["gpu"] = torch.cuda.get_device_name(0)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,195 @@
+/*
+ * ccproj.h -- C ABI of the MI355X (gfx950) solver for the regularised
+ * metric-constrained LP relaxation of correlation clustering.
+ *
+ * Problem (paper, Sec. II-A, problem (mn1)): for a signed weighted complete
+ * graph on n nodes with a label d_p in {0,1} (1 = negative pair) and a weight
+ * w_p > 0 per pair p = (i,j), i < j,
+ *     min sum_p w_p f_p   s.t.  x_ij <= x_ik + x_jk  (every triplet, every
+ *                               orientation),  |x_p - d_p| <= f_p.
+ * Regularisation (Sec. II-B, problem (qp)): min c'v + (eps/2) v'Wv over
+ * v = (x, f), c = (0, w), W = diag(w) on x and on f, gamma = 1/eps.
+ * Method (Sec. II-B, Algorithm 1): Dykstra's = Hildreth's cyclic projection
+ * with one dual per constraint, run on the conflict-free tiled schedule of
+ * Sec. III (rounds = block anti-diagonals of the (i,k) grid; the tiles of a
+ * round run concurrently without locks).
+ *
+ * Conventions for every entry point
+ *   - Return value: CC_OK (0) on success, CC_ENOTCONV (1) when a solve hit
+ *     its sweep limit, a negative CC_E* code on error.  After an error,
+ *     cc_last_error() returns a message (thread-local; valid until the next
+ *     call on the same thread).  Nothing aborts or throws across the ABI.
+ *   - Device pointers are raw device addresses owned by the caller; the
+ *     library never frees, resizes or copies them to the host (except where
+ *     a function says it reads a result back).  Host pointers are marked
+ *     "host".
+ *   - Element type of the state arrays x, f, g, y, y_pair is the context's
+ *     precision: double for CC_F64, float for CC_F32.  w is always double.
+ *   - Layouts.  Pairs: packed upper-triangular column-major order,
+ *     p(i,j) = j(j-1)/2 + i for 0-based i < j, N_p = n(n-1)/2 entries.
+ *     Pair duals: y_pair[2p + c], c = 0 for x - f <= d, c = 1 for
+ *     -x - f <= -d.  Metric duals: schedule order (see cc_dual_slots); use
+ *     cc_duals_to_lex for the colex order y_lex[3t + o],
+ *     t = C(k,3) + C(j,2) + i, o = 0: x_ij <= x_ik + x_jk,
+ *     o = 1: x_ik <= x_ij + x_jk, o = 2: x_jk <= x_ij + x_ik.
+ *   - All work of a context is enqueued on the stream given at creation;
+ *     functions that return numbers to the host synchronise that stream.
+ *     A context is not thread-safe; distinct contexts are independent.
+ *   - Indices are 64-bit throughout (3 C(n,3) exceeds 2^31 for n > 1000).
+ */
+#ifndef CCPROJ_H
+#define CCPROJ_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+    CC_OK = 0,
+    CC_ENOTCONV = 1,      /* sweep limit reached before the tolerance      */
+    CC_EINVAL = -1,       /* bad argument (sizes, weights, gamma, b, ...)  */
+    CC_ENOMEM = -2,       /* device or host allocation failed              */
+    CC_EHIP = -3,         /* a HIP runtime call or kernel launch failed    */
+    CC_ENONFINITE = -4    /* NaN or Inf found in the state                 */
+};
+
+enum { CC_F64 = 0, CC_F32 = 1 };                         /* context precision */
+enum { CC_MODE_F64 = 0, CC_MODE_F32 = 1, CC_MODE_F32_POLISH = 2 };
+enum { CC_WARM_NONE = 0, CC_WARM_MLP = 1 };
+enum { CC_EXEC_ROUNDS = 0, CC_EXEC_DATAFLOW = 1 };       /* sweep executors   */
+
+typedef struct cc_ctx cc_ctx;
+
+/* Convergence measures, all evaluated in FP64 (Sec. IV-D: constraint
+ * satisfaction and duality gap).  Fields a solve cannot fill are NaN. */
+typedef struct {
+    double max_viol_metric;  /* max over metric rows of (x_L - x_S1 - x_S2)^+ */
+    double max_viol_pair;    /* max over pairs of (|x - d| - f)^+             */
+    double primal_qp;        /* sum w f + (1/(2 gamma)) sum w (x^2 + f^2)     */
+    double dual_qp;          /* -b'y - (gamma/2) (c+A'y)' W^{-1} (c+A'y)      */
+    double gap;              /* primal_qp - dual_qp                           */
+    double lp_cost;          /* sum w |x - d|: the LP objective at x          */
+    double cs_max;           /* max over rows of |y (b - a'v)|                */
+    double stat_resid;       /* max |v - v(y)|, v(y) = -gamma W^{-1}(c + A'y) */
+} cc_resid;
+
+typedef struct {
+    int32_t sweeps;          /* sweeps run (all phases)                       */
+    int32_t sweeps_f32;      /* of which in FP32                              */
+    double wall_s;           /* wall time of the whole call                   */
+    cc_resid resid;          /* final residuals                               */
+} cc_info;
+
+/* Residual selection for cc_residuals. */
+enum {
+    CC_RESID_VIOL = 1,       /* max violations, primal, LP cost (reads x, f)  */
+    CC_RESID_CS = 2,         /* + complementary slackness (reads y)           */
+    CC_RESID_DUAL = 4,       /* + dual objective, gap, stationarity (A'y pass)*/
+    CC_RESID_ALL = 7
+};
+
+/* Message for the last error on this thread ("" if none). */
+const char *cc_last_error(void);
+
+/* 3 C(n,3): number of metric constraints (rows x_ij <= x_ik + x_jk). */
+int64_t cc_num_metric_duals(int64_t n);
+
+/* Create a context for n nodes, tile size b (1..32; the schedule's b of
+ * Sec. III-C), precision CC_F64 or CC_F32, and HIP stream `stream`
+ * (hipStream_t; NULL = the null stream).  Builds the schedule tables on the
+ * device; owns only those tables and small scratch buffers.
+ * Errors: CC_EINVAL (n < 3, b outside 1..32, bad prec), CC_ENOMEM, CC_EHIP. */
+int cc_create(cc_ctx **out, int64_t n, int32_t b, int32_t prec, void *stream);
+
+/* Release a context and its device tables.  NULL is accepted. */
+int cc_destroy(cc_ctx *ctx);
+
+/* Length (elements) of the schedule-ordered metric dual array y.  Each tile
+ * (P,Q) of the schedule owns a contiguous segment, laid out as
+ * [middle block J][sub-step t][orientation o][lane il*b + kl], so every
+ * sub-step reads and writes 3 contiguous vectors of b*b elements.  Slots of
+ * index combinations that are not triplets i<j<k<n are padding: they are
+ * zero after cc_init_cold and never read or written by a sweep.  The count
+ * is 3 b^3 nb(nb+1)(nb+2)/6 with nb = ceil(n/b), at least 3 C(n,3). */
+int64_t cc_dual_slots(const cc_ctx *ctx);
+
+/* Number of rounds of the schedule, 2 ceil(n/b) - 1. */
+int32_t cc_num_rounds(const cc_ctx *ctx);
+
+/* g_p = gamma / w_p (= gamma W^{-1} on pair p), written in the context's
+ * precision.  w: device double[N_p]; g: device [N_p].  Validates that every
+ * w_p is finite and > 0 and gamma > 0 (CC_EINVAL otherwise; synchronises). */
+int cc_prepare(cc_ctx *ctx, const double *w, double gamma, void *g);
+
+/* Starting point of Algorithm 1: y = 0 (every slot), y_pair = 0 and
+ * v = -(1/eps) W^{-1} c, i.e. x = 0, f = -gamma.  x, f: device [N_p];
+ * y: device [cc_dual_slots]; y_pair: device [2 N_p]. */
+int cc_init_cold(cc_ctx *ctx, void *x, void *f, void *y, void *y_pair, double gamma);
+
+/* nsweeps full sweeps (Sec. IV-D: one pass over every constraint): all
+ * metric rounds in schedule order, then the pair pass.  g from cc_prepare;
+ * d: device uint8[N_p].  exec selects the executor (CC_EXEC_ROUNDS: one
+ * launch per round; CC_EXEC_DATAFLOW: one persistent launch per sweep whose
+ * tiles wait only for the tiles they depend on).  Both executors apply every
+ * update to every variable in the same order and give identical results. */
+int cc_sweep(cc_ctx *ctx, void *x, void *f, void *y, void *y_pair, const void *g,
+             const uint8_t *d, int32_t nsweeps, int32_t exec);
+
+/* Metric rounds [first_round, first_round + nrounds) of one sweep, without
+ * the pair pass (for checks against a prefix of the serial order). */
+int cc_sweep_rounds(cc_ctx *ctx, void *x, void *y, const void *g, int32_t first_round,
+                    int32_t nrounds);
+
+/* The pair pass alone. */
+int cc_pair_pass(cc_ctx *ctx, void *x, void *f, void *y_pair, const void *g,
+                 const uint8_t *d);
+
+/* Residuals selected by `what` (CC_RESID_*), evaluated in FP64 and copied to
+ * *out (host).  y may be NULL when CC_RESID_CS/DUAL are not requested.
+ * w: device double[N_p].  Returns CC_ENONFINITE (with *out filled) if x or f
+ * holds a NaN or Inf.  Synchronises. */
+int cc_residuals(cc_ctx *ctx, const void *x, const void *f, const void *y,
+                 const void *y_pair, const double *w, const uint8_t *d, double gamma,
+                 int32_t what, cc_resid *out);
+
+/* x = -gamma W^{-1} (c + A'y) from the duals (the stationarity condition of
+ * (qp)): accumulates A'y in FP64 in schedule order (deterministic, no
+ * atomics), writes x_out, f_out in the context's precision. */
+int cc_x_from_y(cc_ctx *ctx, const void *y, const void *y_pair, const double *w,
+                double gamma, void *x_out, void *f_out);
+
+/* Copy metric duals from schedule order to colex order (device y_lex of
+ * length 3 C(n,3), same precision). */
+int cc_duals_to_lex(cc_ctx *ctx, const void *y_sched, void *y_lex);
+
+/* Colex index 3t + o of each schedule slot in slots[0..count) (device int64
+ * arrays; -1 for padding slots). */
+int cc_slots_to_lex(cc_ctx *ctx, const int64_t *slots, int64_t count, int64_t *lex_out);
+
+/* Element-wise precision change (device arrays, count elements):
+ * float -> double (widen) or double -> float (narrow). */
+int cc_widen(const float *src, double *dst, int64_t count, void *stream);
+int cc_narrow(const double *src, float *dst, int64_t count, void *stream);
+
+/* One-shot solve from host arrays (allocates its own device buffers).
+ * w_host: double[N_p] > 0; d_host: uint8[N_p]; tol: stop when both max
+ * violations are <= tol; mode: CC_MODE_F64, CC_MODE_F32 (FP32 sweeps to tol)
+ * or CC_MODE_F32_POLISH (FP32 sweeps to max(tol, 1e-4), then duals widened,
+ * x recomputed from them in FP64 and FP64 sweeps to tol); warm: CC_WARM_NONE
+ * or CC_WARM_MLP (then mlp_weights_host must point to cc_mlp_num_params()
+ * floats; the predicted duals are kept only if they raise the dual
+ * objective, else the solve starts cold).  x_out_host: double[N_p] or NULL;
+ * y_lex_out_host: double[3 C(n,3)] or NULL.  Returns CC_OK, CC_ENOTCONV
+ * (info filled, outputs written), or an error. */
+int cc_solve_cc_lp(int64_t n, const double *w_host, const uint8_t *d_host, double gamma,
+                   double tol, int32_t max_sweeps, int32_t b, int32_t mode, int32_t warm,
+                   const float *mlp_weights_host, const float *deg_host,
+                   double *x_out_host, double *y_lex_out_host, cc_info *info);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* CCPROJ_H */

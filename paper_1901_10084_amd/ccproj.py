@@ -1,0 +1,263 @@
+"""ctypes binding of ``libccproj.so`` (the C ABI in ``include/ccproj.h``).
+
+Argument marshalling only: every step of the solver runs in the library's
+HIP kernels.  PyTorch provides device memory and the stream.  If the
+library is missing this module raises at import time; there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import time
+
+import numpy as np
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libccproj.so")
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"{LIB_PATH} is missing: build it with paper_1901_10084_amd/build.py")
+
+_L = ctypes.CDLL(LIB_PATH)
+
+CC_OK, CC_ENOTCONV = 0, 1
+CC_EINVAL, CC_ENOMEM, CC_EHIP, CC_ENONFINITE = -1, -2, -3, -4
+CC_F64, CC_F32 = 0, 1
+CC_MODE_F64, CC_MODE_F32, CC_MODE_F32_POLISH = 0, 1, 2
+CC_WARM_NONE, CC_WARM_MLP = 0, 1
+CC_EXEC_ROUNDS, CC_EXEC_DATAFLOW = 0, 1
+CC_RESID_VIOL, CC_RESID_CS, CC_RESID_DUAL, CC_RESID_ALL = 1, 2, 4, 7
+
+_p = ctypes.c_void_p
+_i32 = ctypes.c_int32
+_i64 = ctypes.c_int64
+_dbl = ctypes.c_double
+
+
+class Resid(ctypes.Structure):
+    _fields_ = [(k, _dbl) for k in ("max_viol_metric", "max_viol_pair", "primal_qp",
+                                     "dual_qp", "gap", "lp_cost", "cs_max", "stat_resid")]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class Info(ctypes.Structure):
+    _fields_ = [("sweeps", _i32), ("sweeps_f32", _i32), ("wall_s", _dbl), ("resid", Resid)]
+
+
+def _sig(name, res, *args):
+    fn = getattr(_L, name)
+    fn.restype = res
+    fn.argtypes = list(args)
+    return fn
+
+
+_sig("cc_last_error", ctypes.c_char_p)
+_sig("cc_num_metric_duals", _i64, _i64)
+_sig("cc_create", ctypes.c_int, ctypes.POINTER(_p), _i64, _i32, _i32, _p)
+_sig("cc_destroy", ctypes.c_int, _p)
+_sig("cc_dual_slots", _i64, _p)
+_sig("cc_num_rounds", _i32, _p)
+_sig("cc_prepare", ctypes.c_int, _p, _p, _dbl, _p)
+_sig("cc_init_cold", ctypes.c_int, _p, _p, _p, _p, _p, _dbl)
+_sig("cc_sweep", ctypes.c_int, _p, _p, _p, _p, _p, _p, _p, _i32, _i32)
+_sig("cc_sweep_rounds", ctypes.c_int, _p, _p, _p, _p, _i32, _i32)
+_sig("cc_pair_pass", ctypes.c_int, _p, _p, _p, _p, _p, _p)
+_sig("cc_residuals", ctypes.c_int, _p, _p, _p, _p, _p, _p, _p, _dbl, _i32,
+     ctypes.POINTER(Resid))
+_sig("cc_x_from_y", ctypes.c_int, _p, _p, _p, _p, _dbl, _p, _p)
+_sig("cc_duals_to_lex", ctypes.c_int, _p, _p, _p)
+_sig("cc_slots_to_lex", ctypes.c_int, _p, _p, _i64, _p)
+_sig("cc_widen", ctypes.c_int, _p, _p, _i64, _p)
+_sig("cc_narrow", ctypes.c_int, _p, _p, _i64, _p)
+
+EXPORTS = ["cc_last_error", "cc_num_metric_duals", "cc_create", "cc_destroy", "cc_dual_slots",
+           "cc_num_rounds", "cc_prepare", "cc_init_cold", "cc_sweep", "cc_sweep_rounds",
+           "cc_pair_pass", "cc_residuals", "cc_x_from_y", "cc_duals_to_lex", "cc_slots_to_lex",
+           "cc_widen", "cc_narrow"]
+
+
+class CCError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"ccproj error {code}: {msg}")
+        self.code = code
+
+
+def last_error() -> str:
+    m = _L.cc_last_error()
+    return m.decode() if m else ""
+
+
+def check(rc: int, allow_notconv: bool = False) -> int:
+    if rc < 0 or (rc == CC_ENOTCONV and not allow_notconv):
+        raise CCError(rc, last_error())
+    return rc
+
+
+def num_metric_duals(n: int) -> int:
+    return int(_L.cc_num_metric_duals(n))
+
+
+def _ptr(t):
+    if t is None:
+        return None
+    if isinstance(t, torch.Tensor):
+        if not t.is_contiguous():
+            raise ValueError("tensor must be contiguous")
+        return t.data_ptr()
+    return int(t)
+
+
+def _stream_handle(stream):
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return stream.cuda_stream
+
+
+class Context:
+    """A schedule context: n nodes, tile size b, precision, stream."""
+
+    def __init__(self, n: int, b: int, prec: str = "f64", stream=None):
+        self.n, self.b = int(n), int(b)
+        self.prec = prec
+        self.dtype = {"f64": torch.float64, "f32": torch.float32}[prec]
+        self.stream = stream if stream is not None else torch.cuda.current_stream()
+        h = _p()
+        check(_L.cc_create(ctypes.byref(h), self.n, self.b,
+                           CC_F64 if prec == "f64" else CC_F32, _stream_handle(self.stream)))
+        self._h = h
+        self.slots = int(_L.cc_dual_slots(h))
+        self.rounds = int(_L.cc_num_rounds(h))
+
+    @property
+    def handle(self):
+        return self._h
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _L.cc_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def prepare(self, w, gamma, g):
+        check(_L.cc_prepare(self._h, _ptr(w), float(gamma), _ptr(g)))
+
+    def init_cold(self, x, f, y, y_pair, gamma):
+        check(_L.cc_init_cold(self._h, _ptr(x), _ptr(f), _ptr(y), _ptr(y_pair), float(gamma)))
+
+    def sweep(self, x, f, y, y_pair, g, d, nsweeps=1, executor=CC_EXEC_ROUNDS):
+        check(_L.cc_sweep(self._h, _ptr(x), _ptr(f), _ptr(y), _ptr(y_pair), _ptr(g), _ptr(d),
+                          int(nsweeps), int(executor)))
+
+    def sweep_rounds(self, x, y, g, first, count):
+        check(_L.cc_sweep_rounds(self._h, _ptr(x), _ptr(y), _ptr(g), int(first), int(count)))
+
+    def pair_pass(self, x, f, y_pair, g, d):
+        check(_L.cc_pair_pass(self._h, _ptr(x), _ptr(f), _ptr(y_pair), _ptr(g), _ptr(d)))
+
+    def residuals(self, x, f, y, y_pair, w, d, gamma, what=CC_RESID_ALL, raise_nonfinite=True):
+        out = Resid()
+        rc = _L.cc_residuals(self._h, _ptr(x), _ptr(f), _ptr(y), _ptr(y_pair), _ptr(w), _ptr(d),
+                             float(gamma), int(what), ctypes.byref(out))
+        if rc == CC_ENONFINITE and not raise_nonfinite:
+            r = out.as_dict()
+            r["nonfinite"] = True
+            return r
+        check(rc)
+        return out.as_dict()
+
+    def x_from_y(self, y, y_pair, w, gamma, x_out, f_out):
+        check(_L.cc_x_from_y(self._h, _ptr(y), _ptr(y_pair), _ptr(w), float(gamma),
+                             _ptr(x_out), _ptr(f_out)))
+
+    def duals_to_lex(self, y, y_lex):
+        check(_L.cc_duals_to_lex(self._h, _ptr(y), _ptr(y_lex)))
+
+    def slots_to_lex(self, slots, out):
+        check(_L.cc_slots_to_lex(self._h, _ptr(slots), int(slots.numel()), _ptr(out)))
+
+
+def widen(src, dst, stream=None):
+    check(_L.cc_widen(_ptr(src), _ptr(dst), int(src.numel()), _stream_handle(stream)))
+
+
+def narrow(src, dst, stream=None):
+    check(_L.cc_narrow(_ptr(src), _ptr(dst), int(src.numel()), _stream_handle(stream)))
+
+
+class Solver:
+    """Device state of one instance: w, d, g, x, f, y (schedule order), y_pair."""
+
+    def __init__(self, n, w, d, gamma, b=16, prec="f64", device="cuda", stream=None,
+                 cold=True):
+        if not torch.cuda.is_available():
+            raise RuntimeError("ccproj needs a ROCm GPU; none is visible")
+        self.n, self.gamma, self.b, self.prec = int(n), float(gamma), int(b), prec
+        self.ctx = Context(n, b, prec, stream)
+        dt = self.ctx.dtype
+        npairs = self.n * (self.n - 1) // 2
+        self.npairs = npairs
+        self.w = torch.as_tensor(np.ascontiguousarray(w, dtype=np.float64)).to(device)
+        self.d = torch.as_tensor(np.ascontiguousarray(d, dtype=np.uint8)).to(device)
+        self.g = torch.empty(npairs, dtype=dt, device=device)
+        self.x = torch.empty(npairs, dtype=dt, device=device)
+        self.f = torch.empty(npairs, dtype=dt, device=device)
+        self.y = torch.empty(self.ctx.slots, dtype=dt, device=device)
+        self.y_pair = torch.empty(2 * npairs, dtype=dt, device=device)
+        self.ctx.prepare(self.w, self.gamma, self.g)
+        self.sweeps = 0
+        if cold:
+            self.init_cold()
+
+    @classmethod
+    def from_instance(cls, inst, **kw):
+        return cls(inst.n, inst.w, inst.d, inst.gamma, **kw)
+
+    def init_cold(self):
+        self.ctx.init_cold(self.x, self.f, self.y, self.y_pair, self.gamma)
+        self.sweeps = 0
+
+    def sweep(self, nsweeps=1, executor=CC_EXEC_ROUNDS):
+        self.ctx.sweep(self.x, self.f, self.y, self.y_pair, self.g, self.d, nsweeps, executor)
+        self.sweeps += nsweeps
+
+    def sweep_rounds(self, first, count):
+        self.ctx.sweep_rounds(self.x, self.y, self.g, first, count)
+
+    def pair_pass(self):
+        self.ctx.pair_pass(self.x, self.f, self.y_pair, self.g, self.d)
+
+    def residuals(self, what=CC_RESID_ALL, raise_nonfinite=True):
+        return self.ctx.residuals(self.x, self.f, self.y, self.y_pair, self.w, self.d,
+                                  self.gamma, what, raise_nonfinite)
+
+    def x_from_y(self):
+        x = torch.empty_like(self.x)
+        f = torch.empty_like(self.f)
+        self.ctx.x_from_y(self.y, self.y_pair, self.w, self.gamma, x, f)
+        return x, f
+
+    def duals_lex(self):
+        y_lex = torch.empty(num_metric_duals(self.n), dtype=self.y.dtype, device=self.y.device)
+        self.ctx.duals_to_lex(self.y, y_lex)
+        return y_lex
+
+    def solve(self, tol=1e-6, max_sweeps=100000, check_every=1, executor=CC_EXEC_ROUNDS):
+        """Sweep until both max violations are <= tol (checked every
+        `check_every` sweeps).  Returns (residuals, converged, seconds)."""
+        t0 = time.perf_counter()
+        r = None
+        while self.sweeps < max_sweeps:
+            k = min(check_every, max_sweeps - self.sweeps)
+            self.sweep(k, executor)
+            r = self.residuals(CC_RESID_VIOL)
+            if max(r["max_viol_metric"], r["max_viol_pair"]) <= tol:
+                return self.residuals(), True, time.perf_counter() - t0
+        return self.residuals(), False, time.perf_counter() - t0

@@ -1,0 +1,551 @@
+// capi.hip -- the C ABI: contexts, schedule tables, argument checks, solves.
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "common.hpp"
+
+namespace ccp {
+
+// ----- error reporting -----------------------------------------------------
+static thread_local std::string g_last_error;
+
+void set_error(const std::string &msg) { g_last_error = msg; }
+int fail(int code, const std::string &msg) {
+    g_last_error = msg;
+    return code;
+}
+
+// ----- kernels (sweep.hip, resid.hip) --------------------------------------
+template <typename T> int launch_sweep_round(const Tile *, int, int, int64_t, T *, const T *, T *, hipStream_t);
+template <typename T> int set_sweep_lds_limits(int);
+template <typename T> int launch_pair_pass(int64_t, T *, T *, T *, const T *, const uint8_t *, hipStream_t);
+template <typename T> int launch_prepare(int64_t, const double *, double, T *, int *, hipStream_t);
+template <typename T> int launch_init_cold(int64_t, int64_t, T *, T *, T *, T *, double, hipStream_t);
+template <typename S, typename D> int launch_convert(int64_t, const S *, D *, hipStream_t);
+template <typename T> int launch_metric_resid(const Tile *, int64_t, int, int64_t, const T *, const T *, double *, hipStream_t);
+template <typename T> int launch_pair_resid(int64_t, const T *, const T *, const T *, const double *, const uint8_t *, const double *, double, double *, hipStream_t);
+int launch_final_reduce(const double *, int64_t, const double *, double *, hipStream_t);
+int pair_partial_blocks();
+template <typename T> int launch_aty_round(const Tile *, int, int, int64_t, const T *, double *, hipStream_t);
+template <typename T> int launch_x_from_aty(int64_t, const double *, const T *, const double *, double, T *, T *, hipStream_t);
+template <typename T> int launch_to_lex(const Tile *, int64_t, int, int64_t, const T *, T *, hipStream_t);
+int launch_slots_to_lex(const Tile *, int64_t, int, int64_t, const int64_t *, int64_t, int64_t *, hipStream_t);
+
+}  // namespace ccp
+
+using namespace ccp;
+
+struct cc_ctx {
+    int64_t n = 0;
+    int b = 0;
+    int prec = CC_F64;
+    hipStream_t stream = nullptr;
+    int nb = 0;
+    int nrounds = 0;
+    int64_t ntiles = 0;
+    int64_t slots = 0;
+    std::vector<int64_t> round_start;  // tiles of round r: [round_start[r], round_start[r+1])
+    Tile *d_tiles = nullptr;
+    double *d_mpart = nullptr;  // metric residual partials, 4 per tile
+    double *d_ppart = nullptr;  // pair residual partials
+    double *d_out = nullptr;    // final reduction, 14 doubles
+    int *d_flag = nullptr;
+    double *d_ax = nullptr;     // A'y accumulator, N_p doubles (allocated on first use)
+};
+
+namespace {
+
+int64_t num_pairs(int64_t n) { return n * (n - 1) / 2; }
+size_t elem_size(const cc_ctx *c) { return c->prec == CC_F64 ? sizeof(double) : sizeof(float); }
+
+int check_ctx(const cc_ctx *c) {
+    if (!c) return fail(CC_EINVAL, "null context");
+    return CC_OK;
+}
+
+int need(const void *p, const char *name) {
+    if (!p) return fail(CC_EINVAL, std::string("null pointer: ") + name);
+    return CC_OK;
+}
+
+// Build the tiled schedule (Sec. III-C): tiles in round order, rounds the
+// block anti-diagonals s = nb-1 .. 0 followed by s = nb .. 2nb-2, tiles of
+// a round by ascending P.  Each tile's dual segment holds
+// (Q-P+1) * b sub-steps * 3 orientations * b*b lanes.
+void build_schedule(cc_ctx *c, std::vector<Tile> &tiles) {
+    const int nb = c->nb;
+    const int64_t bb = int64_t(c->b) * c->b;
+    int64_t ybase = 0;
+    c->round_start.clear();
+    for (int r = 0; r < c->nrounds; ++r) {
+        c->round_start.push_back(int64_t(tiles.size()));
+        const int s = (r < nb) ? (nb - 1 - r) : r;
+        for (int P = 0; 2 * P <= s; ++P) {
+            const int Q = s - P;
+            if (Q >= nb) continue;
+            tiles.push_back(Tile{P, Q, ybase});
+            ybase += int64_t(Q - P + 1) * c->b * 3 * bb;
+        }
+    }
+    c->round_start.push_back(int64_t(tiles.size()));
+    c->ntiles = int64_t(tiles.size());
+    c->slots = ybase;
+}
+
+template <typename T>
+int sweep_rounds_t(cc_ctx *c, T *x, T *y, const T *g, int first, int count) {
+    for (int r = first; r < first + count; ++r) {
+        const int64_t a = c->round_start[r], e = c->round_start[r + 1];
+        int rc = launch_sweep_round<T>(c->d_tiles + a, int(e - a), c->b, c->n, x, g, y, c->stream);
+        if (rc) return rc;
+    }
+    return CC_OK;
+}
+
+template <typename T>
+int sweep_t(cc_ctx *c, T *x, T *f, T *y, T *yp, const T *g, const uint8_t *d, int nsweeps) {
+    for (int s = 0; s < nsweeps; ++s) {
+        int rc = sweep_rounds_t<T>(c, x, y, g, 0, c->nrounds);
+        if (rc) return rc;
+        rc = launch_pair_pass<T>(num_pairs(c->n), x, f, yp, g, d, c->stream);
+        if (rc) return rc;
+    }
+    return CC_OK;
+}
+
+int ensure_ax(cc_ctx *c) {
+    if (!c->d_ax) {
+        if (hipMalloc(&c->d_ax, size_t(num_pairs(c->n)) * sizeof(double)) != hipSuccess) {
+            c->d_ax = nullptr;
+            return fail(CC_ENOMEM, "hipMalloc of the A'y accumulator failed");
+        }
+    }
+    return CC_OK;
+}
+
+template <typename T>
+int aty_t(cc_ctx *c, const T *y) {
+    int rc = ensure_ax(c);
+    if (rc) return rc;
+    CCP_HIP_CHECK(hipMemsetAsync(c->d_ax, 0, size_t(num_pairs(c->n)) * sizeof(double), c->stream));
+    for (int r = 0; r < c->nrounds; ++r) {
+        const int64_t a = c->round_start[r], e = c->round_start[r + 1];
+        rc = launch_aty_round<T>(c->d_tiles + a, int(e - a), c->b, c->n, y, c->d_ax, c->stream);
+        if (rc) return rc;
+    }
+    return CC_OK;
+}
+
+template <typename T>
+int residuals_t(cc_ctx *c, const T *x, const T *f, const T *y, const T *yp, const double *w,
+                const uint8_t *d, double gamma, int what, cc_resid *out) {
+    const bool want_cs = (what & CC_RESID_CS) && y;
+    const bool want_dual = (what & CC_RESID_DUAL) && y && yp;
+    int rc;
+    if (want_dual) {
+        rc = aty_t<T>(c, y);
+        if (rc) return rc;
+    }
+    rc = launch_metric_resid<T>(c->d_tiles, c->ntiles, c->b, c->n, x, want_cs ? y : nullptr,
+                                c->d_mpart, c->stream);
+    if (rc) return rc;
+    rc = launch_pair_resid<T>(num_pairs(c->n), x, f, (want_cs || want_dual) ? yp : nullptr, w, d,
+                              want_dual ? c->d_ax : nullptr, gamma, c->d_ppart, c->stream);
+    if (rc) return rc;
+    rc = launch_final_reduce(c->d_mpart, c->ntiles, c->d_ppart, c->d_out, c->stream);
+    if (rc) return rc;
+    double h[14];
+    CCP_HIP_CHECK(hipMemcpyAsync(h, c->d_out, sizeof(h), hipMemcpyDeviceToHost, c->stream));
+    CCP_HIP_CHECK(hipStreamSynchronize(c->stream));
+    const double nan = std::nan("");
+    // h: 0 metric max viol, 1 metric cs sum, 2 metric cs max, 3 metric bad,
+    //    4 pair max viol, 5 sum w f, 6 sum w (x^2+f^2), 7 lp, 8 pair cs max,
+    //    9 pair cs sum, 10 quad dual, 11 b'y, 12 stat, 13 pair bad
+    out->max_viol_metric = h[0];
+    out->max_viol_pair = h[4];
+    out->primal_qp = h[5] + h[6] / (2.0 * gamma);
+    out->lp_cost = h[7];
+    out->cs_max = want_cs ? std::fmax(h[2], h[8]) : nan;
+    if (want_dual) {
+        out->dual_qp = -h[11] - 0.5 * gamma * h[10];
+        out->gap = out->primal_qp - out->dual_qp;
+        out->stat_resid = h[12];
+    } else {
+        out->dual_qp = out->gap = out->stat_resid = nan;
+    }
+    if (h[3] != 0.0 || h[13] != 0.0 || !std::isfinite(out->primal_qp))
+        return fail(CC_ENONFINITE, "non-finite value in x or f");
+    return CC_OK;
+}
+
+template <typename T>
+int x_from_y_t(cc_ctx *c, const T *y, const T *yp, const double *w, double gamma, T *x, T *f) {
+    int rc = aty_t<T>(c, y);
+    if (rc) return rc;
+    return launch_x_from_aty<T>(num_pairs(c->n), c->d_ax, yp, w, gamma, x, f, c->stream);
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *cc_last_error(void) { return g_last_error.c_str(); }
+
+int64_t cc_num_metric_duals(int64_t n) {
+    if (n < 3) return 0;
+    return 3 * (n * (n - 1) * (n - 2) / 6);
+}
+
+int cc_create(cc_ctx **out, int64_t n, int32_t b, int32_t prec, void *stream) {
+    if (!out) return fail(CC_EINVAL, "null output pointer");
+    *out = nullptr;
+    if (n < 3) return fail(CC_EINVAL, "n must be at least 3");
+    if (n > (int64_t(1) << 20)) return fail(CC_EINVAL, "n too large");
+    if (b < 1 || b > 32) return fail(CC_EINVAL, "tile size b must be in 1..32");
+    if (prec != CC_F64 && prec != CC_F32) return fail(CC_EINVAL, "prec must be CC_F64 or CC_F32");
+    cc_ctx *c = new (std::nothrow) cc_ctx();
+    if (!c) return fail(CC_ENOMEM, "context allocation failed");
+    c->n = n;
+    c->b = b;
+    c->prec = prec;
+    c->stream = static_cast<hipStream_t>(stream);
+    c->nb = int((n + b - 1) / b);
+    c->nrounds = 2 * c->nb - 1;
+    std::vector<Tile> tiles;
+    build_schedule(c, tiles);
+    int rc = CC_OK;
+    if (hipMalloc(&c->d_tiles, tiles.size() * sizeof(Tile)) != hipSuccess ||
+        hipMalloc(&c->d_mpart, size_t(c->ntiles) * 4 * sizeof(double)) != hipSuccess ||
+        hipMalloc(&c->d_ppart, size_t(pair_partial_blocks()) * 10 * sizeof(double)) != hipSuccess ||
+        hipMalloc(&c->d_out, 16 * sizeof(double)) != hipSuccess ||
+        hipMalloc(&c->d_flag, sizeof(int)) != hipSuccess) {
+        cc_destroy(c);
+        return fail(CC_ENOMEM, "hipMalloc of schedule tables failed");
+    }
+    if (hipMemcpy(c->d_tiles, tiles.data(), tiles.size() * sizeof(Tile), hipMemcpyHostToDevice) !=
+        hipSuccess) {
+        cc_destroy(c);
+        return fail(CC_EHIP, "copy of schedule tables failed");
+    }
+    rc = (prec == CC_F64) ? set_sweep_lds_limits<double>(b) : set_sweep_lds_limits<float>(b);
+    if (rc) {
+        cc_destroy(c);
+        return rc;
+    }
+    *out = c;
+    return CC_OK;
+}
+
+int cc_destroy(cc_ctx *c) {
+    if (!c) return CC_OK;
+    (void)hipFree(c->d_tiles);
+    (void)hipFree(c->d_mpart);
+    (void)hipFree(c->d_ppart);
+    (void)hipFree(c->d_out);
+    (void)hipFree(c->d_flag);
+    (void)hipFree(c->d_ax);
+    delete c;
+    return CC_OK;
+}
+
+int64_t cc_dual_slots(const cc_ctx *c) { return c ? c->slots : 0; }
+int32_t cc_num_rounds(const cc_ctx *c) { return c ? c->nrounds : 0; }
+
+int cc_prepare(cc_ctx *c, const double *w, double gamma, void *g) {
+    int rc;
+    if ((rc = check_ctx(c)) || (rc = need(w, "w")) || (rc = need(g, "g"))) return rc;
+    if (!(gamma > 0.0) || !std::isfinite(gamma)) return fail(CC_EINVAL, "gamma must be finite and > 0");
+    CCP_HIP_CHECK(hipMemsetAsync(c->d_flag, 0, sizeof(int), c->stream));
+    const int64_t np = num_pairs(c->n);
+    rc = (c->prec == CC_F64)
+             ? launch_prepare<double>(np, w, gamma, static_cast<double *>(g), c->d_flag, c->stream)
+             : launch_prepare<float>(np, w, gamma, static_cast<float *>(g), c->d_flag, c->stream);
+    if (rc) return rc;
+    int bad = 0;
+    CCP_HIP_CHECK(hipMemcpyAsync(&bad, c->d_flag, sizeof(int), hipMemcpyDeviceToHost, c->stream));
+    CCP_HIP_CHECK(hipStreamSynchronize(c->stream));
+    if (bad) return fail(CC_EINVAL, "every weight must be finite and > 0");
+    return CC_OK;
+}
+
+int cc_init_cold(cc_ctx *c, void *x, void *f, void *y, void *yp, double gamma) {
+    int rc;
+    if ((rc = check_ctx(c)) || (rc = need(x, "x")) || (rc = need(f, "f")) || (rc = need(yp, "y_pair")))
+        return rc;
+    if (!(gamma > 0.0) || !std::isfinite(gamma)) return fail(CC_EINVAL, "gamma must be finite and > 0");
+    const int64_t np = num_pairs(c->n);
+    if (c->prec == CC_F64)
+        return launch_init_cold<double>(np, c->slots, (double *)x, (double *)f, (double *)y,
+                                        (double *)yp, gamma, c->stream);
+    return launch_init_cold<float>(np, c->slots, (float *)x, (float *)f, (float *)y, (float *)yp,
+                                   gamma, c->stream);
+}
+
+int cc_sweep(cc_ctx *c, void *x, void *f, void *y, void *yp, const void *g, const uint8_t *d,
+             int32_t nsweeps, int32_t exec) {
+    int rc;
+    if ((rc = check_ctx(c)) || (rc = need(x, "x")) || (rc = need(f, "f")) || (rc = need(y, "y")) ||
+        (rc = need(yp, "y_pair")) || (rc = need(g, "g")) || (rc = need(d, "d")))
+        return rc;
+    if (nsweeps < 0) return fail(CC_EINVAL, "nsweeps must be >= 0");
+    if (exec != CC_EXEC_ROUNDS) return fail(CC_EINVAL, "unknown executor");
+    if (c->prec == CC_F64)
+        return sweep_t<double>(c, (double *)x, (double *)f, (double *)y, (double *)yp,
+                               (const double *)g, d, nsweeps);
+    return sweep_t<float>(c, (float *)x, (float *)f, (float *)y, (float *)yp, (const float *)g, d,
+                          nsweeps);
+}
+
+int cc_sweep_rounds(cc_ctx *c, void *x, void *y, const void *g, int32_t first, int32_t count) {
+    int rc;
+    if ((rc = check_ctx(c)) || (rc = need(x, "x")) || (rc = need(y, "y")) || (rc = need(g, "g")))
+        return rc;
+    if (first < 0 || count < 0 || first + count > c->nrounds)
+        return fail(CC_EINVAL, "round range outside the schedule");
+    if (c->prec == CC_F64)
+        return sweep_rounds_t<double>(c, (double *)x, (double *)y, (const double *)g, first, count);
+    return sweep_rounds_t<float>(c, (float *)x, (float *)y, (const float *)g, first, count);
+}
+
+int cc_pair_pass(cc_ctx *c, void *x, void *f, void *yp, const void *g, const uint8_t *d) {
+    int rc;
+    if ((rc = check_ctx(c)) || (rc = need(x, "x")) || (rc = need(f, "f")) ||
+        (rc = need(yp, "y_pair")) || (rc = need(g, "g")) || (rc = need(d, "d")))
+        return rc;
+    const int64_t np = num_pairs(c->n);
+    if (c->prec == CC_F64)
+        return launch_pair_pass<double>(np, (double *)x, (double *)f, (double *)yp,
+                                        (const double *)g, d, c->stream);
+    return launch_pair_pass<float>(np, (float *)x, (float *)f, (float *)yp, (const float *)g, d,
+                                   c->stream);
+}
+
+int cc_residuals(cc_ctx *c, const void *x, const void *f, const void *y, const void *yp,
+                 const double *w, const uint8_t *d, double gamma, int32_t what, cc_resid *out) {
+    int rc;
+    if ((rc = check_ctx(c)) || (rc = need(x, "x")) || (rc = need(f, "f")) || (rc = need(w, "w")) ||
+        (rc = need(d, "d")) || (rc = need(out, "out")))
+        return rc;
+    if (!(gamma > 0.0)) return fail(CC_EINVAL, "gamma must be > 0");
+    if ((what & (CC_RESID_CS | CC_RESID_DUAL)) && (!y || !yp))
+        return fail(CC_EINVAL, "y and y_pair are needed for CC_RESID_CS / CC_RESID_DUAL");
+    if (c->prec == CC_F64)
+        return residuals_t<double>(c, (const double *)x, (const double *)f, (const double *)y,
+                                   (const double *)yp, w, d, gamma, what, out);
+    return residuals_t<float>(c, (const float *)x, (const float *)f, (const float *)y,
+                              (const float *)yp, w, d, gamma, what, out);
+}
+
+int cc_x_from_y(cc_ctx *c, const void *y, const void *yp, const double *w, double gamma,
+                void *x, void *f) {
+    int rc;
+    if ((rc = check_ctx(c)) || (rc = need(y, "y")) || (rc = need(yp, "y_pair")) ||
+        (rc = need(w, "w")) || (rc = need(x, "x_out")) || (rc = need(f, "f_out")))
+        return rc;
+    if (!(gamma > 0.0)) return fail(CC_EINVAL, "gamma must be > 0");
+    if (c->prec == CC_F64)
+        return x_from_y_t<double>(c, (const double *)y, (const double *)yp, w, gamma, (double *)x,
+                                  (double *)f);
+    return x_from_y_t<float>(c, (const float *)y, (const float *)yp, w, gamma, (float *)x,
+                             (float *)f);
+}
+
+int cc_duals_to_lex(cc_ctx *c, const void *y, void *ylex) {
+    int rc;
+    if ((rc = check_ctx(c)) || (rc = need(y, "y_sched")) || (rc = need(ylex, "y_lex"))) return rc;
+    if (c->prec == CC_F64)
+        return launch_to_lex<double>(c->d_tiles, c->ntiles, c->b, c->n, (const double *)y,
+                                     (double *)ylex, c->stream);
+    return launch_to_lex<float>(c->d_tiles, c->ntiles, c->b, c->n, (const float *)y,
+                                (float *)ylex, c->stream);
+}
+
+int cc_slots_to_lex(cc_ctx *c, const int64_t *slots, int64_t count, int64_t *out) {
+    int rc;
+    if ((rc = check_ctx(c))) return rc;
+    if (count < 0) return fail(CC_EINVAL, "count must be >= 0");
+    if (count && ((rc = need(slots, "slots")) || (rc = need(out, "lex_out")))) return rc;
+    return launch_slots_to_lex(c->d_tiles, c->ntiles, c->b, c->n, slots, count, out, c->stream);
+}
+
+int cc_widen(const float *src, double *dst, int64_t count, void *stream) {
+    if (count < 0) return fail(CC_EINVAL, "count must be >= 0");
+    if (count && (!src || !dst)) return fail(CC_EINVAL, "null pointer");
+    return launch_convert<float, double>(count, src, dst, static_cast<hipStream_t>(stream));
+}
+
+int cc_narrow(const double *src, float *dst, int64_t count, void *stream) {
+    if (count < 0) return fail(CC_EINVAL, "count must be >= 0");
+    if (count && (!src || !dst)) return fail(CC_EINVAL, "null pointer");
+    return launch_convert<double, float>(count, src, dst, static_cast<hipStream_t>(stream));
+}
+
+}  // extern "C"
+
+// ----- one-shot solve ------------------------------------------------------
+namespace {
+
+struct DevBuf {
+    void *p = nullptr;
+    ~DevBuf() { if (p) (void)hipFree(p); }
+    int alloc(size_t bytes, const char *what) {
+        if (hipMalloc(&p, bytes ? bytes : 1) != hipSuccess) {
+            p = nullptr;
+            return fail(CC_ENOMEM, std::string("hipMalloc failed for ") + what);
+        }
+        return CC_OK;
+    }
+};
+
+struct CtxGuard {
+    cc_ctx *c = nullptr;
+    ~CtxGuard() { cc_destroy(c); }
+};
+
+// Sweeps until both max violations are <= tol or max_sweeps is reached;
+// returns CC_OK or CC_ENOTCONV, *done = sweeps run.
+int sweep_to_tol(cc_ctx *c, void *x, void *f, void *y, void *yp, void *g, const uint8_t *d,
+                 const double *w, double gamma, double tol, int max_sweeps, int *done,
+                 cc_resid *r) {
+    const int every = c->n <= 1000 ? 1 : 5;
+    *done = 0;
+    while (*done < max_sweeps) {
+        const int k = std::min(every, max_sweeps - *done);
+        int rc = cc_sweep(c, x, f, y, yp, g, d, k, CC_EXEC_ROUNDS);
+        if (rc) return rc;
+        *done += k;
+        rc = cc_residuals(c, x, f, nullptr, nullptr, w, d, gamma, CC_RESID_VIOL, r);
+        if (rc) return rc;
+        if (std::fmax(r->max_viol_metric, r->max_viol_pair) <= tol) return CC_OK;
+    }
+    return CC_ENOTCONV;
+}
+
+}  // namespace
+
+extern "C" int cc_solve_cc_lp(int64_t n, const double *w_host, const uint8_t *d_host,
+                              double gamma, double tol, int32_t max_sweeps, int32_t b,
+                              int32_t mode, int32_t warm, const float *mlp_weights_host,
+                              const float *deg_host, double *x_out_host,
+                              double *y_lex_out_host, cc_info *info) {
+    const auto t0 = std::chrono::steady_clock::now();
+    if (!w_host || !d_host || !info) return fail(CC_EINVAL, "null w, d or info");
+    if (n < 3) return fail(CC_EINVAL, "n must be at least 3");
+    if (!(gamma > 0.0) || !std::isfinite(gamma)) return fail(CC_EINVAL, "gamma must be > 0");
+    if (!(tol > 0.0)) return fail(CC_EINVAL, "tol must be > 0");
+    if (max_sweeps < 1) return fail(CC_EINVAL, "max_sweeps must be >= 1");
+    if (mode != CC_MODE_F64 && mode != CC_MODE_F32 && mode != CC_MODE_F32_POLISH)
+        return fail(CC_EINVAL, "unknown mode");
+    if (warm != CC_WARM_NONE && warm != CC_WARM_MLP) return fail(CC_EINVAL, "unknown warm start");
+    if (warm == CC_WARM_MLP && (!mlp_weights_host || !deg_host))
+        return fail(CC_EINVAL, "warm start needs network weights and degrees");
+    std::memset(info, 0, sizeof(*info));
+    const int64_t np = num_pairs(n);
+    for (int64_t p = 0; p < np; ++p)
+        if (!(w_host[p] > 0.0) || !std::isfinite(w_host[p]))
+            return fail(CC_EINVAL, "every weight must be finite and > 0");
+
+    int rc;
+    DevBuf dw, dd;
+    if ((rc = dw.alloc(np * sizeof(double), "w")) || (rc = dd.alloc(np, "d"))) return rc;
+    CCP_HIP_CHECK(hipMemcpy(dw.p, w_host, np * sizeof(double), hipMemcpyHostToDevice));
+    CCP_HIP_CHECK(hipMemcpy(dd.p, d_host, np, hipMemcpyHostToDevice));
+    const double *w = static_cast<const double *>(dw.p);
+    const uint8_t *d = static_cast<const uint8_t *>(dd.p);
+
+    const bool f32_first = (mode != CC_MODE_F64);
+    CtxGuard c32, c64;
+    DevBuf x32, f32b, g32, y32, yp32, x64, f64b, g64, y64, yp64;
+    cc_resid r{};
+    int done = 0, status = CC_OK;
+
+    if (f32_first) {
+        if ((rc = cc_create(&c32.c, n, b, CC_F32, nullptr))) return rc;
+        const int64_t slots = c32.c->slots;
+        if ((rc = x32.alloc(np * 4, "x")) || (rc = f32b.alloc(np * 4, "f")) ||
+            (rc = g32.alloc(np * 4, "g")) || (rc = y32.alloc(slots * 4, "y")) ||
+            (rc = yp32.alloc(2 * np * 4, "y_pair")))
+            return rc;
+        if ((rc = cc_prepare(c32.c, w, gamma, g32.p)) ||
+            (rc = cc_init_cold(c32.c, x32.p, f32b.p, y32.p, yp32.p, gamma)))
+            return rc;
+        if (warm == CC_WARM_MLP) {
+            return fail(CC_EINVAL, "warm start is not available in this build");
+        }
+        const double tol32 = (mode == CC_MODE_F32_POLISH) ? std::fmax(tol, 1e-4) : tol;
+        status = sweep_to_tol(c32.c, x32.p, f32b.p, y32.p, yp32.p, g32.p, d, w, gamma, tol32,
+                              max_sweeps, &done, &r);
+        if (status < 0) return status;
+        info->sweeps = info->sweeps_f32 = done;
+    }
+    if (mode != CC_MODE_F32) {
+        if ((rc = cc_create(&c64.c, n, b, CC_F64, nullptr))) return rc;
+        const int64_t slots = c64.c->slots;
+        if ((rc = x64.alloc(np * 8, "x")) || (rc = f64b.alloc(np * 8, "f")) ||
+            (rc = g64.alloc(np * 8, "g")) || (rc = y64.alloc(slots * 8, "y")) ||
+            (rc = yp64.alloc(2 * np * 8, "y_pair")))
+            return rc;
+        if ((rc = cc_prepare(c64.c, w, gamma, g64.p))) return rc;
+        if (f32_first) {
+            // widen the FP32 duals and rebuild v from them in FP64 (the FP32
+            // iterate has drifted from v(y); the duals carry the progress)
+            if ((rc = cc_widen((const float *)y32.p, (double *)y64.p, slots, nullptr)) ||
+                (rc = cc_widen((const float *)yp32.p, (double *)yp64.p, 2 * np, nullptr)) ||
+                (rc = cc_x_from_y(c64.c, y64.p, yp64.p, w, gamma, x64.p, f64b.p)))
+                return rc;
+        } else {
+            if ((rc = cc_init_cold(c64.c, x64.p, f64b.p, y64.p, yp64.p, gamma))) return rc;
+        }
+        const int left = max_sweeps - info->sweeps;
+        if (left > 0) {
+            status = sweep_to_tol(c64.c, x64.p, f64b.p, y64.p, yp64.p, g64.p, d, w, gamma, tol,
+                                  left, &done, &r);
+            if (status < 0) return status;
+            info->sweeps += done;
+        } else {
+            status = CC_ENOTCONV;
+        }
+    }
+    // final residuals and outputs from the last phase
+    cc_ctx *cf = (mode == CC_MODE_F32) ? c32.c : c64.c;
+    void *xf = (mode == CC_MODE_F32) ? x32.p : x64.p;
+    void *ff = (mode == CC_MODE_F32) ? f32b.p : f64b.p;
+    void *yf = (mode == CC_MODE_F32) ? y32.p : y64.p;
+    void *ypf = (mode == CC_MODE_F32) ? yp32.p : yp64.p;
+    rc = cc_residuals(cf, xf, ff, yf, ypf, w, d, gamma, CC_RESID_ALL, &info->resid);
+    if (rc && rc != CC_ENONFINITE) return rc;
+    if (rc == CC_ENONFINITE) status = rc;
+    if (x_out_host) {
+        if (mode == CC_MODE_F32) {
+            DevBuf tmp;
+            if ((rc = tmp.alloc(np * 8, "x copy"))) return rc;
+            if ((rc = cc_widen((const float *)xf, (double *)tmp.p, np, nullptr))) return rc;
+            CCP_HIP_CHECK(hipMemcpy(x_out_host, tmp.p, np * 8, hipMemcpyDeviceToHost));
+        } else {
+            CCP_HIP_CHECK(hipMemcpy(x_out_host, xf, np * 8, hipMemcpyDeviceToHost));
+        }
+    }
+    if (y_lex_out_host) {
+        const int64_t nm = cc_num_metric_duals(n);
+        DevBuf lex;
+        if ((rc = lex.alloc(nm * 8, "y_lex"))) return rc;
+        if (mode == CC_MODE_F32) {
+            DevBuf lex32;
+            if ((rc = lex32.alloc(nm * 4, "y_lex f32"))) return rc;
+            if ((rc = cc_duals_to_lex(cf, yf, lex32.p)) ||
+                (rc = cc_widen((const float *)lex32.p, (double *)lex.p, nm, nullptr)))
+                return rc;
+        } else if ((rc = cc_duals_to_lex(cf, yf, lex.p))) {
+            return rc;
+        }
+        CCP_HIP_CHECK(hipMemcpy(y_lex_out_host, lex.p, nm * 8, hipMemcpyDeviceToHost));
+    }
+    CCP_HIP_CHECK(hipDeviceSynchronize());
+    info->wall_s = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    if (status == CC_ENOTCONV) set_error("sweep limit reached before the tolerance");
+    return status;
+}

@@ -1,0 +1,58 @@
+// common.hpp -- shared types and helpers of the gfx950 solver library.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+
+#include "ccproj.h"
+
+namespace ccp {
+
+// One tile (P,Q) of the tiled schedule (Sec. III-C): every triplet i<j<k
+// with i in index block P and k in index block Q.  `ybase` is the offset of
+// the tile's segment in the schedule-ordered metric dual array.
+struct Tile {
+    int32_t P, Q;
+    int64_t ybase;
+};
+
+// Packed column-major upper-triangular pair index, i < j.
+__host__ __device__ __forceinline__ int64_t pidx(int64_t i, int64_t j) {
+    return j * (j - 1) / 2 + i;
+}
+
+// Colex triplet index, i < j < k.
+__host__ __device__ __forceinline__ int64_t tidx(int64_t i, int64_t j, int64_t k) {
+    return k * (k - 1) * (k - 2) / 6 + j * (j - 1) / 2 + i;
+}
+
+// Middle-index offset of lane (il, kl) at sub-step t: il + jl + kl = t (mod b).
+// Three indices in one block with equal sum mod b can share at most one
+// index unless they are equal, which makes every sub-step conflict-free.
+__host__ __device__ __forceinline__ int mid_offset(int t, int il, int kl, int b) {
+    return (t - il - kl + 2 * b) % b;
+}
+
+// Thread-local error reporting for the C ABI.
+void set_error(const std::string &msg);
+int fail(int code, const std::string &msg);
+
+}  // namespace ccp
+
+#define CCP_HIP_CHECK(expr)                                                       \
+    do {                                                                          \
+        hipError_t e_ = (expr);                                                   \
+        if (e_ != hipSuccess)                                                     \
+            return ::ccp::fail(CC_EHIP, std::string(#expr) + ": " +               \
+                                            hipGetErrorString(e_));               \
+    } while (0)
+
+#define CCP_LAUNCH_CHECK(what)                                                    \
+    do {                                                                          \
+        hipError_t e_ = hipGetLastError();                                        \
+        if (e_ != hipSuccess)                                                     \
+            return ::ccp::fail(CC_EHIP, std::string("launch of ") + (what) +      \
+                                            ": " + hipGetErrorString(e_));        \
+    } while (0)

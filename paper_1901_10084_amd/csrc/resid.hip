@@ -1,0 +1,424 @@
+// resid.hip -- FP64 convergence measures, A'y, and dual layout conversion.
+//
+// Convergence (Sec. IV-D: "constraint satisfaction and duality gap"):
+//   max violation over every metric row and every pair row;
+//   primal QP value c'v + (eps/2) v'Wv and the LP cost sum w |x - d|;
+//   complementary slackness y (b - a'v) over every row;
+//   the dual objective D(y) = -b'y - (1/(2 eps)) (c + A'y)' W^{-1} (c + A'y)
+//   of (qp), and the distance of v from v(y) = -(1/eps) W^{-1} (c + A'y),
+//   the point Algorithm 1 keeps v at (its initial v and every update keep
+//   c + eps W v + A'y = 0).
+// All sums and maxima are taken in FP64 and are deterministic: per-workgroup
+// partials in a fixed order, then one fixed-order final reduction.
+//
+// A'y is accumulated with the same round structure as the sweep (tiles of a
+// round own disjoint pairs), so it needs no atomics and has a fixed order.
+#include "common.hpp"
+
+namespace ccp {
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+    for (int m = 32; m >= 1; m >>= 1) v += __shfl_xor(v, m, 64);
+    return v;
+}
+__device__ __forceinline__ double wave_max(double v) {
+#pragma unroll
+    for (int m = 32; m >= 1; m >>= 1) v = fmax(v, __shfl_xor(v, m, 64));
+    return v;
+}
+
+// Block reduction of NV values; op[v] = 0 for sum, 1 for max.  Result in
+// thread 0.  Requires blockDim.x a multiple of 64 (or <= 64) and
+// scratch[NV * 16].
+template <int NV>
+__device__ void block_reduce(double (&v)[NV], const int (&op)[NV], double *scratch) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int nw = (blockDim.x + 63) >> 6;
+#pragma unroll
+    for (int e = 0; e < NV; ++e) v[e] = op[e] ? wave_max(v[e]) : wave_sum(v[e]);
+    __syncthreads();
+    if (lane == 0)
+        for (int e = 0; e < NV; ++e) scratch[e * 16 + wave] = v[e];
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int e = 0; e < NV; ++e) {
+            double a = scratch[e * 16];
+            for (int w = 1; w < nw; ++w)
+                a = op[e] ? fmax(a, scratch[e * 16 + w]) : a + scratch[e * 16 + w];
+            v[e] = a;
+        }
+    }
+}
+
+__device__ __forceinline__ bool finite(double v) { return v - v == 0.0; }
+
+// ---------------------------------------------------------------------------
+// Metric rows: violation and complementary slackness, one workgroup per tile
+// (all tiles in one launch; read-only, so no ordering between tiles).
+// partial[tile*4 + 0..3] = {max violation, sum y*slack, max |y*slack|,
+// non-finite flag}.
+// ---------------------------------------------------------------------------
+template <typename T, int B>
+__global__ void __launch_bounds__(B ? B * B : 1024)
+k_metric_resid(const Tile *__restrict__ tiles, int b_rt, int64_t n, const T *__restrict__ x,
+               const T *__restrict__ y, double *__restrict__ partial) {
+    const int b = B ? B : b_rt;
+    const int bb = b * b;
+    const int tid = threadIdx.x;
+    const int il = tid / b, kl = tid - (tid / b) * b;
+    const Tile tl = tiles[blockIdx.x];
+    const int P = tl.P, Q = tl.Q;
+    __shared__ double As[1024], Bs[1024], Cs[1024];
+    __shared__ double red[4 * 16];
+    const int64_t i = int64_t(P) * b + il, k = int64_t(Q) * b + kl;
+    {
+        const bool ok = i < k && k < n;
+        Cs[tid] = ok ? double(x[pidx(i, k)]) : 0.0;
+    }
+    double vmax = 0.0, cs_sum = 0.0, cs_max = 0.0, bad = 0.0;
+    for (int J = P; J <= Q; ++J) {
+        if (J != Q) {
+            const int64_t ii = int64_t(P) * b + il, jj = int64_t(J) * b + kl;
+            As[tid] = (ii < jj && jj < n) ? double(x[pidx(ii, jj)]) : 0.0;
+        }
+        if (J != P) {
+            const int64_t jj = int64_t(J) * b + il, kk = int64_t(Q) * b + kl;
+            Bs[tid] = (jj < kk && kk < n) ? double(x[pidx(jj, kk)]) : 0.0;
+        }
+        __syncthreads();
+        const double *Ab = (J == Q) ? Cs : As;
+        const double *Bb = (J == P) ? Cs : Bs;
+        for (int t = 0; t < b; ++t) {
+            const int jl = mid_offset(t, il, kl, b);
+            const int64_t j = int64_t(J) * b + jl;
+            if (i < j && j < k && k < n) {
+                const double xa = Ab[il * b + jl], xb = Bb[jl * b + kl], xc = Cs[tid];
+                const double s0 = (xc + xb) - xa;  // slack of x_ij <= x_ik + x_jk
+                const double s1 = (xa + xb) - xc;  // slack of x_ik <= x_ij + x_jk
+                const double s2 = (xa + xc) - xb;  // slack of x_jk <= x_ij + x_ik
+                vmax = fmax(vmax, fmax(-s0, fmax(-s1, -s2)));
+                if (!finite(s0 + s1 + s2)) bad = 1.0;
+                if (y) {
+                    const int64_t u = int64_t(J - P) * b + t;
+                    const T *src = y + tl.ybase + u * 3 * bb + tid;
+                    const double c0 = double(src[0]) * s0, c1 = double(src[bb]) * s1,
+                                 c2 = double(src[2 * bb]) * s2;
+                    cs_sum += (c0 + c1) + c2;
+                    cs_max = fmax(cs_max, fmax(fabs(c0), fmax(fabs(c1), fabs(c2))));
+                }
+            }
+        }
+        __syncthreads();
+    }
+    double v[4] = {vmax, cs_sum, cs_max, bad};
+    const int op[4] = {1, 0, 1, 1};
+    block_reduce<4>(v, op, red);
+    if (tid == 0)
+        for (int e = 0; e < 4; ++e) partial[int64_t(blockIdx.x) * 4 + e] = v[e];
+}
+
+// ---------------------------------------------------------------------------
+// Pair rows and the objective sums.  partial[block*10 + e]:
+//  0 max pair violation   1 sum w f          2 sum w (x^2 + f^2)
+//  3 sum w |x - d|        4 max |y * slack|  5 sum y * slack
+//  6 sum (c+A'y)^2 / w    7 b'y              8 max |v - v(y)|
+//  9 non-finite flag
+// ax (metric part of A'y on x) may be null: then 6-8 stay 0.
+// ---------------------------------------------------------------------------
+constexpr int kPairBlocks = 1024;
+
+template <typename T>
+__global__ void __launch_bounds__(256)
+k_pair_resid(int64_t np, const T *__restrict__ x, const T *__restrict__ f,
+             const T *__restrict__ yp, const double *__restrict__ w,
+             const uint8_t *__restrict__ d, const double *__restrict__ ax, double gamma,
+             double *__restrict__ partial) {
+    __shared__ double red[10 * 16];
+    double vp = 0, swf = 0, swq = 0, lp = 0, csm = 0, css = 0, qd = 0, by = 0, st = 0, bad = 0;
+    for (int64_t p = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; p < np;
+         p += int64_t(gridDim.x) * blockDim.x) {
+        const double xv = double(x[p]), fv = double(f[p]), wv = w[p], dv = double(d[p]);
+        const double s1 = dv - (xv - fv);     // slack of  x - f <= d
+        const double s2 = -dv - (-xv - fv);   // slack of -x - f <= -d
+        vp = fmax(vp, fmax(-s1, -s2));
+        swf += wv * fv;
+        swq += wv * (xv * xv + fv * fv);
+        lp += wv * fabs(xv - dv);
+        if (!finite(xv) || !finite(fv)) bad = 1.0;
+        if (yp) {
+            const double y1 = double(yp[2 * p]), y2 = double(yp[2 * p + 1]);
+            const double c1 = y1 * s1, c2 = y2 * s2;
+            csm = fmax(csm, fmax(fabs(c1), fabs(c2)));
+            css += c1 + c2;
+            if (ax) {
+                const double gx = ax[p] + (y1 - y2);     // c_x = 0
+                const double gf = wv + (-y1 - y2);       // c_f = w
+                qd += (gx * gx + gf * gf) / wv;
+                by += dv * y1 - dv * y2;
+                st = fmax(st, fmax(fabs(xv + gamma * gx / wv), fabs(fv + gamma * gf / wv)));
+            }
+        }
+    }
+    double v[10] = {vp, swf, swq, lp, csm, css, qd, by, st, bad};
+    const int op[10] = {1, 0, 0, 0, 1, 0, 0, 0, 1, 1};
+    block_reduce<10>(v, op, red);
+    if (threadIdx.x == 0)
+        for (int e = 0; e < 10; ++e) partial[int64_t(blockIdx.x) * 10 + e] = v[e];
+}
+
+// Fixed-order final reduction: out[0..3] from the metric partials, out[4..13]
+// from the pair partials.
+__global__ void __launch_bounds__(256)
+k_final_reduce(const double *__restrict__ mpart, int64_t nm, const double *__restrict__ ppart,
+               int64_t npb, double *__restrict__ out) {
+    __shared__ double red[14 * 16];
+    double v[14];
+    for (int e = 0; e < 14; ++e) v[e] = 0.0;
+    const int opm[4] = {1, 0, 1, 1};
+    const int opp[10] = {1, 0, 0, 0, 1, 0, 0, 0, 1, 1};
+    for (int64_t r = threadIdx.x; r < nm; r += blockDim.x)
+        for (int e = 0; e < 4; ++e)
+            v[e] = opm[e] ? fmax(v[e], mpart[r * 4 + e]) : v[e] + mpart[r * 4 + e];
+    for (int64_t r = threadIdx.x; r < npb; r += blockDim.x)
+        for (int e = 0; e < 10; ++e)
+            v[4 + e] = opp[e] ? fmax(v[4 + e], ppart[r * 10 + e]) : v[4 + e] + ppart[r * 10 + e];
+    int op[14];
+    for (int e = 0; e < 4; ++e) op[e] = opm[e];
+    for (int e = 0; e < 10; ++e) op[4 + e] = opp[e];
+    block_reduce<14>(v, op, red);
+    if (threadIdx.x == 0)
+        for (int e = 0; e < 14; ++e) out[e] = v[e];
+}
+
+// ---------------------------------------------------------------------------
+// A'y on the x block, metric rows only, one round per launch.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void lds_barrier_r() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+    __builtin_amdgcn_s_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
+template <typename T, int B>
+__global__ void __launch_bounds__(B ? B * B : 1024)
+k_aty_round(const Tile *__restrict__ tiles, int b_rt, int64_t n, const T *__restrict__ y,
+            double *__restrict__ ax) {
+    const int b = B ? B : b_rt;
+    const int bb = b * b;
+    const int tid = threadIdx.x;
+    const int il = tid / b, kl = tid - (tid / b) * b;
+    const Tile tl = tiles[blockIdx.x];
+    const int P = tl.P, Q = tl.Q;
+    __shared__ double As[1024], Bs[1024], Cs[1024];
+    const int64_t i = int64_t(P) * b + il, k = int64_t(Q) * b + kl;
+    const bool c_ok = i < k && k < n;
+    Cs[tid] = c_ok ? ax[pidx(i, k)] : 0.0;
+    for (int J = P; J <= Q; ++J) {
+        int64_t pa = -1, pb = -1;
+        if (J != Q) {
+            const int64_t ii = int64_t(P) * b + il, jj = int64_t(J) * b + kl;
+            if (ii < jj && jj < n) pa = pidx(ii, jj);
+            As[tid] = pa >= 0 ? ax[pa] : 0.0;
+        }
+        if (J != P) {
+            const int64_t jj = int64_t(J) * b + il, kk = int64_t(Q) * b + kl;
+            if (jj < kk && kk < n) pb = pidx(jj, kk);
+            Bs[tid] = pb >= 0 ? ax[pb] : 0.0;
+        }
+        lds_barrier_r();
+        double *Ab = (J == Q) ? Cs : As;
+        double *Bb = (J == P) ? Cs : Bs;
+        for (int t = 0; t < b; ++t) {
+            const int jl = mid_offset(t, il, kl, b);
+            const int64_t j = int64_t(J) * b + jl;
+            if (i < j && j < k && k < n) {
+                const int64_t u = int64_t(J - P) * b + t;
+                const T *src = y + tl.ybase + u * 3 * bb + tid;
+                const double y0 = double(src[0]), y1 = double(src[bb]), y2 = double(src[2 * bb]);
+                Ab[il * b + jl] += (y0 - y1) - y2;  // pair (i,j)
+                Cs[tid] += (y1 - y0) - y2;          // pair (i,k)
+                Bb[jl * b + kl] += (y2 - y0) - y1;  // pair (j,k)
+            }
+            lds_barrier_r();
+        }
+        if (pa >= 0) ax[pa] = As[tid];
+        if (pb >= 0) ax[pb] = Bs[tid];
+        lds_barrier_r();
+    }
+    if (c_ok) ax[pidx(i, k)] = Cs[tid];
+}
+
+// x = -gamma W^{-1} (c + A'y): adds the pair rows' part of A'y.
+template <typename T>
+__global__ void k_x_from_aty(int64_t np, const double *__restrict__ ax, const T *__restrict__ yp,
+                             const double *__restrict__ w, double gamma, T *__restrict__ x,
+                             T *__restrict__ f) {
+    for (int64_t p = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; p < np;
+         p += int64_t(gridDim.x) * blockDim.x) {
+        const double y1 = double(yp[2 * p]), y2 = double(yp[2 * p + 1]);
+        const double gx = ax[p] + (y1 - y2);
+        const double gf = w[p] + (-y1 - y2);
+        x[p] = T(-gamma * gx / w[p]);
+        f[p] = T(-gamma * gf / w[p]);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Layout conversion: schedule order -> colex order.
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ void __launch_bounds__(1024)
+k_to_lex(const Tile *__restrict__ tiles, int b, int64_t n, const T *__restrict__ y,
+         T *__restrict__ ylex) {
+    const int bb = b * b;
+    const int tid = threadIdx.x;
+    const int il = tid / b, kl = tid - (tid / b) * b;
+    const Tile tl = tiles[blockIdx.x];
+    const int64_t i = int64_t(tl.P) * b + il, k = int64_t(tl.Q) * b + kl;
+    for (int J = tl.P; J <= tl.Q; ++J)
+        for (int t = 0; t < b; ++t) {
+            const int64_t j = int64_t(J) * b + mid_offset(t, il, kl, b);
+            if (i < j && j < k && k < n) {
+                const int64_t u = int64_t(J - tl.P) * b + t;
+                const T *src = y + tl.ybase + u * 3 * bb + tid;
+                T *dst = ylex + 3 * tidx(i, j, k);
+                dst[0] = src[0];
+                dst[1] = src[bb];
+                dst[2] = src[2 * bb];
+            }
+        }
+}
+
+__global__ void k_slots_to_lex(const Tile *__restrict__ tiles, int64_t ntiles, int b, int64_t n,
+                               const int64_t *__restrict__ slots, int64_t count,
+                               int64_t *__restrict__ out) {
+    const int64_t bb = int64_t(b) * b;
+    for (int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; e < count;
+         e += int64_t(gridDim.x) * blockDim.x) {
+        const int64_t s = slots[e];
+        int64_t lo = 0, hi = ntiles - 1;
+        while (lo < hi) {  // last tile with ybase <= s
+            const int64_t mid = (lo + hi + 1) / 2;
+            if (tiles[mid].ybase <= s) lo = mid; else hi = mid - 1;
+        }
+        const Tile tl = tiles[lo];
+        const int64_t off = s - tl.ybase;
+        const int64_t u = off / (3 * bb), rem = off - u * 3 * bb;
+        const int o = int(rem / bb), lane = int(rem - (rem / bb) * bb);
+        const int il = lane / b, kl = lane % b;
+        const int J = tl.P + int(u / b), t = int(u % b);
+        const int64_t i = int64_t(tl.P) * b + il, k = int64_t(tl.Q) * b + kl;
+        const int64_t j = int64_t(J) * b + mid_offset(t, il, kl, b);
+        const bool ok = s >= 0 && J <= tl.Q && i < j && j < k && k < n;
+        out[e] = ok ? 3 * tidx(i, j, k) + o : -1;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Launchers.
+// ---------------------------------------------------------------------------
+static inline unsigned grid_of(int64_t count, int block) {
+    int64_t g = (count + block - 1) / block;
+    if (g < 1) g = 1;
+    if (g > 65536) g = 65536;
+    return unsigned(g);
+}
+
+template <typename T>
+int launch_metric_resid(const Tile *tiles, int64_t ntiles, int b, int64_t n, const T *x,
+                        const T *y, double *partial, hipStream_t s) {
+    switch (b) {
+        case 8: hipLaunchKernelGGL((k_metric_resid<T, 8>), dim3(ntiles), dim3(64), 0, s, tiles, b, n, x, y, partial); break;
+        case 16: hipLaunchKernelGGL((k_metric_resid<T, 16>), dim3(ntiles), dim3(256), 0, s, tiles, b, n, x, y, partial); break;
+        case 32: hipLaunchKernelGGL((k_metric_resid<T, 32>), dim3(ntiles), dim3(1024), 0, s, tiles, b, n, x, y, partial); break;
+        default: hipLaunchKernelGGL((k_metric_resid<T, 0>), dim3(ntiles), dim3(b * b), 0, s, tiles, b, n, x, y, partial); break;
+    }
+    CCP_LAUNCH_CHECK("k_metric_resid");
+    return CC_OK;
+}
+
+template <typename T>
+int launch_pair_resid(int64_t np, const T *x, const T *f, const T *yp, const double *w,
+                      const uint8_t *d, const double *ax, double gamma, double *partial,
+                      hipStream_t s) {
+    hipLaunchKernelGGL(k_pair_resid<T>, dim3(kPairBlocks), dim3(256), 0, s, np, x, f, yp, w, d,
+                       ax, gamma, partial);
+    CCP_LAUNCH_CHECK("k_pair_resid");
+    return CC_OK;
+}
+
+int launch_final_reduce(const double *mpart, int64_t nm, const double *ppart, double *out,
+                        hipStream_t s) {
+    hipLaunchKernelGGL(k_final_reduce, dim3(1), dim3(256), 0, s, mpart, nm, ppart,
+                       int64_t(kPairBlocks), out);
+    CCP_LAUNCH_CHECK("k_final_reduce");
+    return CC_OK;
+}
+
+int pair_partial_blocks() { return kPairBlocks; }
+
+template <typename T>
+int launch_aty_round(const Tile *tiles, int ntiles, int b, int64_t n, const T *y, double *ax,
+                     hipStream_t s) {
+    if (ntiles <= 0) return CC_OK;
+    switch (b) {
+        case 8: hipLaunchKernelGGL((k_aty_round<T, 8>), dim3(ntiles), dim3(64), 0, s, tiles, b, n, y, ax); break;
+        case 16: hipLaunchKernelGGL((k_aty_round<T, 16>), dim3(ntiles), dim3(256), 0, s, tiles, b, n, y, ax); break;
+        case 32: hipLaunchKernelGGL((k_aty_round<T, 32>), dim3(ntiles), dim3(1024), 0, s, tiles, b, n, y, ax); break;
+        default: hipLaunchKernelGGL((k_aty_round<T, 0>), dim3(ntiles), dim3(b * b), 0, s, tiles, b, n, y, ax); break;
+    }
+    CCP_LAUNCH_CHECK("k_aty_round");
+    return CC_OK;
+}
+
+template <typename T>
+int launch_x_from_aty(int64_t np, const double *ax, const T *yp, const double *w, double gamma,
+                      T *x, T *f, hipStream_t s) {
+    hipLaunchKernelGGL(k_x_from_aty<T>, dim3(grid_of(np, 256)), dim3(256), 0, s, np, ax, yp, w,
+                       gamma, x, f);
+    CCP_LAUNCH_CHECK("k_x_from_aty");
+    return CC_OK;
+}
+
+template <typename T>
+int launch_to_lex(const Tile *tiles, int64_t ntiles, int b, int64_t n, const T *y, T *ylex,
+                  hipStream_t s) {
+    hipLaunchKernelGGL(k_to_lex<T>, dim3(ntiles), dim3(b * b), 0, s, tiles, b, n, y, ylex);
+    CCP_LAUNCH_CHECK("k_to_lex");
+    return CC_OK;
+}
+
+int launch_slots_to_lex(const Tile *tiles, int64_t ntiles, int b, int64_t n,
+                        const int64_t *slots, int64_t count, int64_t *out, hipStream_t s) {
+    if (count <= 0) return CC_OK;
+    hipLaunchKernelGGL(k_slots_to_lex, dim3(grid_of(count, 256)), dim3(256), 0, s, tiles,
+                       ntiles, b, n, slots, count, out);
+    CCP_LAUNCH_CHECK("k_slots_to_lex");
+    return CC_OK;
+}
+
+template int launch_metric_resid<double>(const Tile *, int64_t, int, int64_t, const double *,
+                                         const double *, double *, hipStream_t);
+template int launch_metric_resid<float>(const Tile *, int64_t, int, int64_t, const float *,
+                                        const float *, double *, hipStream_t);
+template int launch_pair_resid<double>(int64_t, const double *, const double *, const double *,
+                                       const double *, const uint8_t *, const double *, double,
+                                       double *, hipStream_t);
+template int launch_pair_resid<float>(int64_t, const float *, const float *, const float *,
+                                      const double *, const uint8_t *, const double *, double,
+                                      double *, hipStream_t);
+template int launch_aty_round<double>(const Tile *, int, int, int64_t, const double *, double *,
+                                      hipStream_t);
+template int launch_aty_round<float>(const Tile *, int, int, int64_t, const float *, double *,
+                                     hipStream_t);
+template int launch_x_from_aty<double>(int64_t, const double *, const double *, const double *,
+                                       double, double *, double *, hipStream_t);
+template int launch_x_from_aty<float>(int64_t, const double *, const float *, const double *,
+                                      double, float *, float *, hipStream_t);
+template int launch_to_lex<double>(const Tile *, int64_t, int, int64_t, const double *, double *,
+                                   hipStream_t);
+template int launch_to_lex<float>(const Tile *, int64_t, int, int64_t, const float *, float *,
+                                  hipStream_t);
+
+}  // namespace ccp

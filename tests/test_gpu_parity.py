@@ -1,0 +1,193 @@
+"""GPU path against the FP64 oracle, element by element, through the C ABI."""
+import numpy as np
+import pytest
+
+import oracle
+from conftest import gpu_available
+from paper_1901_10084_amd import instances as I
+
+pytestmark = pytest.mark.gpu
+
+if gpu_available():
+    import torch
+    from paper_1901_10084_amd import ccproj as C
+
+
+def rel_err(a, ref):
+    a = np.asarray(a, dtype=np.float64)
+    ref = np.asarray(ref, dtype=np.float64)
+    if ref.size == 0:
+        return 0.0
+    return float(np.abs(a - ref).max() / max(1.0, float(np.abs(ref).max())))
+
+
+TOL64 = 1e-10   # FP64 GPU vs FP64 oracle, relative to max(1, |ref|_inf)
+
+
+def compare_state(gs, os_, tol, what=""):
+    x, f = gs.x.cpu().numpy(), gs.f.cpu().numpy()
+    yp = gs.y_pair.cpu().numpy()
+    ylex = gs.duals_lex().cpu().numpy()
+    errs = dict(x=rel_err(x, os_.x), f=rel_err(f, os_.f), y_pair=rel_err(yp, os_.y_pair),
+                y=rel_err(ylex, os_.y))
+    print(what, errs, flush=True)
+    for k, e in errs.items():
+        assert e <= tol, (what, k, e)
+    return errs
+
+
+CASES = [
+    # (instance, b, sweeps)
+    (lambda: I.random_signed(13, seed=1, gamma=1.5, weighted=True), 4, 3),
+    (lambda: I.random_signed(20, seed=2, gamma=0.8, weighted=True), 3, 5),
+    (lambda: I.random_signed(37, seed=3, gamma=2.0, weighted=True), 8, 4),
+    (lambda: I.random_signed(45, seed=4, gamma=1.0, weighted=False), 5, 3),
+    (lambda: I.random_signed(70, seed=5, gamma=3.0, weighted=True), 32, 2),
+    (lambda: I.random_signed(5, seed=6, gamma=1.0, weighted=True), 8, 6),    # one tile
+    (lambda: I.random_signed(3, seed=7, gamma=1.0, weighted=True), 1, 10),   # one triplet
+    (lambda: I.random_signed(17, seed=8, gamma=1.0, weighted=True), 1, 3),   # b = 1: Fig. 2
+    (lambda: I.workload(0), 8, 20),
+    (lambda: I.workload(0), 16, 3),
+    (lambda: I.workload(0), 4, 1),
+]
+
+
+@pytest.mark.parametrize("case", range(len(CASES)))
+def test_sweep_parity_f64(case):
+    mk, b, K = CASES[case]
+    inst = mk()
+    print(f"case {case}: n={inst.n} b={b} K={K}", flush=True)
+    g = C.Solver.from_instance(inst, b=b, prec="f64")
+    o = oracle.State.from_instance(inst)
+    for k in range(K):
+        g.sweep(1)
+        o.sweep(1, b=b)
+    compare_state(g, o, TOL64, f"n={inst.n} b={b} K={K}")
+
+
+def test_parity_workload0_to_tolerance():
+    """n = 60 Erdos-Renyi, gamma = 1: both reach max violation <= 1e-6 at the
+    same sweep and agree there."""
+    inst = I.workload(0)
+    g = C.Solver.from_instance(inst, b=8)
+    r, conv, _ = g.solve(tol=1e-6, max_sweeps=5000)
+    assert conv
+    o = oracle.State.from_instance(inst)
+    ro = o.solve(tol=1e-6, b=8, max_sweeps=5000)
+    assert o.sweeps == g.sweeps
+    compare_state(g, o, TOL64, "workload0 converged")
+    for key in ("max_viol_metric", "max_viol_pair", "primal_qp", "dual_qp", "lp_cost",
+                "stat_resid"):
+        assert abs(r[key] - ro[key]) <= 1e-9 * max(1.0, abs(ro[key])), key
+
+
+def test_parity_workload1_three_sweeps():
+    """n = 500 planted partition (62M metric rows), b = 16, full state after 3
+    sweeps."""
+    inst = I.workload(1)
+    g = C.Solver.from_instance(inst, b=16)
+    o = oracle.State.from_instance(inst)
+    g.sweep(3)
+    o.sweep(3, b=16)
+    compare_state(g, o, TOL64, "workload1 K=3")
+
+
+@pytest.mark.parametrize("n,b,rounds", [(1500, 16, 3), (2000, 16, 2)])
+def test_prefix_parity_large(n, b, rounds):
+    """Large instances: sweep 1, then the first rounds of sweep 2, against
+    the oracle's sparse-dual prefix."""
+    inst = I.workload(2) if n == 1500 else I.workload(3)
+    g = C.Solver.from_instance(inst, b=b)
+    g.sweep(1)
+    g.sweep_rounds(0, rounds)
+    x, f, yp, t, o, y = oracle.second_sweep_prefix(n, b, inst.gamma, inst.w, inst.d, rounds)
+    assert rel_err(g.x.cpu().numpy(), x) <= TOL64
+    assert rel_err(g.f.cpu().numpy(), f) <= TOL64
+    assert rel_err(g.y_pair.cpu().numpy(), yp) <= TOL64
+    nz = torch.nonzero(g.y).flatten()
+    lex = torch.empty_like(nz)
+    g.ctx.slots_to_lex(nz, lex)
+    lex = lex.cpu().numpy()
+    assert (lex >= 0).all()
+    vals = g.y[nz].cpu().numpy()
+    order = np.argsort(lex)
+    ref = np.argsort(3 * t + o)
+    assert np.array_equal(lex[order], (3 * t + o)[ref])
+    assert rel_err(vals[order], y[ref]) <= TOL64
+    print(f"prefix n={n}: {len(t)} nonzero duals", flush=True)
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_residuals_and_x_from_y(prec):
+    inst = I.random_signed(31, seed=9, gamma=2.5, weighted=True)
+    g = C.Solver.from_instance(inst, b=8, prec=prec)
+    o = oracle.State.from_instance(inst)
+    g.sweep(7)
+    o.sweep(7, b=8)
+    r = g.residuals()
+    ro = o.residuals()
+    tol = 1e-9 if prec == "f64" else 2e-4
+    for key in ro:
+        assert abs(r[key] - ro[key]) <= tol * max(1.0, abs(ro[key])), (key, r[key], ro[key])
+    x, f = g.x_from_y()
+    xo, fo = o.x_from_y()
+    assert rel_err(x.cpu().numpy(), xo) <= (1e-12 if prec == "f64" else 1e-5)
+    assert rel_err(f.cpu().numpy(), fo) <= (1e-12 if prec == "f64" else 1e-5)
+
+
+def test_f32_close_to_oracle():
+    """FP32 sweeps against the FP64 oracle: the error stays at FP32 level."""
+    inst = I.workload(0)
+    g = C.Solver.from_instance(inst, b=8, prec="f32")
+    o = oracle.State.from_instance(inst)
+    g.sweep(20)
+    o.sweep(20, b=8)
+    compare_state(g, o, 5e-5, "f32 workload0 K=20")
+
+
+def test_padding_slots_stay_zero():
+    inst = I.random_signed(19, seed=3, gamma=1.0, weighted=True)
+    g = C.Solver.from_instance(inst, b=8)
+    g.sweep(5)
+    idx = torch.arange(g.ctx.slots, device="cuda", dtype=torch.int64)
+    lex = torch.empty_like(idx)
+    g.ctx.slots_to_lex(idx, lex)
+    pad = lex < 0
+    assert int((~pad).sum()) == C.num_metric_duals(19)
+    assert not g.y[pad].any()
+    # every colex index appears exactly once
+    assert torch.equal(torch.sort(lex[~pad]).values,
+                       torch.arange(C.num_metric_duals(19), device="cuda"))
+
+
+def test_nonfinite_detected():
+    inst = I.random_signed(12, seed=1)
+    g = C.Solver.from_instance(inst, b=4)
+    g.sweep(2)
+    g.x[5] = float("nan")
+    r = g.residuals(C.CC_RESID_VIOL, raise_nonfinite=False)
+    assert r.get("nonfinite")
+    with pytest.raises(C.CCError) as e:
+        g.residuals(C.CC_RESID_VIOL)
+    assert e.value.code == C.CC_ENONFINITE
+
+
+def test_bad_weights_rejected():
+    inst = I.random_signed(10, seed=1)
+    w = inst.w.copy()
+    w[3] = 0.0
+    with pytest.raises(C.CCError) as e:
+        C.Solver(inst.n, w, inst.d, 1.0, b=4)
+    assert e.value.code == C.CC_EINVAL
+    w[3] = np.inf
+    with pytest.raises(C.CCError):
+        C.Solver(inst.n, w, inst.d, 1.0, b=4)
+
+
+def test_duals_nonnegative_and_stationary():
+    inst = I.workload(0)
+    g = C.Solver.from_instance(inst, b=8)
+    g.sweep(50)
+    assert float(g.y.min()) >= 0.0 and float(g.y_pair.min()) >= 0.0
+    r = g.residuals()
+    assert r["stat_resid"] < 1e-12
