@@ -25,7 +25,9 @@
  * block P and k in block Q (a b x b group of the sets S_{i,k}).  Rounds are
  * the block anti-diagonals s = P+Q, taken in the order s = nb-1, nb-2, ..., 0
  * and then s = nb, ..., 2nb-2 (the two double loops of Fig. 2); tiles of a
- * round go by ascending P.  Inside a tile the middle block J runs P..Q; inside
+ * round go by ascending P.  Inside a tile the middle block J runs from Q down
+ * to P in the rounds of the first loop (s < nb) and from P up to Q in those
+ * of the second loop (s >= nb); inside
  * a (tile, J) cube the sub-steps t = 0..b-1 each take, for every local pair
  * (il, kl) in row-major order, the middle index with local offset
  * jl = (t - il - kl) mod b, so that il + jl + kl = t (mod b).  A triplet is
@@ -75,7 +77,10 @@ static void visit_schedule(int64_t n, int64_t b, int64_t max_rounds,
         for (int64_t P = 0; 2 * P <= s; P++) {
             int64_t Q = s - P;
             if (Q >= nb) continue;
-            for (int64_t J = P; J <= Q; J++)
+            /* middle blocks: descending in the first loop's rounds,
+             * ascending in the second loop's */
+            for (int64_t m = 0; m <= Q - P; m++) {
+                int64_t J = (s < nb) ? Q - m : P + m;
                 for (int64_t t = 0; t < b; t++)
                     for (int64_t il = 0; il < b; il++)
                         for (int64_t kl = 0; kl < b; kl++) {
@@ -84,6 +89,7 @@ static void visit_schedule(int64_t n, int64_t b, int64_t max_rounds,
                             if (i < j && j < k && k < n)
                                 fn(ctx, i, j, k, r, P, J, t);
                         }
+            }
         }
     }
 }

@@ -263,18 +263,24 @@ def test_schedule_exact_cover_and_conflict_free(n, b):
 
 def test_schedule_b1_is_the_diagonal_order():
     """With b = 1 the order is that of Fig. 2: sets S_{i,k} by anti-diagonal
-    i + k from n+1 down to 4 (1-based), then from n+2 up to 2n-2, sets on a
-    diagonal by ascending i, and j ascending inside each set."""
+    i + k from n+1 down to 4 (1-based, first double loop), then from n+2 up
+    to 2n-2 (second double loop), sets on a diagonal by ascending i.  The
+    order of j inside a set, which Fig. 2 leaves open, is descending in the
+    first loop and ascending in the second."""
     n = 11
     rows = oracle.schedule(n, 1)
     expect = []
-    diagonals = list(range(n + 1, 3, -1)) + list(range(n + 2, 2 * n - 1))
-    for sdiag in diagonals:                        # 1-based i + k
+    first = list(range(n + 1, 3, -1))
+    second = list(range(n + 2, 2 * n - 1))
+    for sdiag in first + second:                   # 1-based i + k
         for i1 in range(1, n + 1):
             k1 = sdiag - i1
             if not (i1 < k1 <= n) or k1 < i1 + 2:
                 continue
-            for j1 in range(i1 + 1, k1):
+            js = range(i1 + 1, k1)
+            if sdiag in first:
+                js = reversed(js)
+            for j1 in js:
                 expect.append((i1 - 1, j1 - 1, k1 - 1))
     assert [tuple(r) for r in rows[:, :3]] == expect
 
