@@ -66,7 +66,7 @@ def main():
     ap.add_argument("--config", type=int, default=1, help="workload index 0..4")
     ap.add_argument("--b", type=int, default=16, help="tile size")
     ap.add_argument("--prec", default="f64", choices=["f64", "f32"])
-    ap.add_argument("--exec", default="rounds", choices=["rounds", "dataflow"])
+    ap.add_argument("--exec", default="dataflow", choices=["rounds", "dataflow"])
     ap.add_argument("--cpu-budget", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-solve", action="store_true")

@@ -108,11 +108,13 @@ int cc_destroy(cc_ctx *ctx);
 
 /* Length (elements) of the schedule-ordered metric dual array y.  Each tile
  * (P,Q) of the schedule owns a contiguous segment, laid out as
- * [middle block J][sub-step t][orientation o][lane il*b + kl], so every
- * sub-step reads and writes 3 contiguous vectors of b*b elements.  Slots of
- * index combinations that are not triplets i<j<k<n are padding: they are
- * zero after cc_init_cold and never read or written by a sweep.  The count
- * is 3 b^3 nb(nb+1)(nb+2)/6 with nb = ceil(n/b), at least 3 C(n,3). */
+ * [tile step m][sub-step t][orientation o][lane il*b + kl]; step m visits
+ * middle block J = Q - m in the rounds of the first loop of Fig. 2
+ * (P + Q < nb) and J = P + m in the others.  Every sub-step reads and writes
+ * 3 contiguous vectors of b*b elements.  Slots of index combinations that
+ * are not triplets i<j<k<n are padding: zero after cc_init_cold, and a sweep
+ * writes back the value it read.  The count is 3 b^3 nb(nb+1)(nb+2)/6 with
+ * nb = ceil(n/b), at least 3 C(n,3). */
 int64_t cc_dual_slots(const cc_ctx *ctx);
 
 /* Number of rounds of the schedule, 2 ceil(n/b) - 1. */
@@ -131,9 +133,12 @@ int cc_init_cold(cc_ctx *ctx, void *x, void *f, void *y, void *y_pair, double ga
 /* nsweeps full sweeps (Sec. IV-D: one pass over every constraint): all
  * metric rounds in schedule order, then the pair pass.  g from cc_prepare;
  * d: device uint8[N_p].  exec selects the executor (CC_EXEC_ROUNDS: one
- * launch per round; CC_EXEC_DATAFLOW: one persistent launch per sweep whose
- * tiles wait only for the tiles they depend on).  Both executors apply every
- * update to every variable in the same order and give identical results. */
+ * launch per round; CC_EXEC_DATAFLOW, for b = 8, 16, 32: one persistent
+ * launch per sweep whose tile steps wait only for the earlier steps that
+ * touch the same blocks of x).  Both executors apply the updates of every
+ * variable in the same order and give identical results.  A dataflow wait
+ * longer than 10 s aborts the sweep with CC_EHIP (the state is then
+ * incomplete); no wait can block forever. */
 int cc_sweep(cc_ctx *ctx, void *x, void *f, void *y, void *y_pair, const void *g,
              const uint8_t *d, int32_t nsweeps, int32_t exec);
 
@@ -167,6 +172,17 @@ int cc_duals_to_lex(cc_ctx *ctx, const void *y_sched, void *y_lex);
 /* Colex index 3t + o of each schedule slot in slots[0..count) (device int64
  * arrays; -1 for padding slots). */
 int cc_slots_to_lex(cc_ctx *ctx, const int64_t *slots, int64_t count, int64_t *lex_out);
+
+/* Host only, no GPU: the dependency tables of the CC_EXEC_DATAFLOW executor
+ * for (n, b), for verification.  Tiles are in schedule order; tile t has
+ * blocks (P,Q) = tile_pq[2t], tile_pq[2t+1], its first step at jsbase[t],
+ * and waits for need_c[t] earlier touches of block (P,Q); step s waits for
+ * needs[2s] earlier touches of block (P,J) (J != Q) and needs[2s+1] of block
+ * (J,Q) (J != P); K[X] counts the touches of block X = B(B+1)/2 + A per
+ * sweep.  Pass NULL outputs to query the sizes first. */
+int cc_dataflow_tables(int64_t n, int32_t b, int64_t *ntiles, int64_t *nsteps, int64_t *nblocks,
+                       int32_t *tile_pq, uint32_t *need_c, int32_t *jsbase, uint32_t *needs,
+                       uint32_t *K);
 
 /* Element-wise precision change (device arrays, count elements):
  * float -> double (widen) or double -> float (narrow). */

@@ -70,13 +70,14 @@ _sig("cc_residuals", ctypes.c_int, _p, _p, _p, _p, _p, _p, _p, _dbl, _i32,
 _sig("cc_x_from_y", ctypes.c_int, _p, _p, _p, _p, _dbl, _p, _p)
 _sig("cc_duals_to_lex", ctypes.c_int, _p, _p, _p)
 _sig("cc_slots_to_lex", ctypes.c_int, _p, _p, _i64, _p)
+_sig("cc_dataflow_tables", ctypes.c_int, _i64, _i32, _p, _p, _p, _p, _p, _p, _p, _p)
 _sig("cc_widen", ctypes.c_int, _p, _p, _i64, _p)
 _sig("cc_narrow", ctypes.c_int, _p, _p, _i64, _p)
 
 EXPORTS = ["cc_last_error", "cc_num_metric_duals", "cc_create", "cc_destroy", "cc_dual_slots",
            "cc_num_rounds", "cc_prepare", "cc_init_cold", "cc_sweep", "cc_sweep_rounds",
            "cc_pair_pass", "cc_residuals", "cc_x_from_y", "cc_duals_to_lex", "cc_slots_to_lex",
-           "cc_widen", "cc_narrow"]
+           "cc_dataflow_tables", "cc_widen", "cc_narrow"]
 
 
 class CCError(RuntimeError):
@@ -182,6 +183,22 @@ class Context:
 
     def slots_to_lex(self, slots, out):
         check(_L.cc_slots_to_lex(self._h, _ptr(slots), int(slots.numel()), _ptr(out)))
+
+
+def dataflow_tables(n: int, b: int) -> dict:
+    """Dependency tables of the dataflow executor (host only, no GPU)."""
+    nt, ns, nbk = _i64(), _i64(), _i64()
+    check(_L.cc_dataflow_tables(n, b, ctypes.byref(nt), ctypes.byref(ns), ctypes.byref(nbk),
+                                None, None, None, None, None))
+    pq = np.zeros(2 * nt.value, dtype=np.int32)
+    needc = np.zeros(nt.value, dtype=np.uint32)
+    jsb = np.zeros(nt.value, dtype=np.int32)
+    needs = np.zeros(2 * ns.value, dtype=np.uint32)
+    K = np.zeros(nbk.value, dtype=np.uint32)
+    check(_L.cc_dataflow_tables(n, b, None, None, None, pq.ctypes.data, needc.ctypes.data,
+                                jsb.ctypes.data, needs.ctypes.data, K.ctypes.data))
+    return dict(tile_pq=pq.reshape(-1, 2), need_c=needc, jsbase=jsb, needs=needs.reshape(-1, 2),
+                K=K)
 
 
 def widen(src, dst, stream=None):

@@ -35,6 +35,28 @@ template <typename T> int launch_x_from_aty(int64_t, const double *, const T *, 
 template <typename T> int launch_to_lex(const Tile *, int64_t, int, int64_t, const T *, T *, hipStream_t);
 int launch_slots_to_lex(const Tile *, int64_t, int, int64_t, const int64_t *, int64_t, int64_t *, hipStream_t);
 
+struct DTile {
+    int32_t P, Q;
+    int64_t ybase;
+    int32_t jsbase;
+    uint32_t needC;
+};
+struct DataflowArgs {
+    const DTile *tiles;
+    int ntiles;
+    const uint32_t *needs;
+    const uint32_t *K;
+    uint32_t *cnt;
+    uint32_t *ctl;
+    uint32_t epoch;
+    uint64_t wait_ticks;
+};
+void build_dataflow_tables(int64_t n, int b, std::vector<DTile> &tiles, std::vector<uint32_t> &needs,
+                           std::vector<uint32_t> &K);
+template <typename T> int launch_sweep_dataflow(const DataflowArgs &, int, int, int64_t, T *, const T *, T *, hipStream_t);
+template <typename T> int dataflow_occupancy(int, int *);
+int launch_fill_u32(int64_t, uint32_t *, hipStream_t);
+
 }  // namespace ccp
 
 using namespace ccp;
@@ -55,6 +77,17 @@ struct cc_ctx {
     double *d_out = nullptr;    // final reduction, 14 doubles
     int *d_flag = nullptr;
     double *d_ax = nullptr;     // A'y accumulator, N_p doubles (allocated on first use)
+    // dataflow executor (built on first use)
+    DTile *d_dtiles = nullptr;
+    uint32_t *d_needs = nullptr;
+    uint32_t *d_K = nullptr;
+    uint32_t *d_cnt = nullptr;   // completed touches per block
+    uint32_t *d_ctl = nullptr;   // ticket counter, abort flag
+    int64_t nblocks = 0;
+    uint32_t kmax = 0;
+    uint32_t epoch = 0;
+    int df_grid = 0;
+    uint64_t wait_ticks = 0;
 };
 
 namespace {
@@ -113,6 +146,70 @@ int sweep_t(cc_ctx *c, T *x, T *f, T *y, T *yp, const T *g, const uint8_t *d, in
         if (rc) return rc;
         rc = launch_pair_pass<T>(num_pairs(c->n), x, f, yp, g, d, c->stream);
         if (rc) return rc;
+    }
+    return CC_OK;
+}
+
+int ensure_dataflow(cc_ctx *c) {
+    if (c->d_dtiles) return CC_OK;
+    if (c->b != 8 && c->b != 16 && c->b != 32)
+        return fail(CC_EINVAL, "the dataflow executor supports b = 8, 16 and 32");
+    std::vector<DTile> tiles;
+    std::vector<uint32_t> needs, K;
+    build_dataflow_tables(c->n, c->b, tiles, needs, K);
+    c->nblocks = int64_t(K.size());
+    c->kmax = 1;
+    for (uint32_t v : K) c->kmax = std::max(c->kmax, v);
+    if (hipMalloc(&c->d_dtiles, tiles.size() * sizeof(DTile)) != hipSuccess ||
+        hipMalloc(&c->d_needs, needs.size() * sizeof(uint32_t)) != hipSuccess ||
+        hipMalloc(&c->d_K, K.size() * sizeof(uint32_t)) != hipSuccess ||
+        hipMalloc(&c->d_cnt, K.size() * sizeof(uint32_t)) != hipSuccess ||
+        hipMalloc(&c->d_ctl, 4 * sizeof(uint32_t)) != hipSuccess)
+        return fail(CC_ENOMEM, "hipMalloc of dataflow tables failed");
+    CCP_HIP_CHECK(hipMemcpy(c->d_dtiles, tiles.data(), tiles.size() * sizeof(DTile), hipMemcpyHostToDevice));
+    CCP_HIP_CHECK(hipMemcpy(c->d_needs, needs.data(), needs.size() * sizeof(uint32_t), hipMemcpyHostToDevice));
+    CCP_HIP_CHECK(hipMemcpy(c->d_K, K.data(), K.size() * sizeof(uint32_t), hipMemcpyHostToDevice));
+    int rc = launch_fill_u32(c->nblocks, c->d_cnt, c->stream);
+    if (rc) return rc;
+    if ((rc = launch_fill_u32(4, c->d_ctl, c->stream))) return rc;
+    c->epoch = 0;
+    int per_cu = 0, dev = 0, cus = 0, khz = 0;
+    rc = (c->prec == CC_F64) ? dataflow_occupancy<double>(c->b, &per_cu) : dataflow_occupancy<float>(c->b, &per_cu);
+    if (rc) return rc;
+    CCP_HIP_CHECK(hipGetDevice(&dev));
+    CCP_HIP_CHECK(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+    CCP_HIP_CHECK(hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev));
+    if (per_cu < 1) return fail(CC_EHIP, "dataflow kernel does not fit on a compute unit");
+    c->df_grid = int(std::min<int64_t>(c->ntiles, int64_t(per_cu) * cus));
+    c->wait_ticks = uint64_t(khz > 0 ? khz : 100000) * 1000ull * 10ull;  // 10 s per wait
+    return CC_OK;
+}
+
+template <typename T>
+int sweep_dataflow_t(cc_ctx *c, T *x, T *f, T *y, T *yp, const T *g, const uint8_t *d,
+                     int nsweeps) {
+    int rc = ensure_dataflow(c);
+    if (rc) return rc;
+    for (int s = 0; s < nsweeps; ++s) {
+        if (uint64_t(c->epoch + 1) * c->kmax >= (1ull << 31)) {
+            if ((rc = launch_fill_u32(c->nblocks, c->d_cnt, c->stream))) return rc;
+            c->epoch = 0;
+        }
+        DataflowArgs a{c->d_dtiles, int(c->ntiles), c->d_needs, c->d_K, c->d_cnt, c->d_ctl,
+                       c->epoch, c->wait_ticks};
+        if ((rc = launch_sweep_dataflow<T>(a, c->df_grid, c->b, c->n, x, g, y, c->stream))) return rc;
+        c->epoch++;
+        if ((rc = launch_pair_pass<T>(num_pairs(c->n), x, f, yp, g, d, c->stream))) return rc;
+    }
+    uint32_t ctl[4];
+    CCP_HIP_CHECK(hipMemcpyAsync(ctl, c->d_ctl, sizeof(ctl), hipMemcpyDeviceToHost, c->stream));
+    CCP_HIP_CHECK(hipStreamSynchronize(c->stream));
+    if (ctl[1]) {
+        // a wait timed out: the state is incomplete; reset the counters
+        (void)launch_fill_u32(c->nblocks, c->d_cnt, c->stream);
+        (void)launch_fill_u32(4, c->d_ctl, c->stream);
+        c->epoch = 0;
+        return fail(CC_EHIP, "dataflow sweep aborted: a dependency wait timed out");
     }
     return CC_OK;
 }
@@ -248,6 +345,11 @@ int cc_destroy(cc_ctx *c) {
     (void)hipFree(c->d_out);
     (void)hipFree(c->d_flag);
     (void)hipFree(c->d_ax);
+    (void)hipFree(c->d_dtiles);
+    (void)hipFree(c->d_needs);
+    (void)hipFree(c->d_K);
+    (void)hipFree(c->d_cnt);
+    (void)hipFree(c->d_ctl);
     delete c;
     return CC_OK;
 }
@@ -292,7 +394,14 @@ int cc_sweep(cc_ctx *c, void *x, void *f, void *y, void *yp, const void *g, cons
         (rc = need(yp, "y_pair")) || (rc = need(g, "g")) || (rc = need(d, "d")))
         return rc;
     if (nsweeps < 0) return fail(CC_EINVAL, "nsweeps must be >= 0");
-    if (exec != CC_EXEC_ROUNDS) return fail(CC_EINVAL, "unknown executor");
+    if (exec != CC_EXEC_ROUNDS && exec != CC_EXEC_DATAFLOW) return fail(CC_EINVAL, "unknown executor");
+    if (exec == CC_EXEC_DATAFLOW) {
+        if (c->prec == CC_F64)
+            return sweep_dataflow_t<double>(c, (double *)x, (double *)f, (double *)y, (double *)yp,
+                                            (const double *)g, d, nsweeps);
+        return sweep_dataflow_t<float>(c, (float *)x, (float *)f, (float *)y, (float *)yp,
+                                       (const float *)g, d, nsweeps);
+    }
     if (c->prec == CC_F64)
         return sweep_t<double>(c, (double *)x, (double *)f, (double *)y, (double *)yp,
                                (const double *)g, d, nsweeps);
@@ -370,6 +479,26 @@ int cc_slots_to_lex(cc_ctx *c, const int64_t *slots, int64_t count, int64_t *out
     if (count < 0) return fail(CC_EINVAL, "count must be >= 0");
     if (count && ((rc = need(slots, "slots")) || (rc = need(out, "lex_out")))) return rc;
     return launch_slots_to_lex(c->d_tiles, c->ntiles, c->b, c->n, slots, count, out, c->stream);
+}
+
+int cc_dataflow_tables(int64_t n, int32_t b, int64_t *ntiles, int64_t *nsteps, int64_t *nblocks,
+                       int32_t *tile_pq, uint32_t *need_c, int32_t *jsbase, uint32_t *needs,
+                       uint32_t *K) {
+    if (n < 3 || b < 1 || b > 32) return fail(CC_EINVAL, "bad n or b");
+    std::vector<DTile> tiles;
+    std::vector<uint32_t> nd, kk;
+    build_dataflow_tables(n, b, tiles, nd, kk);
+    if (ntiles) *ntiles = int64_t(tiles.size());
+    if (nsteps) *nsteps = int64_t(nd.size() / 2);
+    if (nblocks) *nblocks = int64_t(kk.size());
+    for (size_t t = 0; t < tiles.size(); ++t) {
+        if (tile_pq) { tile_pq[2 * t] = tiles[t].P; tile_pq[2 * t + 1] = tiles[t].Q; }
+        if (need_c) need_c[t] = tiles[t].needC;
+        if (jsbase) jsbase[t] = tiles[t].jsbase;
+    }
+    if (needs) std::memcpy(needs, nd.data(), nd.size() * sizeof(uint32_t));
+    if (K) std::memcpy(K, kk.data(), kk.size() * sizeof(uint32_t));
+    return CC_OK;
 }
 
 int cc_widen(const float *src, double *dst, int64_t count, void *stream) {

@@ -35,6 +35,16 @@ __host__ __device__ __forceinline__ int mid_offset(int t, int il, int kl, int b)
     return (t - il - kl + 2 * b) % b;
 }
 
+// Order of the middle blocks J inside tile (P,Q): from Q down to P in the
+// rounds of the first double loop of Fig. 2 (P + Q < nb), from P up to Q in
+// those of the second.  Step m = 0..Q-P of the tile visits tile_J(m).  (The
+// paper leaves this order open; this one lets a tile release the block that
+// the next tile of its column waits for as early as possible.)
+__host__ __device__ __forceinline__ bool tile_desc(int P, int Q, int nb) { return P + Q < nb; }
+__host__ __device__ __forceinline__ int tile_J(int P, int Q, int m, bool desc) {
+    return desc ? Q - m : P + m;
+}
+
 // Thread-local error reporting for the C ABI.
 void set_error(const std::string &msg);
 int fail(int code, const std::string &msg);

@@ -1,0 +1,366 @@
+// dataflow.hip -- the sweep as one persistent launch whose tiles wait only
+// for the tile steps they depend on, instead of for whole rounds.
+//
+// The result of a sweep depends only on the order in which each variable is
+// updated.  The schedule of Sec. III fixes that order: a block of x (the
+// pairs with one index in block A and the other in block B) is touched by a
+// sequence of tile steps (tile, middle block J), in schedule order.  Here
+// every block X carries a counter of completed touches; a tile step waits
+// until the counters of the blocks it touches reach the number of touches
+// that precede it in schedule order, so every block sees exactly the
+// schedule's sequence of updates and the result equals the round-by-round
+// executor's bit for bit.  Tiles are handed out by a ticket counter in
+// schedule order, so the oldest unfinished tile never waits on an unfinished
+// one and the launch always makes progress.  Every wait is bounded by a
+// wall-clock limit; a timed-out wait raises an abort flag that every other
+// wait also checks, so the grid always drains.
+//
+// Memory ordering across the chip's L2 slices: a tile step writes its x
+// blocks back, then one thread releases (agent-scope release: L2 write-back)
+// before bumping the counters; a waiting tile acquires (agent-scope acquire:
+// L2 invalidate) before reading them.
+#include <vector>
+
+#include "common.hpp"
+#include "project.hpp"
+
+namespace ccp {
+
+struct DTile {
+    int32_t P, Q;
+    int64_t ybase;
+    int32_t jsbase;  // index of the tile's first step in the `needs` table
+    uint32_t needC;  // touches of block (P,Q) before this tile, per sweep
+};
+
+__host__ __device__ __forceinline__ int block_id(int A, int B) { return B * (B + 1) / 2 + A; }
+
+// ---------------------------------------------------------------------------
+// Host: dependency tables.  For tile step (tile, m) with middle block J the
+// blocks touched besides (P,Q) are A = (P,J) unless J = Q and B = (J,Q)
+// unless J = P; needs[2 s], needs[2 s + 1] count the touches of A and B that
+// precede the step in one sweep.  K[X] = touches of block X per sweep.
+// ---------------------------------------------------------------------------
+void build_dataflow_tables(int64_t n, int b, std::vector<DTile> &tiles,
+                           std::vector<uint32_t> &needs, std::vector<uint32_t> &K) {
+    const int nb = int((n + b - 1) / b);
+    const int64_t bb = int64_t(b) * b;
+    K.assign(size_t(nb) * (nb + 1) / 2, 0u);
+    tiles.clear();
+    needs.clear();
+    int64_t ybase = 0;
+    for (int r = 0; r < 2 * nb - 1; ++r) {
+        const int s = (r < nb) ? (nb - 1 - r) : r;
+        for (int P = 0; 2 * P <= s; ++P) {
+            const int Q = s - P;
+            if (Q >= nb) continue;
+            DTile t;
+            t.P = P;
+            t.Q = Q;
+            t.ybase = ybase;
+            t.jsbase = int32_t(needs.size() / 2);
+            t.needC = K[block_id(P, Q)];
+            const bool desc = tile_desc(P, Q, nb);
+            for (int m = 0; m <= Q - P; ++m) {
+                const int J = tile_J(P, Q, m, desc);
+                uint32_t na = 0, nbn = 0;
+                if (J != Q) na = K[block_id(P, J)]++;
+                if (J != P) nbn = K[block_id(J, Q)]++;
+                needs.push_back(na);
+                needs.push_back(nbn);
+            }
+            K[block_id(P, Q)] += uint32_t(Q - P + 1);
+            tiles.push_back(t);
+            ybase += int64_t(Q - P + 1) * b * 3 * bb;
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Device.
+// ---------------------------------------------------------------------------
+struct DataflowArgs {
+    const DTile *tiles;
+    int ntiles;
+    const uint32_t *needs;
+    const uint32_t *K;
+    uint32_t *cnt;       // completed touches per block (cumulative over epochs)
+    uint32_t *ctl;       // [0] ticket counter, [1] abort flag
+    uint32_t epoch;      // sweeps already run on these counters
+    uint64_t wait_ticks; // wall-clock limit of one wait
+};
+
+// Thread 0 only.  True once cnt >= need; false on time-out or abort.
+__device__ __forceinline__ bool wait_count(const uint32_t *cnt, uint32_t need, uint32_t *abort_flag,
+                                           uint64_t ticks) {
+    const uint64_t start = wall_clock64();
+    for (;;) {
+        const uint32_t v = __hip_atomic_load(cnt, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (int32_t(v - need) >= 0) return true;
+        if (__hip_atomic_load(abort_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) return false;
+        if (wall_clock64() - start > ticks) {
+            __hip_atomic_store(abort_flag, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            return false;
+        }
+        __builtin_amdgcn_s_sleep(2);
+    }
+}
+
+template <typename T, int B, int D>
+__global__ void __launch_bounds__(B * B)
+k_sweep_dataflow(DataflowArgs a, int64_t n, T *__restrict__ x, const T *__restrict__ g,
+                 T *__restrict__ y) {
+    constexpr int b = B;
+    constexpr int bb = B * B;
+    const int tid = threadIdx.x;
+    const int il = tid / b, kl = tid % b;
+    const int nn = int(n);
+    const int nb = (nn + b - 1) / b;
+
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    XG<T> *lds = reinterpret_cast<XG<T> *>(smem_raw);
+    XG<T> *const Cs = lds + 4 * bb;
+    __shared__ int s_tix, s_ok;
+
+    // Control structure: every `if (tid == 0)` region is closed by a
+    // barrier, and every value broadcast through LDS is made wave-uniform
+    // (readfirstlane) before it steers a branch.  Branches around barriers
+    // must be uniform; otherwise the compiler may merge thread-0 regions
+    // across a loop back-edge and split a wave's lanes between barriers.
+    if (tid == 0) s_tix = int(atomicAdd(&a.ctl[0], 1u));
+    __syncthreads();
+    for (;;) {
+        const int tix = __builtin_amdgcn_readfirstlane(s_tix);
+        if (tix >= a.ntiles) break;
+        const DTile tl = a.tiles[tix];
+        const int P = tl.P, Q = tl.Q;
+        const bool desc = tile_desc(P, Q, nb);
+        const int i = P * b + il, k = Q * b + kl;
+        const int idC = block_id(P, Q);
+
+        auto a_pair = [&](int J, int64_t &p) {
+            const int ii = P * b + il, jj = J * b + kl;
+            const bool ok = ii < jj && jj < nn;
+            p = ok ? pidx(ii, jj) : 0;
+            return ok;
+        };
+        auto b_pair = [&](int J, int64_t &p) {
+            const int jj = J * b + il, kk = Q * b + kl;
+            const bool ok = jj < kk && kk < nn;
+            p = ok ? pidx(jj, kk) : 0;
+            return ok;
+        };
+
+        // Duals are private to the tile: start their stream at once.
+        const int U = (Q - P + 1) * b;
+        T *const ylane = y + tl.ybase + tid;
+        const int64_t ystep = int64_t(3) * bb;
+        T yq[D][3];
+#pragma unroll
+        for (int d = 0; d < D; ++d) {
+            const T *src = ylane + int64_t(d < U ? d : U - 1) * ystep;
+            yq[d][0] = src[0];
+            yq[d][1] = src[bb];
+            yq[d][2] = src[2 * bb];
+        }
+
+        // Block (P,Q): wait for its earlier touches, then hold it.
+        if (tid == 0) {
+            const bool ok =
+                wait_count(&a.cnt[idC], a.epoch * a.K[idC] + tl.needC, &a.ctl[1], a.wait_ticks);
+            if (ok) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+            s_ok = ok;
+        }
+        __syncthreads();
+        if (!__builtin_amdgcn_readfirstlane(s_ok)) break;
+        const bool c_ok = (i < k) && (k < nn);
+        const int64_t pc = c_ok ? pidx(i, k) : 0;
+        {
+            const T cx = x[pc], cg = g[pc];
+            Cs[tid] = XG<T>{c_ok ? cx : T(0), c_ok ? cg : T(0)};
+        }
+
+        bool aborted = false;
+        for (int m = 0; m <= Q - P; ++m) {
+            const int J = tile_J(P, Q, m, desc);
+            const int idA = (J != Q) ? block_id(P, J) : -1;
+            const int idB = (J != P) ? block_id(J, Q) : -1;
+            XG<T> *const As = (J == Q) ? Cs : lds;
+            XG<T> *const Bs = (J == P) ? Cs : lds + 2 * bb;
+
+            if (tid == 0) {
+                const uint32_t *nd = a.needs + 2 * int64_t(tl.jsbase + m);
+                bool ok = true;
+                if (idA >= 0)
+                    ok = wait_count(&a.cnt[idA], a.epoch * a.K[idA] + nd[0], &a.ctl[1], a.wait_ticks);
+                if (ok && idB >= 0)
+                    ok = wait_count(&a.cnt[idB], a.epoch * a.K[idB] + nd[1], &a.ctl[1], a.wait_ticks);
+                if (ok && (idA >= 0 || idB >= 0)) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+                s_ok = ok;
+            }
+            __syncthreads();
+            if (!__builtin_amdgcn_readfirstlane(s_ok)) {
+                aborted = true;
+                break;
+            }
+            int64_t pa = 0, pbp = 0;
+            const bool aok = idA >= 0 && a_pair(J, pa);
+            const bool bok = idB >= 0 && b_pair(J, pbp);
+            if (idA >= 0) {
+                const T vx = x[pa], vg = g[pa];
+                As[tid] = XG<T>{aok ? vx : T(0), aok ? vg : T(0)};
+            }
+            if (idB >= 0) {
+                const T vx = x[pbp], vg = g[pbp];
+                Bs[tid] = XG<T>{bok ? vx : T(0), bok ? vg : T(0)};
+            }
+            lds_barrier();
+
+            auto qof = [&](int t) {
+                const int jl = mid_offset(t, il, kl, b);
+                const T s = (As[il * b + jl].g + Cs[tid].g) + Bs[jl * b + kl].g;
+                return recip<T>(s > T(0) ? s : T(1));
+            };
+            T qn = qof(0);
+            for (int t0 = 0; t0 < b; t0 += D) {
+#pragma unroll
+                for (int d = 0; d < D; ++d) {
+                    const int t = t0 + d;
+                    const int u = m * b + t;
+                    T y0 = yq[d][0], y1 = yq[d][1], y2 = yq[d][2];
+                    {
+                        const int un = u + D < U ? u + D : U - 1;
+                        const T *src = ylane + int64_t(un) * ystep;
+                        yq[d][0] = src[0];
+                        yq[d][1] = src[bb];
+                        yq[d][2] = src[2 * bb];
+                    }
+                    const T q = qn;
+                    if (t + 1 < b) qn = qof(t + 1);
+                    const int jl = mid_offset(t, il, kl, b);
+                    const int j = J * b + jl;
+                    if (i < j && j < k && k < nn) {
+                        XG<T> ea = As[il * b + jl];
+                        XG<T> eb = Bs[jl * b + kl];
+                        XG<T> ec = Cs[tid];
+                        T xa = ea.x, xb = eb.x, xc = ec.x;
+                        project(xa, xc, xb, ea.g, ec.g, eb.g, q, y0);
+                        project(xc, xa, xb, ec.g, ea.g, eb.g, q, y1);
+                        project(xb, xa, xc, eb.g, ea.g, ec.g, q, y2);
+                        As[il * b + jl].x = xa;
+                        Bs[jl * b + kl].x = xb;
+                        Cs[tid].x = xc;
+                    }
+                    T *dst = ylane + int64_t(u) * ystep;
+                    dst[0] = y0;
+                    dst[bb] = y1;
+                    dst[2 * bb] = y2;
+                    lds_barrier();
+                }
+            }
+
+            // Publish this step's (P,J) and (J,Q) blocks.
+            if (aok) x[pa] = As[tid].x;
+            if (bok) x[pbp] = Bs[tid].x;
+            __syncthreads();
+            if (tid == 0) {
+                if (idA >= 0) __hip_atomic_fetch_add(&a.cnt[idA], 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+                if (idB >= 0) __hip_atomic_fetch_add(&a.cnt[idB], 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+            }
+            __syncthreads();
+        }
+        if (aborted) break;
+
+        // Publish block (P,Q), then take the next ticket.
+        if (c_ok) x[pc] = Cs[tid].x;
+        __syncthreads();
+        if (tid == 0) {
+            __hip_atomic_fetch_add(&a.cnt[idC], uint32_t(Q - P + 1), __ATOMIC_RELEASE,
+                                   __HIP_MEMORY_SCOPE_AGENT);
+            s_tix = int(atomicAdd(&a.ctl[0], 1u));
+        }
+        __syncthreads();
+    }
+}
+
+__global__ void k_dataflow_reset(uint32_t *ctl) {
+    if (threadIdx.x == 0) {
+        ctl[0] = 0u;
+    }
+}
+
+__global__ void k_fill_u32(int64_t count, uint32_t *a) {
+    for (int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; e < count;
+         e += int64_t(gridDim.x) * blockDim.x)
+        a[e] = 0u;
+}
+
+template <typename T>
+size_t dataflow_lds_bytes(int b) {
+    return size_t(5) * b * b * sizeof(XG<T>);
+}
+
+template <typename T, int B, int D>
+static int launch_df_t(const DataflowArgs &a, int grid, int64_t n, T *x, const T *g, T *y,
+                       hipStream_t s) {
+    const size_t lds = dataflow_lds_bytes<T>(B);
+    hipLaunchKernelGGL(k_dataflow_reset, dim3(1), dim3(64), 0, s, a.ctl);
+    CCP_LAUNCH_CHECK("k_dataflow_reset");
+    hipLaunchKernelGGL((k_sweep_dataflow<T, B, D>), dim3(grid), dim3(B * B), lds, s, a, n, x, g, y);
+    CCP_LAUNCH_CHECK("k_sweep_dataflow");
+    return CC_OK;
+}
+
+template <typename T>
+int launch_sweep_dataflow(const DataflowArgs &a, int grid, int b, int64_t n, T *x, const T *g,
+                          T *y, hipStream_t s) {
+    switch (b) {
+        case 8: return launch_df_t<T, 8, 4>(a, grid, n, x, g, y, s);
+        case 16: return launch_df_t<T, 16, 8>(a, grid, n, x, g, y, s);
+        case 32: return launch_df_t<T, 32, 4>(a, grid, n, x, g, y, s);
+        default: return fail(CC_EINVAL, "the dataflow executor supports b = 8, 16, 32");
+    }
+}
+
+template <typename T>
+int dataflow_occupancy(int b, int *blocks_per_cu) {
+    hipError_t e = hipSuccess;
+    const int lds = int(dataflow_lds_bytes<T>(b));
+    switch (b) {
+        case 8:
+            e = hipFuncSetAttribute((const void *)k_sweep_dataflow<T, 8, 4>, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+            if (e == hipSuccess) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, k_sweep_dataflow<T, 8, 4>, 64, lds);
+            break;
+        case 16:
+            e = hipFuncSetAttribute((const void *)k_sweep_dataflow<T, 16, 8>, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+            if (e == hipSuccess) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, k_sweep_dataflow<T, 16, 8>, 256, lds);
+            break;
+        case 32:
+            e = hipFuncSetAttribute((const void *)k_sweep_dataflow<T, 32, 4>, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+            if (e == hipSuccess) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, k_sweep_dataflow<T, 32, 4>, 1024, lds);
+            break;
+        default:
+            *blocks_per_cu = 0;
+            return CC_OK;
+    }
+    if (e != hipSuccess) return fail(CC_EHIP, std::string("dataflow occupancy: ") + hipGetErrorString(e));
+    return CC_OK;
+}
+
+int launch_fill_u32(int64_t count, uint32_t *a, hipStream_t s) {
+    if (count <= 0) return CC_OK;
+    int64_t grid = (count + 255) / 256;
+    if (grid > 65536) grid = 65536;
+    hipLaunchKernelGGL(k_fill_u32, dim3(unsigned(grid)), dim3(256), 0, s, count, a);
+    CCP_LAUNCH_CHECK("k_fill_u32");
+    return CC_OK;
+}
+
+template int launch_sweep_dataflow<double>(const DataflowArgs &, int, int, int64_t, double *,
+                                           const double *, double *, hipStream_t);
+template int launch_sweep_dataflow<float>(const DataflowArgs &, int, int, int64_t, float *,
+                                          const float *, float *, hipStream_t);
+template int dataflow_occupancy<double>(int, int *);
+template int dataflow_occupancy<float>(int, int *);
+
+}  // namespace ccp

@@ -77,7 +77,9 @@ k_metric_resid(const Tile *__restrict__ tiles, int b_rt, int64_t n, const T *__r
         Cs[tid] = ok ? double(x[pidx(i, k)]) : 0.0;
     }
     double vmax = 0.0, cs_sum = 0.0, cs_max = 0.0, bad = 0.0;
-    for (int J = P; J <= Q; ++J) {
+    const bool desc = tile_desc(P, Q, int((n + b - 1) / b));
+    for (int m = 0; m <= Q - P; ++m) {
+        const int J = tile_J(P, Q, m, desc);
         if (J != Q) {
             const int64_t ii = int64_t(P) * b + il, jj = int64_t(J) * b + kl;
             As[tid] = (ii < jj && jj < n) ? double(x[pidx(ii, jj)]) : 0.0;
@@ -100,7 +102,7 @@ k_metric_resid(const Tile *__restrict__ tiles, int b_rt, int64_t n, const T *__r
                 vmax = fmax(vmax, fmax(-s0, fmax(-s1, -s2)));
                 if (!finite(s0 + s1 + s2)) bad = 1.0;
                 if (y) {
-                    const int64_t u = int64_t(J - P) * b + t;
+                    const int64_t u = int64_t(m) * b + t;
                     const T *src = y + tl.ybase + u * 3 * bb + tid;
                     const double c0 = double(src[0]) * s0, c1 = double(src[bb]) * s1,
                                  c2 = double(src[2 * bb]) * s2;
@@ -214,7 +216,9 @@ k_aty_round(const Tile *__restrict__ tiles, int b_rt, int64_t n, const T *__rest
     const int64_t i = int64_t(P) * b + il, k = int64_t(Q) * b + kl;
     const bool c_ok = i < k && k < n;
     Cs[tid] = c_ok ? ax[pidx(i, k)] : 0.0;
-    for (int J = P; J <= Q; ++J) {
+    const bool desc = tile_desc(P, Q, int((n + b - 1) / b));
+    for (int m = 0; m <= Q - P; ++m) {
+        const int J = tile_J(P, Q, m, desc);
         int64_t pa = -1, pb = -1;
         if (J != Q) {
             const int64_t ii = int64_t(P) * b + il, jj = int64_t(J) * b + kl;
@@ -233,7 +237,7 @@ k_aty_round(const Tile *__restrict__ tiles, int b_rt, int64_t n, const T *__rest
             const int jl = mid_offset(t, il, kl, b);
             const int64_t j = int64_t(J) * b + jl;
             if (i < j && j < k && k < n) {
-                const int64_t u = int64_t(J - P) * b + t;
+                const int64_t u = int64_t(m) * b + t;
                 const T *src = y + tl.ybase + u * 3 * bb + tid;
                 const double y0 = double(src[0]), y1 = double(src[bb]), y2 = double(src[2 * bb]);
                 Ab[il * b + jl] += (y0 - y1) - y2;  // pair (i,j)
@@ -276,11 +280,13 @@ k_to_lex(const Tile *__restrict__ tiles, int b, int64_t n, const T *__restrict__
     const int il = tid / b, kl = tid - (tid / b) * b;
     const Tile tl = tiles[blockIdx.x];
     const int64_t i = int64_t(tl.P) * b + il, k = int64_t(tl.Q) * b + kl;
-    for (int J = tl.P; J <= tl.Q; ++J)
+    const bool desc = tile_desc(tl.P, tl.Q, int((n + b - 1) / b));
+    for (int m = 0; m <= tl.Q - tl.P; ++m)
         for (int t = 0; t < b; ++t) {
+            const int J = tile_J(tl.P, tl.Q, m, desc);
             const int64_t j = int64_t(J) * b + mid_offset(t, il, kl, b);
             if (i < j && j < k && k < n) {
-                const int64_t u = int64_t(J - tl.P) * b + t;
+                const int64_t u = int64_t(m) * b + t;
                 const T *src = y + tl.ybase + u * 3 * bb + tid;
                 T *dst = ylex + 3 * tidx(i, j, k);
                 dst[0] = src[0];
@@ -307,10 +313,12 @@ __global__ void k_slots_to_lex(const Tile *__restrict__ tiles, int64_t ntiles, i
         const int64_t u = off / (3 * bb), rem = off - u * 3 * bb;
         const int o = int(rem / bb), lane = int(rem - (rem / bb) * bb);
         const int il = lane / b, kl = lane % b;
-        const int J = tl.P + int(u / b), t = int(u % b);
+        const int mm = int(u / b), t = int(u % b);
+        const bool desc = tile_desc(tl.P, tl.Q, int((n + b - 1) / b));
+        const int J = tile_J(tl.P, tl.Q, mm, desc);
         const int64_t i = int64_t(tl.P) * b + il, k = int64_t(tl.Q) * b + kl;
         const int64_t j = int64_t(J) * b + mid_offset(t, il, kl, b);
-        const bool ok = s >= 0 && J <= tl.Q && i < j && j < k && k < n;
+        const bool ok = s >= 0 && mm <= tl.Q - tl.P && i < j && j < k && k < n;
         out[e] = ok ? 3 * tidx(i, j, k) + o : -1;
     }
 }

@@ -28,48 +28,19 @@
 // J); the duals stream through a register ring D sub-steps deep.  Each
 // sub-step reads and writes three contiguous vectors of b*b duals.
 #include "common.hpp"
+#include "project.hpp"
 
 namespace ccp {
 
-template <typename T>
-struct XG {
-    T x;  // distance variable x_p
-    T g;  // gamma / w_p
-};
-
-__device__ __forceinline__ void lds_barrier() {
-    // Orders LDS only: global loads in flight (the dual prefetch) stay in
-    // flight across the barrier.
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
-    __builtin_amdgcn_s_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
-}
-
-template <typename T>
-__device__ __forceinline__ T recip(T s) {
-    return T(1) / s;
-}
-template <>
-__device__ __forceinline__ float recip<float>(float s) {
-    return __builtin_amdgcn_rcpf(s);
-}
-
-// One row of Algorithm 1 (correction + projection + dual update, merged).
-template <typename T>
-__device__ __forceinline__ void project(T &xL, T &xS1, T &xS2, T gL, T gS1, T gS2, T q,
-                                        T &y) {
-    T delta = (xL - xS1) - xS2;
-    T th = fma(delta, q, y);
-    th = th > T(0) ? th : T(0);
-    T dlt = th - y;
-    xL = fma(-dlt, gL, xL);
-    xS1 = fma(dlt, gS1, xS1);
-    xS2 = fma(dlt, gS2, xS2);
-    y = th;
-}
-
 // Metric rounds: one workgroup of b*b threads per tile of the round.
 // B: compile-time tile size (0 = runtime b), D: dual prefetch depth (D | b).
+//
+// Every thread issues its dual loads and stores unconditionally, at an
+// address inside its tile's segment (lanes without a triplet touch their
+// own padding slot and write back what they read), so the hardware's
+// in-order load counter lets each sub-step wait only for the load it needs
+// and the prefetch ring stays in flight.  1/(g_ij + g_ik + g_jk) does not
+// depend on x, so it is computed one sub-step ahead.
 template <typename T, int B, int D>
 __global__ void __launch_bounds__(B ? B * B : 1024)
 k_sweep_round(const Tile *__restrict__ tiles, int b_rt, int64_t n, T *__restrict__ x,
@@ -80,118 +51,111 @@ k_sweep_round(const Tile *__restrict__ tiles, int b_rt, int64_t n, T *__restrict
     const int il = tid / b, kl = tid - (tid / b) * b;
     const Tile tl = tiles[blockIdx.x];
     const int P = tl.P, Q = tl.Q;
-    const int64_t ybase = tl.ybase;
+    const int nn = int(n);
 
     extern __shared__ __align__(16) unsigned char smem_raw[];
     XG<T> *lds = reinterpret_cast<XG<T> *>(smem_raw);
     XG<T> *const Cs = lds + 4 * bb;
 
-    const int64_t i = int64_t(P) * b + il;
-    const int64_t k = int64_t(Q) * b + kl;
+    const int i = P * b + il;
+    const int k = Q * b + kl;
 
     // (P,Q) block: pair (i,k) of this lane.
+    const bool c_ok = (i < k) && (k < nn);
+    const int64_t pc = c_ok ? pidx(i, k) : 0;
     {
-        const bool ok = (i < k) && (k < n);
-        XG<T> v{T(0), T(0)};
-        if (ok) {
-            const int64_t p = pidx(i, k);
-            v.x = x[p];
-            v.g = g[p];
-        }
-        Cs[tid] = v;
+        const T cx = x[pc], cg = g[pc];
+        Cs[tid] = XG<T>{c_ok ? cx : T(0), c_ok ? cg : T(0)};
     }
 
     // Element (il, kl) of the (P,J) and (J,Q) blocks, fetched and written
-    // back by this thread.
+    // back by this thread (pair 0 stands in for missing pairs).
     auto a_pair = [&](int J, int64_t &p) {
-        const int64_t ii = int64_t(P) * b + il, jj = int64_t(J) * b + kl;
-        const bool ok = ii < jj && jj < n;
+        const int ii = P * b + il, jj = J * b + kl;
+        const bool ok = ii < jj && jj < nn;
         p = ok ? pidx(ii, jj) : 0;
         return ok;
     };
     auto b_pair = [&](int J, int64_t &p) {
-        const int64_t jj = int64_t(J) * b + il, kk = int64_t(Q) * b + kl;
-        const bool ok = jj < kk && kk < n;
+        const int jj = J * b + il, kk = Q * b + kl;
+        const bool ok = jj < kk && kk < nn;
         p = ok ? pidx(jj, kk) : 0;
         return ok;
     };
 
-    // Linear sub-step index u = (J - P) * b + t over the tile; the tile's
-    // duals for step u are y[ybase + u*3*bb + o*bb + tid].
-    const int64_t U = int64_t(Q - P + 1) * b;
-    auto step_valid = [&](int64_t u) {
-        const int J = P + int(u / b);
-        const int t = int(u - int64_t(u / b) * b);
-        const int64_t j = int64_t(J) * b + mid_offset(t, il, kl, b);
-        return (u < U) && (i < j) && (j < k) && (k < n);
-    };
+    // Linear sub-step u = m * b + t (m-th middle block of the tile, see
+    // tile_J); the duals of step u live at y[ybase + u*3*bb + o*bb + tid].
+    const int U = (Q - P + 1) * b;
+    const bool desc = tile_desc(P, Q, (nn + b - 1) / b);
+    T *const ylane = y + tl.ybase + tid;
+    const int64_t ystep = int64_t(3) * bb;
 
     T yq[D][3];
 #pragma unroll
     for (int d = 0; d < D; ++d) {
-        yq[d][0] = yq[d][1] = yq[d][2] = T(0);
-        if (step_valid(d)) {
-            const T *src = y + ybase + int64_t(d) * 3 * bb + tid;
-            yq[d][0] = src[0];
-            yq[d][1] = src[bb];
-            yq[d][2] = src[2 * bb];
-        }
+        const T *src = ylane + int64_t(d < U ? d : U - 1) * ystep;
+        yq[d][0] = src[0];
+        yq[d][1] = src[bb];
+        yq[d][2] = src[2 * bb];
     }
 
-    // Prologue: (P,J) and (J,Q) blocks of the first J into buffer 0.
-    {
+    // Prologue: stage the first middle block's (P,J) / (J,Q) block into
+    // buffer 0.  J = P: A is block (P,P), B aliases C.  J = Q: A aliases C,
+    // B is block (Q,Q).
+    if (P != Q) {
         int64_t p;
-        if (P != Q) {  // J = P: A is block (P,P), B aliases C
-            XG<T> v{T(0), T(0)};
-            if (a_pair(P, p)) { v.x = x[p]; v.g = g[p]; }
-            lds[tid] = v;
-        }
+        const bool ok = desc ? b_pair(Q, p) : a_pair(P, p);
+        const T vx = x[p], vg = g[p];
+        lds[(desc ? 2 : 0) * bb + tid] = XG<T>{ok ? vx : T(0), ok ? vg : T(0)};
     }
     lds_barrier();
 
-    for (int J = P; J <= Q; ++J) {
-        const int cur = (J - P) & 1;
+    for (int m = 0; m <= Q - P; ++m) {
+        const int J = tile_J(P, Q, m, desc);
+        const int cur = m & 1;
         XG<T> *const As = (J == Q) ? Cs : lds + cur * bb;
         XG<T> *const Bs = (J == P) ? Cs : lds + (2 + cur) * bb;
 
-        // Fetch next J's blocks into registers; they land during this J.
-        const int Jn = J + 1;
-        XG<T> na{T(0), T(0)}, nbv{T(0), T(0)};
-        bool na_ok = false, nb_ok = false;
-        int64_t pa = 0, pb = 0;
-        if (Jn <= Q) {
-            if (Jn != Q) {
-                na_ok = a_pair(Jn, pa);
-                if (na_ok) { na.x = x[pa]; na.g = g[pa]; }
-            }
-            nb_ok = b_pair(Jn, pb);  // Jn > P always
-            if (nb_ok) { nbv.x = x[pb]; nbv.g = g[pb]; }
-        }
+        // Next middle block: fetched now, staged into LDS after this one.
+        const bool more = m < Q - P;
+        const int Jn = more ? tile_J(P, Q, m + 1, desc) : J;
+        int64_t pa, pb;
+        const bool na_ok = more && Jn != Q && a_pair(Jn, pa);
+        const bool nb_ok = more && Jn != P && b_pair(Jn, pb);
+        if (!na_ok) pa = 0;
+        if (!nb_ok) pb = 0;
+        const T nax = x[pa], nag = g[pa], nbx = x[pb], nbg = g[pb];
+
+        auto qof = [&](int t) {
+            const int jl = mid_offset(t, il, kl, b);
+            const T s = (As[il * b + jl].g + Cs[tid].g) + Bs[jl * b + kl].g;
+            return recip<T>(s > T(0) ? s : T(1));
+        };
+        T qn = qof(0);
 
         for (int t0 = 0; t0 < b; t0 += D) {
 #pragma unroll
             for (int d = 0; d < D; ++d) {
                 const int t = t0 + d;
-                const int64_t u = int64_t(J - P) * b + t;
+                const int u = m * b + t;
                 T y0 = yq[d][0], y1 = yq[d][1], y2 = yq[d][2];
                 // prefetch step u + D into the freed ring slot
                 {
-                    const int64_t un = u + D;
-                    yq[d][0] = yq[d][1] = yq[d][2] = T(0);
-                    if (step_valid(un)) {
-                        const T *src = y + ybase + un * 3 * bb + tid;
-                        yq[d][0] = src[0];
-                        yq[d][1] = src[bb];
-                        yq[d][2] = src[2 * bb];
-                    }
+                    const int un = u + D < U ? u + D : U - 1;
+                    const T *src = ylane + int64_t(un) * ystep;
+                    yq[d][0] = src[0];
+                    yq[d][1] = src[bb];
+                    yq[d][2] = src[2 * bb];
                 }
+                const T q = qn;
+                if (t + 1 < b) qn = qof(t + 1);
                 const int jl = mid_offset(t, il, kl, b);
-                const int64_t j = int64_t(J) * b + jl;
-                if (i < j && j < k && k < n) {
+                const int j = J * b + jl;
+                const bool ok = i < j && j < k && k < nn;
+                if (ok) {
                     XG<T> ea = As[il * b + jl];  // pair (i,j)
                     XG<T> eb = Bs[jl * b + kl];  // pair (j,k)
                     XG<T> ec = Cs[tid];          // pair (i,k)
-                    const T q = recip<T>((ea.g + ec.g) + eb.g);
                     T xa = ea.x, xb = eb.x, xc = ec.x;
                     project(xa, xc, xb, ea.g, ec.g, eb.g, q, y0);  // x_ij <= x_ik + x_jk
                     project(xc, xa, xb, ec.g, ea.g, eb.g, q, y1);  // x_ik <= x_ij + x_jk
@@ -199,35 +163,30 @@ k_sweep_round(const Tile *__restrict__ tiles, int b_rt, int64_t n, T *__restrict
                     As[il * b + jl].x = xa;
                     Bs[jl * b + kl].x = xb;
                     Cs[tid].x = xc;
-                    T *dst = y + ybase + u * 3 * bb + tid;
-                    dst[0] = y0;
-                    dst[bb] = y1;
-                    dst[2 * bb] = y2;
                 }
+                T *dst = ylane + int64_t(u) * ystep;
+                dst[0] = y0;
+                dst[bb] = y1;
+                dst[2 * bb] = y2;
                 lds_barrier();
             }
         }
 
-        // Write back this J's (P,J) and (J,Q) blocks; stage the next J's.
+        // Write back this step's (P,J) and (J,Q) blocks; stage the next.
         {
             int64_t p;
             if (As != Cs && a_pair(J, p)) x[p] = As[tid].x;
             if (Bs != Cs && b_pair(J, p)) x[p] = Bs[tid].x;
-            if (Jn <= Q) {
+            if (more) {
                 const int nxt = cur ^ 1;
-                if (Jn != Q) lds[nxt * bb + tid] = na;
-                lds[(2 + nxt) * bb + tid] = nbv;
+                if (Jn != Q) lds[nxt * bb + tid] = XG<T>{na_ok ? nax : T(0), na_ok ? nag : T(0)};
+                if (Jn != P) lds[(2 + nxt) * bb + tid] = XG<T>{nb_ok ? nbx : T(0), nb_ok ? nbg : T(0)};
             }
         }
-        (void)na_ok;
-        (void)nb_ok;
         lds_barrier();
     }
 
-    {
-        const bool ok = (i < k) && (k < n);
-        if (ok) x[pidx(i, k)] = Cs[tid].x;
-    }
+    if (c_ok) x[pc] = Cs[tid].x;
 }
 
 // Pair pass: rows x - f <= d and -x - f <= -d of every pair, in that order.

@@ -24,6 +24,15 @@ def rel_err(a, ref):
 TOL64 = 1e-10   # FP64 GPU vs FP64 oracle, relative to max(1, |ref|_inf)
 
 
+def nonzero_positions(t, chunk=1 << 28):
+    """Flat indices of the nonzeros of a 1-D tensor, in chunks (torch's
+    nonzero fails on tensors with more than 2^32 elements)."""
+    parts = []
+    for s in range(0, t.numel(), chunk):
+        parts.append(torch.nonzero(t[s:s + chunk]).flatten() + s)
+    return torch.cat(parts)
+
+
 def compare_state(gs, os_, tol, what=""):
     x, f = gs.x.cpu().numpy(), gs.f.cpu().numpy()
     yp = gs.y_pair.cpu().numpy()
@@ -104,16 +113,24 @@ def test_prefix_parity_large(n, b, rounds):
     assert rel_err(g.x.cpu().numpy(), x) <= TOL64
     assert rel_err(g.f.cpu().numpy(), f) <= TOL64
     assert rel_err(g.y_pair.cpu().numpy(), yp) <= TOL64
-    nz = torch.nonzero(g.y).flatten()
+    nz = nonzero_positions(g.y)
     lex = torch.empty_like(nz)
     g.ctx.slots_to_lex(nz, lex)
     lex = lex.cpu().numpy()
     assert (lex >= 0).all()
     vals = g.y[nz].cpu().numpy()
-    order = np.argsort(lex)
-    ref = np.argsort(3 * t + o)
-    assert np.array_equal(lex[order], (3 * t + o)[ref])
-    assert rel_err(vals[order], y[ref]) <= TOL64
+    # Compare as dense vectors over the union of nonzero positions: a dual
+    # whose row sits within rounding of zero may be exactly zero on one side
+    # and a few ulps on the other.
+    gpos, opos = lex, 3 * t + o.astype(np.int64)
+    union = np.union1d(gpos, opos)
+    gv = np.zeros(union.size)
+    ov = np.zeros(union.size)
+    gv[np.searchsorted(union, gpos)] = vals
+    ov[np.searchsorted(union, opos)] = y
+    assert rel_err(gv, ov) <= TOL64
+    only = np.setxor1d(gpos, opos)
+    assert only.size <= 1e-3 * max(1, opos.size)
     print(f"prefix n={n}: {len(t)} nonzero duals", flush=True)
 
 
@@ -191,3 +208,32 @@ def test_duals_nonnegative_and_stationary():
     assert float(g.y.min()) >= 0.0 and float(g.y_pair.min()) >= 0.0
     r = g.residuals()
     assert r["stat_resid"] < 1e-12
+
+
+# --------------------------------------------------------------------------
+# Dataflow executor: same updates in the same order per variable, so the
+# result must equal the round-by-round executor bit for bit.
+# --------------------------------------------------------------------------
+@pytest.mark.parametrize("n,b,prec,K", [(60, 8, "f64", 3), (61, 8, "f64", 2), (100, 16, "f64", 3),
+                                        (130, 32, "f64", 2), (200, 16, "f32", 3),
+                                        (500, 16, "f64", 2)])
+def test_dataflow_equals_rounds(n, b, prec, K):
+    inst = I.workload(1) if n == 500 else I.random_signed(n, seed=n, gamma=2.0, weighted=True)
+    print(f"dataflow n={n} b={b} {prec} K={K}", flush=True)
+    r = C.Solver.from_instance(inst, b=b, prec=prec)
+    d = C.Solver.from_instance(inst, b=b, prec=prec)
+    r.sweep(K, C.CC_EXEC_ROUNDS)
+    d.sweep(K, C.CC_EXEC_DATAFLOW)
+    torch.cuda.synchronize()
+    for name in ("x", "f", "y", "y_pair"):
+        a, bb = getattr(r, name), getattr(d, name)
+        assert torch.equal(a, bb), (name, float((a - bb).abs().max()))
+
+
+def test_dataflow_parity_oracle():
+    inst = I.random_signed(70, seed=4, gamma=1.5, weighted=True)
+    g = C.Solver.from_instance(inst, b=8)
+    o = oracle.State.from_instance(inst)
+    g.sweep(6, C.CC_EXEC_DATAFLOW)
+    o.sweep(6, b=8)
+    compare_state(g, o, TOL64, "dataflow n=70 K=6")
