@@ -42,6 +42,25 @@ def metric_sweep_bytes(inst, elem):
     return 2 * inst.num_constraints * elem + inst.num_pairs * 3 * elem
 
 
+def recorded_traffic(kernel, inst, b, prec):
+    """HBM bytes per launch from a committed PMC record, if the kernel's
+    sources are unchanged since the counters were taken; else None."""
+    import hashlib
+    wl = {"sbm_n500_k10": "sbm_n500"}.get(inst.name, inst.name)
+    path = os.path.join(ROOT, "profiles", f"{kernel}_{wl}_{prec}.traffic.json")
+    if not os.path.exists(path):
+        return None
+    rec = json.load(open(path))
+    if rec.get("b") != b or rec.get("workload") != inst.name:
+        return None
+    h = hashlib.sha256()
+    for s in rec["sources"]:
+        h.update(open(os.path.join(ROOT, s), "rb").read())
+    if h.hexdigest() != rec["source_sha256"]:
+        return None
+    return rec["traffic_bytes_per_launch"]
+
+
 def cpu_baseline(inst, b, budget_s):
     import oracle
     s = oracle.State.from_instance(inst)
@@ -70,6 +89,9 @@ def main():
     ap.add_argument("--cpu-budget", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-solve", action="store_true")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MiB",
+                    help="after the timed region, copy a buffer of this size (reference "
+                         "kernel for HBM byte counters)")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -99,17 +121,13 @@ def main():
     ev_m1 = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps)]
     t0 = time.perf_counter()
     for s in range(args.steps):
-        if executor == C.CC_EXEC_ROUNDS:
-            ev_m0[s].record(stream)
-            g.sweep_rounds(0, g.ctx.rounds)
-            ev_m1[s].record(stream)
-            g.pair_pass()
-            g.sweeps += 1
-        else:
-            ev_m0[s].record(stream)
-            g.sweep(1, executor)
-            ev_m1[s].record(stream)
+        ev_m0[s].record(stream)
+        g.sweep_metric(executor)
+        ev_m1[s].record(stream)
+        g.pair_pass()
+        g.sweeps += 1
     torch.cuda.synchronize()
+    g.status()
     wall = time.perf_counter() - t0
     metric_ms = sum(a.elapsed_time(b) for a, b in zip(ev_m0, ev_m1))
     launches_per_sweep = g.ctx.rounds if executor == C.CC_EXEC_ROUNDS else 1
@@ -122,6 +140,7 @@ def main():
         f"{metric_ms/args.steps:.3f} ms/sweep, {achieved:.1f} GB/s, viol {r['max_viol_metric']:.2e}")
 
     value = inst.num_constraints * args.steps / wall
+    kernel_name = "k_sweep_round" if executor == C.CC_EXEC_ROUNDS else "k_sweep_dataflow"
     out = {
         "metric": "triplet-projections/s + time-to-1e-4 max violation, FP64 plain vs FP32+MLP warm start",
         "value": value,
@@ -135,12 +154,22 @@ def main():
                    "executor": args.exec, "step": "one full sweep (metric rounds + pair pass)"},
         "triplets_per_s": value / 3,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                     "kernel": "k_sweep_round" if executor == C.CC_EXEC_ROUNDS else "k_sweep_dataflow",
+                     "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": recorded_traffic(kernel_name, inst, args.b, args.prec),
+                     "kernel": kernel_name,
                      "avg_launch_us": avg_launch_s * 1e6,
                      "algorithmic_bytes_per_launch": bytes_sweep / launches_per_sweep,
                      "launches_per_step": launches_per_sweep},
     }
+
+    if args.copy_calibration:
+        src = torch.ones(args.copy_calibration << 17, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            torch.add(src, 1.0, out=dst)      # reads and writes the stated bytes once
+        torch.cuda.synchronize()
+        out["copy_calibration_bytes"] = {"read": src.numel() * 8, "write": dst.numel() * 8}
+        del src, dst
 
     if not args.no_solve:
         g2 = C.Solver.from_instance(inst, b=args.b, prec=args.prec)

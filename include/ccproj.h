@@ -136,11 +136,21 @@ int cc_init_cold(cc_ctx *ctx, void *x, void *f, void *y, void *y_pair, double ga
  * launch per round; CC_EXEC_DATAFLOW, for b = 8, 16, 32: one persistent
  * launch per sweep whose tile steps wait only for the earlier steps that
  * touch the same blocks of x).  Both executors apply the updates of every
- * variable in the same order and give identical results.  A dataflow wait
- * longer than 10 s aborts the sweep with CC_EHIP (the state is then
- * incomplete); no wait can block forever. */
+ * variable in the same order and give identical results.  Enqueues only
+ * (no host synchronisation).  A dataflow wait longer than 10 s aborts the
+ * sweep (the state is then incomplete); no wait can block forever.  Such an
+ * abort is reported as CC_EHIP by the next cc_status or cc_residuals call
+ * on the context. */
 int cc_sweep(cc_ctx *ctx, void *x, void *f, void *y, void *y_pair, const void *g,
              const uint8_t *d, int32_t nsweeps, int32_t exec);
+
+/* One sweep's metric rounds only (no pair pass) with the given executor;
+ * enqueues only. */
+int cc_sweep_metric(cc_ctx *ctx, void *x, void *y, const void *g, int32_t exec);
+
+/* Synchronise the context's stream and report a dataflow sweep aborted
+ * since the last check (CC_EHIP), else CC_OK. */
+int cc_status(cc_ctx *ctx);
 
 /* Metric rounds [first_round, first_round + nrounds) of one sweep, without
  * the pair pass (for checks against a prefix of the serial order). */

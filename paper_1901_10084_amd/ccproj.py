@@ -64,6 +64,8 @@ _sig("cc_prepare", ctypes.c_int, _p, _p, _dbl, _p)
 _sig("cc_init_cold", ctypes.c_int, _p, _p, _p, _p, _p, _dbl)
 _sig("cc_sweep", ctypes.c_int, _p, _p, _p, _p, _p, _p, _p, _i32, _i32)
 _sig("cc_sweep_rounds", ctypes.c_int, _p, _p, _p, _p, _i32, _i32)
+_sig("cc_sweep_metric", ctypes.c_int, _p, _p, _p, _p, _i32)
+_sig("cc_status", ctypes.c_int, _p)
 _sig("cc_pair_pass", ctypes.c_int, _p, _p, _p, _p, _p, _p)
 _sig("cc_residuals", ctypes.c_int, _p, _p, _p, _p, _p, _p, _p, _dbl, _i32,
      ctypes.POINTER(Resid))
@@ -72,12 +74,15 @@ _sig("cc_duals_to_lex", ctypes.c_int, _p, _p, _p)
 _sig("cc_slots_to_lex", ctypes.c_int, _p, _p, _i64, _p)
 _sig("cc_dataflow_tables", ctypes.c_int, _i64, _i32, _p, _p, _p, _p, _p, _p, _p, _p)
 _sig("cc_widen", ctypes.c_int, _p, _p, _i64, _p)
+_sig("cc_solve_cc_lp", ctypes.c_int, _i64, _p, _p, _dbl, _dbl, _i32, _i32, _i32, _i32, _p, _p,
+     _p, _p, ctypes.POINTER(Info))
 _sig("cc_narrow", ctypes.c_int, _p, _p, _i64, _p)
 
 EXPORTS = ["cc_last_error", "cc_num_metric_duals", "cc_create", "cc_destroy", "cc_dual_slots",
            "cc_num_rounds", "cc_prepare", "cc_init_cold", "cc_sweep", "cc_sweep_rounds",
+           "cc_sweep_metric", "cc_status",
            "cc_pair_pass", "cc_residuals", "cc_x_from_y", "cc_duals_to_lex", "cc_slots_to_lex",
-           "cc_dataflow_tables", "cc_widen", "cc_narrow"]
+           "cc_dataflow_tables", "cc_widen", "cc_narrow", "cc_solve_cc_lp"]
 
 
 class CCError(RuntimeError):
@@ -160,6 +165,12 @@ class Context:
     def sweep_rounds(self, x, y, g, first, count):
         check(_L.cc_sweep_rounds(self._h, _ptr(x), _ptr(y), _ptr(g), int(first), int(count)))
 
+    def sweep_metric(self, x, y, g, executor=CC_EXEC_ROUNDS):
+        check(_L.cc_sweep_metric(self._h, _ptr(x), _ptr(y), _ptr(g), int(executor)))
+
+    def status(self):
+        check(_L.cc_status(self._h))
+
     def pair_pass(self, x, f, y_pair, g, d):
         check(_L.cc_pair_pass(self._h, _ptr(x), _ptr(f), _ptr(y_pair), _ptr(g), _ptr(d)))
 
@@ -199,6 +210,29 @@ def dataflow_tables(n: int, b: int) -> dict:
                                 jsb.ctypes.data, needs.ctypes.data, K.ctypes.data))
     return dict(tile_pq=pq.reshape(-1, 2), need_c=needc, jsbase=jsb, needs=needs.reshape(-1, 2),
                 K=K)
+
+
+def solve_cc_lp(n, w, d, gamma, tol=1e-6, max_sweeps=100000, b=16, mode=CC_MODE_F64,
+                mlp_weights=None, deg=None, want_duals=False):
+    """One-shot solve from host arrays (cc_solve_cc_lp).  Returns
+    (status, x, y_lex or None, info dict)."""
+    w = np.ascontiguousarray(w, dtype=np.float64)
+    d = np.ascontiguousarray(d, dtype=np.uint8)
+    x = np.zeros(n * (n - 1) // 2)
+    ylex = np.zeros(num_metric_duals(n)) if want_duals else None
+    warm = CC_WARM_MLP if mlp_weights is not None else CC_WARM_NONE
+    mw = None if mlp_weights is None else np.ascontiguousarray(mlp_weights, dtype=np.float32)
+    dg = None if deg is None else np.ascontiguousarray(deg, dtype=np.float32)
+    info = Info()
+    rc = _L.cc_solve_cc_lp(int(n), w.ctypes.data, d.ctypes.data, float(gamma), float(tol),
+                           int(max_sweeps), int(b), int(mode), int(warm),
+                           None if mw is None else mw.ctypes.data,
+                           None if dg is None else dg.ctypes.data, x.ctypes.data,
+                           None if ylex is None else ylex.ctypes.data, ctypes.byref(info))
+    check(rc, allow_notconv=True)
+    out = dict(sweeps=info.sweeps, sweeps_f32=info.sweeps_f32, wall_s=info.wall_s,
+               resid=info.resid.as_dict())
+    return rc, x, ylex, out
 
 
 def widen(src, dst, stream=None):
@@ -247,6 +281,12 @@ class Solver:
 
     def sweep_rounds(self, first, count):
         self.ctx.sweep_rounds(self.x, self.y, self.g, first, count)
+
+    def sweep_metric(self, executor=CC_EXEC_ROUNDS):
+        self.ctx.sweep_metric(self.x, self.y, self.g, executor)
+
+    def status(self):
+        self.ctx.status()
 
     def pair_pass(self):
         self.ctx.pair_pass(self.x, self.f, self.y_pair, self.g, self.d)

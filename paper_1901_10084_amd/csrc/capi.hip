@@ -186,21 +186,22 @@ int ensure_dataflow(cc_ctx *c) {
 }
 
 template <typename T>
+int sweep_metric_t(cc_ctx *c, T *x, T *y, const T *g, int exec);
+
+template <typename T>
 int sweep_dataflow_t(cc_ctx *c, T *x, T *f, T *y, T *yp, const T *g, const uint8_t *d,
                      int nsweeps) {
-    int rc = ensure_dataflow(c);
-    if (rc) return rc;
+    int rc;
     for (int s = 0; s < nsweeps; ++s) {
-        if (uint64_t(c->epoch + 1) * c->kmax >= (1ull << 31)) {
-            if ((rc = launch_fill_u32(c->nblocks, c->d_cnt, c->stream))) return rc;
-            c->epoch = 0;
-        }
-        DataflowArgs a{c->d_dtiles, int(c->ntiles), c->d_needs, c->d_K, c->d_cnt, c->d_ctl,
-                       c->epoch, c->wait_ticks};
-        if ((rc = launch_sweep_dataflow<T>(a, c->df_grid, c->b, c->n, x, g, y, c->stream))) return rc;
-        c->epoch++;
+        if ((rc = sweep_metric_t<T>(c, x, y, g, CC_EXEC_DATAFLOW))) return rc;
         if ((rc = launch_pair_pass<T>(num_pairs(c->n), x, f, yp, g, d, c->stream))) return rc;
     }
+    return CC_OK;
+}
+
+// Reports (and clears) an aborted dataflow sweep.  Synchronises.
+int check_dataflow(cc_ctx *c) {
+    if (!c->d_ctl) return CC_OK;
     uint32_t ctl[4];
     CCP_HIP_CHECK(hipMemcpyAsync(ctl, c->d_ctl, sizeof(ctl), hipMemcpyDeviceToHost, c->stream));
     CCP_HIP_CHECK(hipStreamSynchronize(c->stream));
@@ -211,6 +212,22 @@ int sweep_dataflow_t(cc_ctx *c, T *x, T *f, T *y, T *yp, const T *g, const uint8
         c->epoch = 0;
         return fail(CC_EHIP, "dataflow sweep aborted: a dependency wait timed out");
     }
+    return CC_OK;
+}
+
+template <typename T>
+int sweep_metric_t(cc_ctx *c, T *x, T *y, const T *g, int exec) {
+    if (exec == CC_EXEC_ROUNDS) return sweep_rounds_t<T>(c, x, y, g, 0, c->nrounds);
+    int rc = ensure_dataflow(c);
+    if (rc) return rc;
+    if (uint64_t(c->epoch + 1) * c->kmax >= (1ull << 31)) {
+        if ((rc = launch_fill_u32(c->nblocks, c->d_cnt, c->stream))) return rc;
+        c->epoch = 0;
+    }
+    DataflowArgs a{c->d_dtiles, int(c->ntiles), c->d_needs, c->d_K, c->d_cnt, c->d_ctl,
+                   c->epoch, c->wait_ticks};
+    if ((rc = launch_sweep_dataflow<T>(a, c->df_grid, c->b, c->n, x, g, y, c->stream))) return rc;
+    c->epoch++;
     return CC_OK;
 }
 
@@ -409,6 +426,23 @@ int cc_sweep(cc_ctx *c, void *x, void *f, void *y, void *yp, const void *g, cons
                           nsweeps);
 }
 
+int cc_sweep_metric(cc_ctx *c, void *x, void *y, const void *g, int32_t exec) {
+    int rc;
+    if ((rc = check_ctx(c)) || (rc = need(x, "x")) || (rc = need(y, "y")) || (rc = need(g, "g")))
+        return rc;
+    if (exec != CC_EXEC_ROUNDS && exec != CC_EXEC_DATAFLOW) return fail(CC_EINVAL, "unknown executor");
+    if (c->prec == CC_F64) return sweep_metric_t<double>(c, (double *)x, (double *)y, (const double *)g, exec);
+    return sweep_metric_t<float>(c, (float *)x, (float *)y, (const float *)g, exec);
+}
+
+int cc_status(cc_ctx *c) {
+    int rc;
+    if ((rc = check_ctx(c))) return rc;
+    if ((rc = check_dataflow(c))) return rc;
+    CCP_HIP_CHECK(hipStreamSynchronize(c->stream));
+    return CC_OK;
+}
+
 int cc_sweep_rounds(cc_ctx *c, void *x, void *y, const void *g, int32_t first, int32_t count) {
     int rc;
     if ((rc = check_ctx(c)) || (rc = need(x, "x")) || (rc = need(y, "y")) || (rc = need(g, "g")))
@@ -442,6 +476,7 @@ int cc_residuals(cc_ctx *c, const void *x, const void *f, const void *y, const v
     if (!(gamma > 0.0)) return fail(CC_EINVAL, "gamma must be > 0");
     if ((what & (CC_RESID_CS | CC_RESID_DUAL)) && (!y || !yp))
         return fail(CC_EINVAL, "y and y_pair are needed for CC_RESID_CS / CC_RESID_DUAL");
+    if ((rc = check_dataflow(c))) return rc;
     if (c->prec == CC_F64)
         return residuals_t<double>(c, (const double *)x, (const double *)f, (const double *)y,
                                    (const double *)yp, w, d, gamma, what, out);
@@ -541,10 +576,11 @@ int sweep_to_tol(cc_ctx *c, void *x, void *f, void *y, void *yp, void *g, const 
                  const double *w, double gamma, double tol, int max_sweeps, int *done,
                  cc_resid *r) {
     const int every = c->n <= 1000 ? 1 : 5;
+    const int exec = (c->b == 8 || c->b == 16 || c->b == 32) ? CC_EXEC_DATAFLOW : CC_EXEC_ROUNDS;
     *done = 0;
     while (*done < max_sweeps) {
         const int k = std::min(every, max_sweeps - *done);
-        int rc = cc_sweep(c, x, f, y, yp, g, d, k, CC_EXEC_ROUNDS);
+        int rc = cc_sweep(c, x, f, y, yp, g, d, k, exec);
         if (rc) return rc;
         *done += k;
         rc = cc_residuals(c, x, f, nullptr, nullptr, w, d, gamma, CC_RESID_VIOL, r);

@@ -224,7 +224,7 @@ def test_dataflow_equals_rounds(n, b, prec, K):
     d = C.Solver.from_instance(inst, b=b, prec=prec)
     r.sweep(K, C.CC_EXEC_ROUNDS)
     d.sweep(K, C.CC_EXEC_DATAFLOW)
-    torch.cuda.synchronize()
+    d.status()
     for name in ("x", "f", "y", "y_pair"):
         a, bb = getattr(r, name), getattr(d, name)
         assert torch.equal(a, bb), (name, float((a - bb).abs().max()))
@@ -235,5 +235,42 @@ def test_dataflow_parity_oracle():
     g = C.Solver.from_instance(inst, b=8)
     o = oracle.State.from_instance(inst)
     g.sweep(6, C.CC_EXEC_DATAFLOW)
+    g.status()
     o.sweep(6, b=8)
     compare_state(g, o, TOL64, "dataflow n=70 K=6")
+
+
+# --------------------------------------------------------------------------
+# One-shot solve: FP64, FP32, and FP32 sweeps followed by FP64 polish.
+# --------------------------------------------------------------------------
+def test_solve_modes():
+    inst = I.workload(0)
+    rc64, x64, y64, i64 = C.solve_cc_lp(inst.n, inst.w, inst.d, inst.gamma, tol=1e-6, b=8,
+                                        mode=C.CC_MODE_F64, want_duals=True)
+    assert rc64 == C.CC_OK
+    o = oracle.State.from_instance(inst)
+    ro = o.solve(tol=1e-6, b=8, max_sweeps=5000)
+    assert i64["sweeps"] == o.sweeps
+    assert rel_err(x64, o.x) <= TOL64 and rel_err(y64, o.y) <= TOL64
+    rc32, x32, _, i32 = C.solve_cc_lp(inst.n, inst.w, inst.d, inst.gamma, tol=1e-4, b=8,
+                                      mode=C.CC_MODE_F32)
+    assert rc32 == C.CC_OK and i32["sweeps_f32"] == i32["sweeps"]
+    assert max(i32["resid"]["max_viol_metric"], i32["resid"]["max_viol_pair"]) <= 1e-4
+    rcp, xp, _, ip = C.solve_cc_lp(inst.n, inst.w, inst.d, inst.gamma, tol=1e-6, b=8,
+                                   mode=C.CC_MODE_F32_POLISH)
+    assert rcp == C.CC_OK and 0 < ip["sweeps_f32"] < ip["sweeps"]
+    r = ip["resid"]
+    assert max(r["max_viol_metric"], r["max_viol_pair"]) <= 1e-6
+    # the polished solution is the FP64 one (unique primal optimum of the QP)
+    assert abs(r["primal_qp"] - ro["primal_qp"]) <= 1e-5 * abs(ro["primal_qp"])
+    assert rel_err(xp, o.x) <= 1e-4
+    print("sweeps f64", i64["sweeps"], "f32", i32["sweeps"], "polish", ip["sweeps_f32"],
+          ip["sweeps"], flush=True)
+
+
+def test_solve_not_converged_reports():
+    inst = I.workload(0)
+    rc, x, _, info = C.solve_cc_lp(inst.n, inst.w, inst.d, inst.gamma, tol=1e-12, b=8,
+                                   max_sweeps=5, mode=C.CC_MODE_F64)
+    assert rc == C.CC_ENOTCONV and info["sweeps"] == 5
+    assert info["resid"]["max_viol_metric"] > 1e-12
