@@ -61,6 +61,50 @@ def recorded_traffic(kernel, inst, b, prec):
     return rec["traffic_bytes_per_launch"]
 
 
+def warm_report(b, tol=1e-4):
+    """FP64 plain cold solve vs FP32 cold vs FP32 + learned warm start on the
+    n = 2000 planted partition (20 blocks, p_in 0.25, p_out 0.01, gamma 5).
+    Wall times include inference, the x-from-y pass and every residual check;
+    objective errors are against an FP64 solve to 1e-7."""
+    import torch
+    from paper_1901_10084_amd import ccproj as C
+    from paper_1901_10084_amd import instances as I
+    from paper_1901_10084_amd import warmstart as W
+    inst = I.workload(3)
+    deg = W.degrees(inst)
+    net = W.load()
+    res = {"workload": inst.name, "n": inst.n, "tol": tol, "b": b}
+
+    def run(prec, warm):
+        s = C.Solver.from_instance(inst, b=b, prec=prec)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        info = W.warm_start(s, net, deg) if warm else None
+        r, conv, _ = s.solve(tol=tol, max_sweeps=20000, executor=C.CC_EXEC_DATAFLOW)
+        dt = time.perf_counter() - t0
+        out = {"seconds": dt, "sweeps": s.sweeps, "converged": conv, "primal_qp": r["primal_qp"],
+               "max_viol": max(r["max_viol_metric"], r["max_viol_pair"])}
+        if info:
+            out.update(accepted=info["accepted"], dual_warm=info["dual_warm"],
+                       dual_cold=info["dual_cold"])
+        del s
+        torch.cuda.empty_cache()
+        return out
+
+    ref = C.Solver.from_instance(inst, b=b, prec="f64")
+    rr, _, _ = ref.solve(tol=1e-7, max_sweeps=20000, executor=C.CC_EXEC_DATAFLOW)
+    pstar = rr["primal_qp"]
+    del ref
+    torch.cuda.empty_cache()
+    for name, prec, warm in (("f64_cold", "f64", False), ("f32_cold", "f32", False),
+                             ("f32_warm", "f32", True)):
+        res[name] = run(prec, warm)
+        res[name]["objective_rel_err"] = abs(res[name]["primal_qp"] - pstar) / abs(pstar)
+        log(f"warm report {name}: {res[name]}")
+    res["reference_primal_qp"] = pstar
+    return res
+
+
 def cpu_baseline(inst, b, budget_s):
     import oracle
     s = oracle.State.from_instance(inst)
@@ -89,6 +133,9 @@ def main():
     ap.add_argument("--cpu-budget", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-solve", action="store_true")
+    ap.add_argument("--warm-report", action="store_true",
+                    help="n = 2000 planted partition: FP64 cold vs FP32 cold vs FP32 + learned "
+                         "warm start, each to max violation <= 1e-4")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MiB",
                     help="after the timed region, copy a buffer of this size (reference "
                          "kernel for HBM byte counters)")
@@ -190,6 +237,9 @@ def main():
         log("timing the oracle ...")
         out["cpu_baseline"] = cpu_baseline(inst, args.b, args.cpu_budget)
         log(f"oracle: {out['cpu_baseline']}")
+
+    if args.warm_report:
+        out["warm_start"] = warm_report(args.b)
 
     out["gpu"] = torch.cuda.get_device_name(0)
     print(json.dumps(out), flush=True)

@@ -78,6 +78,8 @@ typedef struct {
 typedef struct {
     int32_t sweeps;          /* sweeps run (all phases)                       */
     int32_t sweeps_f32;      /* of which in FP32                              */
+    int32_t warm_accepted;   /* 1 if the learned warm start was kept          */
+    int32_t reserved;
     double wall_s;           /* wall time of the whole call                   */
     cc_resid resid;          /* final residuals                               */
 } cc_info;
@@ -199,14 +201,76 @@ int cc_dataflow_tables(int64_t n, int32_t b, int64_t *ntiles, int64_t *nsteps, i
 int cc_widen(const float *src, double *dst, int64_t count, void *stream);
 int cc_narrow(const double *src, float *dst, int64_t count, void *stream);
 
+/* ----- Learned warm start (a 4-32-32-1 network per metric row) ---------
+ * A nonnegative dual predicted for every metric row is a valid start for
+ * Algorithm 1, which is dual coordinate ascent: started from any y >= 0 at
+ * x = x(y) it converges to the same unique primal optimum.
+ * Network: ReLU after every layer, mean squared error; parameters are one
+ * flat fp32 vector of cc_mlp_num_params() values: W1[32][4], b1[32],
+ * W2[32][32], b2[32], W3[32], b3.  Products take bf16 operands and
+ * accumulate in fp32 (the 32x32 layer, its transpose and the weight
+ * gradient on MFMA).  Features of the row x_ab <= x_ac + x_bc (long side
+ * (a,b)): (s_ab w_ab, s_ac w_ac, s_bc w_bc, (deg_a + deg_b) / (2 mean deg)),
+ * s = +1 for a positive pair, -1 for a negative one; deg: device float[n],
+ * the degrees of the unsigned source graph.  The network's output is the
+ * dual times n - 2 (the number of triplets through a pair), so one network
+ * serves every n: graph training scales the targets by n - 2 and the warm
+ * start divides the prediction by it. */
+
+/* Number of network parameters (1249). */
+int32_t cc_mlp_num_params(void);
+
+/* Bytes of device workspace a training step over `count` samples needs. */
+int64_t cc_mlp_workspace_bytes(int64_t count);
+
+/* Host: He-initialised parameters from a seeded generator. */
+int cc_mlp_init(float *params_host, uint64_t seed);
+
+/* y[i] = network(phi[4i..4i+3]) for count samples (device arrays). */
+int cc_mlp_forward(const float *params, const float *phi, int64_t count, float *y, void *stream);
+
+/* One training step on explicit samples (device arrays): mean squared error
+ * over the count samples, its gradient (written to grad_out if not NULL),
+ * then, if lr > 0, one Adam step (beta 0.9/0.999, eps 1e-8, bias-corrected
+ * with `step` >= 1) on params with moment buffers adam_m, adam_v.
+ * workspace: cc_mlp_workspace_bytes(count) bytes; loss_out: device float. */
+int cc_mlp_train_step(const float *phi, const float *target, int64_t count, float *params,
+                      float *adam_m, float *adam_v, int32_t step, float lr, float *grad_out,
+                      void *workspace, float *loss_out, void *stream);
+
+/* One training step on `batch` metric rows drawn (seeded, with
+ * replacement) from the schedule slots of the context's instance, with
+ * targets y_star (converged duals, schedule order, context precision);
+ * padding slots drawn count as zero-weight samples.  Same update and
+ * outputs as cc_mlp_train_step. */
+int cc_mlp_train_graph(cc_ctx *ctx, const void *y_star, const double *w, const uint8_t *d,
+                       const float *deg, int64_t batch, uint64_t seed, float *params, float *adam_m,
+                       float *adam_v, int32_t step, float lr, void *workspace, float *loss_out);
+
+/* Features (4 floats, bf16-rounded) of the metric rows at the given
+ * schedule slots (zeros for padding). */
+int cc_mlp_slot_features(cc_ctx *ctx, const double *w, const uint8_t *d, const float *deg,
+                         const int64_t *slots, int64_t count, float *phi_out);
+
+/* Warm start: y = network prediction for every metric row (0 on padding),
+ * y_pair = 0, (x, f) = v(y), then one pair pass (which gives the pair duals
+ * their best values for this y: the two pair rows of a pair are
+ * W-orthogonal).  The start is kept only if its dual objective is at least
+ * the cold start's after its first pair pass; otherwise the state is reset
+ * to the cold start.  *accepted (nullable) tells which; *dual_warm and
+ * *dual_cold (nullable) return the two dual values.  g from cc_prepare. */
+int cc_warm_start_mlp(cc_ctx *ctx, const float *params, const float *deg, const double *w,
+                      const uint8_t *d, double gamma, void *x, void *f, void *y, void *y_pair,
+                      const void *g, int32_t *accepted, double *dual_warm, double *dual_cold);
+
 /* One-shot solve from host arrays (allocates its own device buffers).
  * w_host: double[N_p] > 0; d_host: uint8[N_p]; tol: stop when both max
  * violations are <= tol; mode: CC_MODE_F64, CC_MODE_F32 (FP32 sweeps to tol)
  * or CC_MODE_F32_POLISH (FP32 sweeps to max(tol, 1e-4), then duals widened,
  * x recomputed from them in FP64 and FP64 sweeps to tol); warm: CC_WARM_NONE
  * or CC_WARM_MLP (then mlp_weights_host must point to cc_mlp_num_params()
- * floats; the predicted duals are kept only if they raise the dual
- * objective, else the solve starts cold).  x_out_host: double[N_p] or NULL;
+ * floats and deg_host to n floats; see cc_warm_start_mlp for the gate;
+ * info->warm_accepted tells whether the start was kept).  x_out_host: double[N_p] or NULL;
  * y_lex_out_host: double[3 C(n,3)] or NULL.  Returns CC_OK, CC_ENOTCONV
  * (info filled, outputs written), or an error. */
 int cc_solve_cc_lp(int64_t n, const double *w_host, const uint8_t *d_host, double gamma,

@@ -44,7 +44,8 @@ class Resid(ctypes.Structure):
 
 
 class Info(ctypes.Structure):
-    _fields_ = [("sweeps", _i32), ("sweeps_f32", _i32), ("wall_s", _dbl), ("resid", Resid)]
+    _fields_ = [("sweeps", _i32), ("sweeps_f32", _i32), ("warm_accepted", _i32),
+                ("reserved", _i32), ("wall_s", _dbl), ("resid", Resid)]
 
 
 def _sig(name, res, *args):
@@ -77,6 +78,18 @@ _sig("cc_widen", ctypes.c_int, _p, _p, _i64, _p)
 _sig("cc_solve_cc_lp", ctypes.c_int, _i64, _p, _p, _dbl, _dbl, _i32, _i32, _i32, _i32, _p, _p,
      _p, _p, ctypes.POINTER(Info))
 _sig("cc_narrow", ctypes.c_int, _p, _p, _i64, _p)
+
+_sig("cc_mlp_num_params", _i32)
+_sig("cc_mlp_workspace_bytes", _i64, _i64)
+_sig("cc_mlp_init", ctypes.c_int, _p, ctypes.c_uint64)
+_sig("cc_mlp_forward", ctypes.c_int, _p, _p, _i64, _p, _p)
+_sig("cc_mlp_train_step", ctypes.c_int, _p, _p, _i64, _p, _p, _p, _i32, ctypes.c_float, _p, _p,
+     _p, _p)
+_sig("cc_mlp_train_graph", ctypes.c_int, _p, _p, _p, _p, _p, _i64, ctypes.c_uint64, _p, _p, _p,
+     _i32, ctypes.c_float, _p, _p)
+_sig("cc_mlp_slot_features", ctypes.c_int, _p, _p, _p, _p, _p, _i64, _p)
+_sig("cc_warm_start_mlp", ctypes.c_int, _p, _p, _p, _p, _p, _dbl, _p, _p, _p, _p, _p,
+     ctypes.POINTER(_i32), ctypes.POINTER(_dbl), ctypes.POINTER(_dbl))
 
 EXPORTS = ["cc_last_error", "cc_num_metric_duals", "cc_create", "cc_destroy", "cc_dual_slots",
            "cc_num_rounds", "cc_prepare", "cc_init_cold", "cc_sweep", "cc_sweep_rounds",
@@ -231,7 +244,7 @@ def solve_cc_lp(n, w, d, gamma, tol=1e-6, max_sweeps=100000, b=16, mode=CC_MODE_
                            None if ylex is None else ylex.ctypes.data, ctypes.byref(info))
     check(rc, allow_notconv=True)
     out = dict(sweeps=info.sweeps, sweeps_f32=info.sweeps_f32, wall_s=info.wall_s,
-               resid=info.resid.as_dict())
+               warm_accepted=info.warm_accepted, resid=info.resid.as_dict())
     return rc, x, ylex, out
 
 

@@ -57,6 +57,29 @@ template <typename T> int launch_sweep_dataflow(const DataflowArgs &, int, int, 
 template <typename T> int dataflow_occupancy(int, int *);
 int launch_fill_u32(int64_t, uint32_t *, hipStream_t);
 
+struct GraphView {
+    const Tile *tiles;
+    int64_t ntiles;
+    int b;
+    int64_t n;
+    const double *w;
+    const uint8_t *d;
+    const float *deg;
+    const float *mean_deg;
+};
+int mlp_num_params();
+size_t mlp_workspace_bytes(int64_t count);
+int mlp_grad_blocks(int64_t count);
+int launch_mlp_train_explicit(const float *, const float *, int64_t, float *, float *, float *, int,
+                              float, float *, void *, float *, hipStream_t);
+template <typename T>
+int launch_mlp_train_graph(const GraphView &, const T *, int64_t, uint64_t, int64_t, float *, float *,
+                           float *, int, float, void *, float *, hipStream_t);
+int launch_mlp_forward(const float *, const float *, int64_t, float *, hipStream_t);
+template <typename T> int launch_mlp_infer(const GraphView &, const float *, T *, hipStream_t);
+int launch_mlp_slot_features(const GraphView &, const int64_t *, int64_t, float *, hipStream_t);
+int launch_mean_deg(const float *, int64_t, float *, hipStream_t);
+
 }  // namespace ccp
 
 using namespace ccp;
@@ -88,6 +111,7 @@ struct cc_ctx {
     uint32_t epoch = 0;
     int df_grid = 0;
     uint64_t wait_ticks = 0;
+    float *d_mean_deg = nullptr;  // warm-start features
 };
 
 namespace {
@@ -104,6 +128,19 @@ int need(const void *p, const char *name) {
     if (!p) return fail(CC_EINVAL, std::string("null pointer: ") + name);
     return CC_OK;
 }
+
+// Scratch allocation released at scope exit.
+struct DevTmp {
+    void *p = nullptr;
+    ~DevTmp() { if (p) (void)hipFree(p); }
+    int alloc(size_t bytes) {
+        if (hipMalloc(&p, bytes ? bytes : 1) != hipSuccess) {
+            p = nullptr;
+            return fail(CC_ENOMEM, "hipMalloc of scratch failed");
+        }
+        return CC_OK;
+    }
+};
 
 // Build the tiled schedule (Sec. III-C): tiles in round order, rounds the
 // block anti-diagonals s = nb-1 .. 0 followed by s = nb .. 2nb-2, tiles of
@@ -367,6 +404,7 @@ int cc_destroy(cc_ctx *c) {
     (void)hipFree(c->d_K);
     (void)hipFree(c->d_cnt);
     (void)hipFree(c->d_ctl);
+    (void)hipFree(c->d_mean_deg);
     delete c;
     return CC_OK;
 }
@@ -550,6 +588,166 @@ int cc_narrow(const double *src, float *dst, int64_t count, void *stream) {
 
 }  // extern "C"
 
+// ----- learned warm start ----------------------------------------------------
+namespace {
+
+int graph_view(cc_ctx *c, const double *w, const uint8_t *d, const float *deg, GraphView &G) {
+    if (!c->d_mean_deg && hipMalloc(&c->d_mean_deg, sizeof(float)) != hipSuccess) {
+        c->d_mean_deg = nullptr;
+        return fail(CC_ENOMEM, "hipMalloc failed");
+    }
+    int rc = launch_mean_deg(deg, c->n, c->d_mean_deg, c->stream);
+    if (rc) return rc;
+    G = GraphView{c->d_tiles, c->ntiles, c->b, c->n, w, d, deg, c->d_mean_deg};
+    return CC_OK;
+}
+
+// Dual objective from the pair state and the metric part of A'y (ax; null
+// means zero): D = -b'y - (gamma/2) sum (c + A'y)^2 / w.
+template <typename T>
+int dual_value(cc_ctx *c, const T *x, const T *f, const T *yp, const double *w, const uint8_t *d,
+               const double *ax, double gamma, double *out) {
+    int rc = launch_pair_resid<T>(num_pairs(c->n), x, f, yp, w, d, ax, gamma, c->d_ppart, c->stream);
+    if (rc) return rc;
+    if ((rc = launch_final_reduce(c->d_mpart, 0, c->d_ppart, c->d_out, c->stream))) return rc;
+    double h[14];
+    CCP_HIP_CHECK(hipMemcpyAsync(h, c->d_out, sizeof(h), hipMemcpyDeviceToHost, c->stream));
+    CCP_HIP_CHECK(hipStreamSynchronize(c->stream));
+    *out = -h[11] - 0.5 * gamma * h[10];
+    return CC_OK;
+}
+
+template <typename T>
+int warm_start_t(cc_ctx *c, const float *P, const float *deg, const double *w, const uint8_t *d,
+                 double gamma, T *x, T *f, T *y, T *yp, const T *g, int32_t *accepted,
+                 double *dwarm, double *dcold) {
+    const int64_t np = num_pairs(c->n);
+    GraphView G;
+    int rc;
+    if ((rc = graph_view(c, w, d, deg, G))) return rc;
+    // predicted metric duals, pair duals 0, v = v(y), one pair pass
+    if ((rc = launch_mlp_infer<T>(G, P, y, c->stream))) return rc;
+    if ((rc = launch_init_cold<T>(np, c->slots, x, f, nullptr, yp, gamma, c->stream))) return rc;
+    if ((rc = x_from_y_t<T>(c, y, yp, w, gamma, x, f))) return rc;
+    if ((rc = launch_pair_pass<T>(np, x, f, yp, g, d, c->stream))) return rc;
+    double Dw = 0.0, Dc = 0.0;
+    if ((rc = dual_value<T>(c, x, f, yp, w, d, c->d_ax, gamma, &Dw))) return rc;
+    // the cold start's value after its first pair pass (metric duals 0)
+    DevTmp t0, t1, t2, tz;
+    if ((rc = t0.alloc(np * sizeof(T))) || (rc = t1.alloc(np * sizeof(T))) ||
+        (rc = t2.alloc(2 * np * sizeof(T))) || (rc = tz.alloc(np * sizeof(double))))
+        return rc;
+    T *x0 = (T *)t0.p, *f0 = (T *)t1.p, *yp0 = (T *)t2.p;
+    CCP_HIP_CHECK(hipMemsetAsync(tz.p, 0, np * sizeof(double), c->stream));
+    if ((rc = launch_init_cold<T>(np, c->slots, x0, f0, nullptr, yp0, gamma, c->stream))) return rc;
+    if ((rc = launch_pair_pass<T>(np, x0, f0, yp0, g, d, c->stream))) return rc;
+    if ((rc = dual_value<T>(c, x0, f0, yp0, w, d, (const double *)tz.p, gamma, &Dc))) return rc;
+    const bool ok = std::isfinite(Dw) && Dw >= Dc;
+    if (!ok && (rc = launch_init_cold<T>(np, c->slots, x, f, y, yp, gamma, c->stream))) return rc;
+    if (accepted) *accepted = ok ? 1 : 0;
+    if (dwarm) *dwarm = Dw;
+    if (dcold) *dcold = Dc;
+    return CC_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int32_t cc_mlp_num_params(void) { return mlp_num_params(); }
+
+int64_t cc_mlp_workspace_bytes(int64_t count) { return int64_t(mlp_workspace_bytes(count)); }
+
+int cc_mlp_init(float *params, uint64_t seed) {
+    if (!params) return fail(CC_EINVAL, "null params");
+    // He initialisation from a splitmix64 stream (Box-Muller)
+    uint64_t st = seed;
+    auto next = [&]() {
+        st += 0x9E3779B97F4A7C15ull;
+        uint64_t z = st;
+        z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+        z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+        z ^= z >> 31;
+        return (double(z >> 11) + 0.5) * (1.0 / 9007199254740992.0);
+    };
+    auto normal = [&]() {
+        const double u1 = next(), u2 = next();
+        return std::sqrt(-2.0 * std::log(u1)) * std::cos(6.283185307179586 * u2);
+    };
+    for (int e = 0; e < 128; ++e) params[e] = float(normal() * std::sqrt(2.0 / 4.0));
+    for (int e = 128; e < 160; ++e) params[e] = 0.01f;
+    for (int e = 160; e < 1184; ++e) params[e] = float(normal() * std::sqrt(2.0 / 32.0));
+    for (int e = 1184; e < 1216; ++e) params[e] = 0.01f;
+    for (int e = 1216; e < 1248; ++e) params[e] = float(normal() * std::sqrt(2.0 / 32.0));
+    params[1248] = 0.05f;
+    return CC_OK;
+}
+
+int cc_mlp_forward(const float *params, const float *phi, int64_t count, float *y, void *stream) {
+    if (count < 0) return fail(CC_EINVAL, "count must be >= 0");
+    if (count && (!params || !phi || !y)) return fail(CC_EINVAL, "null pointer");
+    return launch_mlp_forward(params, phi, count, y, static_cast<hipStream_t>(stream));
+}
+
+int cc_mlp_train_step(const float *phi, const float *target, int64_t count, float *params,
+                      float *adam_m, float *adam_v, int32_t step, float lr, float *grad_out,
+                      void *workspace, float *loss_out, void *stream) {
+    if (count < 1) return fail(CC_EINVAL, "count must be >= 1");
+    if (!phi || !target || !params || !workspace || !loss_out) return fail(CC_EINVAL, "null pointer");
+    if (lr > 0.0f && (!adam_m || !adam_v || step < 1)) return fail(CC_EINVAL, "Adam state and step >= 1 needed");
+    return launch_mlp_train_explicit(phi, target, count, params, adam_m, adam_v, step, lr, grad_out,
+                                     workspace, loss_out, static_cast<hipStream_t>(stream));
+}
+
+int cc_mlp_train_graph(cc_ctx *c, const void *ystar, const double *w, const uint8_t *d,
+                       const float *deg, int64_t batch, uint64_t seed, float *params, float *adam_m,
+                       float *adam_v, int32_t step, float lr, void *workspace, float *loss_out) {
+    int rc;
+    if ((rc = check_ctx(c)) || (rc = need(ystar, "y_star")) || (rc = need(w, "w")) ||
+        (rc = need(d, "d")) || (rc = need(deg, "deg")) || (rc = need(params, "params")) ||
+        (rc = need(workspace, "workspace")) || (rc = need(loss_out, "loss")))
+        return rc;
+    if (batch < 1) return fail(CC_EINVAL, "batch must be >= 1");
+    if (lr > 0.0f && (!adam_m || !adam_v || step < 1)) return fail(CC_EINVAL, "Adam state and step >= 1 needed");
+    GraphView G;
+    if ((rc = graph_view(c, w, d, deg, G))) return rc;
+    if (c->prec == CC_F64)
+        return launch_mlp_train_graph<double>(G, (const double *)ystar, c->slots, seed, batch, params,
+                                              adam_m, adam_v, step, lr, workspace, loss_out, c->stream);
+    return launch_mlp_train_graph<float>(G, (const float *)ystar, c->slots, seed, batch, params,
+                                         adam_m, adam_v, step, lr, workspace, loss_out, c->stream);
+}
+
+int cc_mlp_slot_features(cc_ctx *c, const double *w, const uint8_t *d, const float *deg,
+                         const int64_t *slots, int64_t count, float *phi) {
+    int rc;
+    if ((rc = check_ctx(c)) || (rc = need(w, "w")) || (rc = need(d, "d")) || (rc = need(deg, "deg")))
+        return rc;
+    if (count < 0) return fail(CC_EINVAL, "count must be >= 0");
+    if (count && ((rc = need(slots, "slots")) || (rc = need(phi, "phi")))) return rc;
+    GraphView G;
+    if ((rc = graph_view(c, w, d, deg, G))) return rc;
+    return launch_mlp_slot_features(G, slots, count, phi, c->stream);
+}
+
+int cc_warm_start_mlp(cc_ctx *c, const float *params, const float *deg, const double *w,
+                      const uint8_t *d, double gamma, void *x, void *f, void *y, void *yp,
+                      const void *g, int32_t *accepted, double *dual_warm, double *dual_cold) {
+    int rc;
+    if ((rc = check_ctx(c)) || (rc = need(params, "params")) || (rc = need(deg, "deg")) ||
+        (rc = need(w, "w")) || (rc = need(d, "d")) || (rc = need(x, "x")) || (rc = need(f, "f")) ||
+        (rc = need(y, "y")) || (rc = need(yp, "y_pair")) || (rc = need(g, "g")))
+        return rc;
+    if (!(gamma > 0.0)) return fail(CC_EINVAL, "gamma must be > 0");
+    if (c->prec == CC_F64)
+        return warm_start_t<double>(c, params, deg, w, d, gamma, (double *)x, (double *)f, (double *)y,
+                                    (double *)yp, (const double *)g, accepted, dual_warm, dual_cold);
+    return warm_start_t<float>(c, params, deg, w, d, gamma, (float *)x, (float *)f, (float *)y,
+                               (float *)yp, (const float *)g, accepted, dual_warm, dual_cold);
+}
+
+}  // extern "C"
+
 // ----- one-shot solve ------------------------------------------------------
 namespace {
 
@@ -639,7 +837,18 @@ extern "C" int cc_solve_cc_lp(int64_t n, const double *w_host, const uint8_t *d_
             (rc = cc_init_cold(c32.c, x32.p, f32b.p, y32.p, yp32.p, gamma)))
             return rc;
         if (warm == CC_WARM_MLP) {
-            return fail(CC_EINVAL, "warm start is not available in this build");
+            DevBuf dP, dDeg;
+            if ((rc = dP.alloc(size_t(mlp_num_params()) * sizeof(float), "network")) ||
+                (rc = dDeg.alloc(size_t(n) * sizeof(float), "degrees")))
+                return rc;
+            CCP_HIP_CHECK(hipMemcpy(dP.p, mlp_weights_host, size_t(mlp_num_params()) * sizeof(float),
+                                    hipMemcpyHostToDevice));
+            CCP_HIP_CHECK(hipMemcpy(dDeg.p, deg_host, size_t(n) * sizeof(float), hipMemcpyHostToDevice));
+            int32_t acc = 0;
+            rc = cc_warm_start_mlp(c32.c, (const float *)dP.p, (const float *)dDeg.p, w, d, gamma,
+                                   x32.p, f32b.p, y32.p, yp32.p, g32.p, &acc, nullptr, nullptr);
+            if (rc) return rc;
+            info->warm_accepted = acc;
         }
         const double tol32 = (mode == CC_MODE_F32_POLISH) ? std::fmax(tol, 1e-4) : tol;
         status = sweep_to_tol(c32.c, x32.p, f32b.p, y32.p, yp32.p, g32.p, d, w, gamma, tol32,
@@ -664,6 +873,20 @@ extern "C" int cc_solve_cc_lp(int64_t n, const double *w_host, const uint8_t *d_
                 return rc;
         } else {
             if ((rc = cc_init_cold(c64.c, x64.p, f64b.p, y64.p, yp64.p, gamma))) return rc;
+            if (warm == CC_WARM_MLP) {
+                DevBuf dP, dDeg;
+                if ((rc = dP.alloc(size_t(mlp_num_params()) * sizeof(float), "network")) ||
+                    (rc = dDeg.alloc(size_t(n) * sizeof(float), "degrees")))
+                    return rc;
+                CCP_HIP_CHECK(hipMemcpy(dP.p, mlp_weights_host, size_t(mlp_num_params()) * sizeof(float),
+                                        hipMemcpyHostToDevice));
+                CCP_HIP_CHECK(hipMemcpy(dDeg.p, deg_host, size_t(n) * sizeof(float), hipMemcpyHostToDevice));
+                int32_t acc = 0;
+                rc = cc_warm_start_mlp(c64.c, (const float *)dP.p, (const float *)dDeg.p, w, d, gamma,
+                                       x64.p, f64b.p, y64.p, yp64.p, g64.p, &acc, nullptr, nullptr);
+                if (rc) return rc;
+                info->warm_accepted = acc;
+            }
         }
         const int left = max_sweeps - info->sweeps;
         if (left > 0) {

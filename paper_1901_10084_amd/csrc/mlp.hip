@@ -1,0 +1,546 @@
+// mlp.hip -- the learned warm start: a 4-32-32-1 network that predicts a
+// nonnegative dual for every metric row from local features, trained on
+// converged duals.  A warm start is valid because Algorithm 1 is dual
+// coordinate ascent: it converges from any y >= 0 started at x = x(y).
+//
+// Network: ReLU after every layer, mean squared error of the output, with the
+// output ReLU's gradient passed through where the target is positive (a row
+// whose target is 0 is fitted by any output <= 0).  Parameters are one
+// flat fp32 vector: W1[32][4], b1[32], W2[32][32], b2[32], W3[32], b3.
+// Products take bf16 operands (phi, W1, h1, W2, h2, W3; in the backward pass
+// delta2 before it meets W2 and h1) and accumulate in fp32.
+//
+// Layout on a 64-lane wave: lane l works on sample s = l % 16 of a group of
+// 16 samples and on the units U_g = {4g..4g+3, 16+4g..16+4g+3}, g = l / 16.
+// The 32x32 layer and its transpose run on v_mfma_f32_16x16x32_bf16 with the
+// K index permuted so that a lane's 8 K slots are exactly its units U_g:
+// the B operand is then the lane's own h1 (forward) or delta2 (backward) and
+// the D rows it receives are again units U_g, so every layer stays in
+// registers.  The weight gradient dW2 = sum over samples of delta2 h1^T is an
+// MFMA with K = 32 samples, fed through a small LDS transpose.
+#include "common.hpp"
+
+namespace ccp {
+
+typedef __attribute__((ext_vector_type(8))) __bf16 bf16x8;
+typedef __attribute__((ext_vector_type(4))) float f32x4;
+
+constexpr int kNParam = 1249;
+constexpr int oW1 = 0, oB1 = 128, oW2 = 160, oB2 = 1184, oW3 = 1216, oB3 = 1248;
+
+__host__ __device__ __forceinline__ int unit_of(int g, int q) {
+    return q < 4 ? 4 * g + q : 16 + 4 * g + (q - 4);
+}
+
+// Round to the nearest bfloat16 (ties to even), kept as a float.
+__device__ __forceinline__ float bf16r(float v) {
+    uint32_t u = __float_as_uint(v);
+    u = (u + 0x7FFFu + ((u >> 16) & 1u)) & 0xFFFF0000u;
+    return __uint_as_float(u);
+}
+__device__ __forceinline__ __bf16 tobf(float v) {
+    const uint16_t h = uint16_t(__float_as_uint(bf16r(v)) >> 16);
+    return __builtin_bit_cast(__bf16, h);
+}
+
+struct LaneNet {
+    float w1[8][4];
+    float b1[8];
+    bf16x8 a2[2];   // a2[t][q]  = W2[16t + i][U_g[q]]   (forward)
+    bf16x8 a2t[2];  // a2t[t][q] = W2[U_g[q]][16t + i]   (backward, transposed)
+    float b2[8];
+    float w3[8];
+    float b3;
+};
+
+__device__ __forceinline__ void load_net(LaneNet &N, const float *__restrict__ P) {
+    const int lane = threadIdx.x & 63, i = lane & 15, g = lane >> 4;
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+        const int u = unit_of(g, q);
+#pragma unroll
+        for (int k = 0; k < 4; ++k) N.w1[q][k] = bf16r(P[oW1 + u * 4 + k]);
+        N.b1[q] = P[oB1 + u];
+        N.b2[q] = P[oB2 + u];
+        N.w3[q] = bf16r(P[oW3 + u]);
+#pragma unroll
+        for (int t = 0; t < 2; ++t) {
+            N.a2[t][q] = tobf(P[oW2 + (16 * t + i) * 32 + u]);
+            N.a2t[t][q] = tobf(P[oW2 + u * 32 + 16 * t + i]);
+        }
+    }
+    N.b3 = P[oB3];
+}
+
+struct Fwd {
+    float z1[8], h1[8], z2[8], h2[8];
+    float z3, y;
+};
+
+// Forward pass of the lane's sample (phi already bf16-rounded).
+__device__ __forceinline__ void forward(const LaneNet &N, const float phi[4], Fwd &F) {
+    bf16x8 bh;
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+        float z = N.b1[q];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) z = fmaf(N.w1[q][k], phi[k], z);
+        F.z1[q] = z;
+        F.h1[q] = bf16r(fmaxf(z, 0.0f));
+        bh[q] = tobf(F.h1[q]);
+    }
+    const f32x4 zero = {0.f, 0.f, 0.f, 0.f};
+    const f32x4 d0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(N.a2[0], bh, zero, 0, 0, 0);
+    const f32x4 d1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(N.a2[1], bh, zero, 0, 0, 0);
+    float part = 0.0f;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        F.z2[r] = d0[r] + N.b2[r];
+        F.z2[4 + r] = d1[r] + N.b2[4 + r];
+    }
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+        F.h2[q] = bf16r(fmaxf(F.z2[q], 0.0f));
+        part = fmaf(N.w3[q], F.h2[q], part);
+    }
+    part += __shfl_xor(part, 16, 64);
+    part += __shfl_xor(part, 32, 64);
+    F.z3 = part + N.b3;
+    F.y = fmaxf(F.z3, 0.0f);
+}
+
+// ---------------------------------------------------------------------------
+// Metric-row features (the reading of "3 edge weights + endpoint degrees"):
+// for the row with long side (a,b) and apex c,
+// (s_ab w_ab, s_ac w_ac, s_bc w_bc, (deg_a + deg_b) / (2 mean deg)),
+// s = +1 for a positive pair, -1 for a negative one.  Rounded to bf16.
+// ---------------------------------------------------------------------------
+struct GraphView {
+    const Tile *tiles;
+    int64_t ntiles;
+    int b;
+    int64_t n;
+    const double *w;
+    const uint8_t *d;
+    const float *deg;
+    const float *mean_deg;
+};
+
+// Decodes schedule slot s of tile tl; false for padding.
+__device__ __forceinline__ bool decode_slot(const Tile &tl, int64_t s, int b, int64_t n, int64_t &i,
+                                            int64_t &j, int64_t &k, int &o) {
+    const int64_t bb = int64_t(b) * b;
+    const int64_t off = s - tl.ybase;
+    const int64_t u = off / (3 * bb), rem = off - u * 3 * bb;
+    o = int(rem / bb);
+    const int lane = int(rem - int64_t(o) * bb);
+    const int il = lane / b, kl = lane - (lane / b) * b;
+    const int m = int(u / b), t = int(u - int64_t(m) * b);
+    const int nb = int((n + b - 1) / b);
+    const int J = tile_J(tl.P, tl.Q, m, tile_desc(tl.P, tl.Q, nb));
+    i = int64_t(tl.P) * b + il;
+    k = int64_t(tl.Q) * b + kl;
+    j = int64_t(J) * b + mid_offset(t, il, kl, b);
+    return m <= tl.Q - tl.P && i < j && j < k && k < n;
+}
+
+__device__ __forceinline__ void row_features(const GraphView &G, int64_t i, int64_t j, int64_t k,
+                                             int o, float phi[4]) {
+    const int64_t pij = pidx(i, j), pik = pidx(i, k), pjk = pidx(j, k);
+    const int64_t L = o == 0 ? pij : (o == 1 ? pik : pjk);
+    const int64_t S1 = o == 2 ? pij : (o == 1 ? pij : pik);
+    const int64_t S2 = o == 0 ? pjk : (o == 1 ? pjk : pik);
+    const int64_t a = o == 2 ? j : i;
+    const int64_t bn = o == 0 ? j : k;
+    auto sw = [&](int64_t p) { return float(G.d[p] == 0 ? G.w[p] : -G.w[p]); };
+    const float md = G.mean_deg[0];
+    phi[0] = bf16r(sw(L));
+    phi[1] = bf16r(sw(S1));
+    phi[2] = bf16r(sw(S2));
+    phi[3] = bf16r(md > 0.0f ? (G.deg[a] + G.deg[bn]) / (2.0f * md) : 0.0f);
+}
+
+__device__ __forceinline__ uint64_t mix64(uint64_t z) {
+    // splitmix64 finaliser
+    z += 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+// Sample sources for training.
+struct ExplicitSource {
+    const float *phi;
+    const float *target;
+    int64_t count;
+    __device__ void get(int64_t idx, float phi[4], float &t, float &wgt) const {
+        const bool ok = idx < count;
+        const int64_t e = ok ? idx : 0;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) phi[k] = bf16r(this->phi[4 * e + k]);
+        t = this->target[e];
+        wgt = ok ? 1.0f : 0.0f;
+    }
+};
+
+template <typename T>
+struct GraphSource {
+    GraphView G;
+    const T *ystar;   // converged duals, schedule order
+    int64_t slots;
+    uint64_t seed;
+    int64_t count;    // samples in the batch
+    __device__ void get(int64_t idx, float phi[4], float &t, float &wgt) const {
+        const int64_t s = int64_t(mix64(seed ^ (uint64_t(idx) * 0xD1B54A32D192ED03ull)) %
+                                  uint64_t(slots));
+        int64_t lo = 0, hi = G.ntiles - 1;
+        while (lo < hi) {
+            const int64_t mid = (lo + hi + 1) / 2;
+            if (G.tiles[mid].ybase <= s) lo = mid; else hi = mid - 1;
+        }
+        int64_t i, j, k;
+        int o;
+        const bool ok = idx < count && decode_slot(G.tiles[lo], s, G.b, G.n, i, j, k, o);
+        if (ok) {
+            row_features(G, i, j, k, o, phi);
+        } else {
+            phi[0] = phi[1] = phi[2] = phi[3] = 0.0f;
+        }
+        // target: the dual times n - 2 (see k_mlp_infer)
+        t = ok ? float(ystar[s]) * float(G.n - 2) : 0.0f;
+        wgt = ok ? 1.0f : 0.0f;
+    }
+};
+
+// ---------------------------------------------------------------------------
+// Training: one wave per workgroup; chunks of 32 samples; per-workgroup
+// partial gradients (kNParam values + the loss) in a fixed order.
+// ---------------------------------------------------------------------------
+template <typename Src>
+__global__ void __launch_bounds__(64)
+k_mlp_grad(Src src, int64_t count, float inv_norm, const float *__restrict__ P,
+           float *__restrict__ partial) {
+    __shared__ __bf16 D2s[32][32];
+    __shared__ __bf16 H1s[32][32];
+    const int lane = threadIdx.x, j = lane & 15, g = lane >> 4;
+    LaneNet N;
+    load_net(N, P);
+    float gW1[8][4], gb1[8], gb2[8], gW3[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+        gb1[q] = gb2[q] = gW3[q] = 0.0f;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) gW1[q][k] = 0.0f;
+    }
+    float gb3 = 0.0f, loss = 0.0f;
+    f32x4 acc[2][2];
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int c = 0; c < 2; ++c) acc[a][c] = f32x4{0.f, 0.f, 0.f, 0.f};
+
+    const int64_t nchunks = (count + 31) / 32;
+    for (int64_t c = blockIdx.x; c < nchunks; c += gridDim.x) {
+#pragma unroll
+        for (int G = 0; G < 2; ++G) {
+            float phi[4], t, wgt;
+            src.get(32 * c + 16 * G + j, phi, t, wgt);
+            Fwd F;
+            forward(N, phi, F);
+            // squared error of the ReLU output; where the target is
+            // positive the output ReLU passes the gradient, so a row pushed
+            // below zero can still learn a positive dual
+            const float r = (t > 0.0f) ? F.z3 - t : F.y;
+            if (g == 0) loss = fmaf(wgt * r, r, loss);
+            const float d3 = (t > 0.0f || F.z3 > 0.0f) ? wgt * 2.0f * r * inv_norm : 0.0f;
+            if (g == 0) gb3 += d3;
+            bf16x8 bd2;
+            float d2b[8];
+#pragma unroll
+            for (int q = 0; q < 8; ++q) {
+                gW3[q] = fmaf(d3, F.h2[q], gW3[q]);
+                const float d2 = (F.z2[q] > 0.0f) ? d3 * N.w3[q] : 0.0f;
+                gb2[q] += d2;
+                d2b[q] = bf16r(d2);
+                bd2[q] = tobf(d2b[q]);
+            }
+            const f32x4 zero = {0.f, 0.f, 0.f, 0.f};
+            const f32x4 e0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(N.a2t[0], bd2, zero, 0, 0, 0);
+            const f32x4 e1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(N.a2t[1], bd2, zero, 0, 0, 0);
+#pragma unroll
+            for (int q = 0; q < 8; ++q) {
+                const float dh1 = q < 4 ? e0[q] : e1[q - 4];
+                const float d1 = F.z1[q] > 0.0f ? dh1 : 0.0f;
+                gb1[q] += d1;
+#pragma unroll
+                for (int k = 0; k < 4; ++k) gW1[q][k] = fmaf(d1, phi[k], gW1[q][k]);
+                D2s[16 * G + j][unit_of(g, q)] = tobf(d2b[q]);
+                H1s[16 * G + j][unit_of(g, q)] = tobf(F.h1[q]);
+            }
+        }
+        __syncthreads();
+        // dW2 += sum over the 32 samples of delta2 h1^T (K = samples)
+#pragma unroll
+        for (int Mt = 0; Mt < 2; ++Mt) {
+            bf16x8 A;
+#pragma unroll
+            for (int q = 0; q < 8; ++q) A[q] = D2s[8 * g + q][16 * Mt + j];
+#pragma unroll
+            for (int Nt = 0; Nt < 2; ++Nt) {
+                bf16x8 Bv;
+#pragma unroll
+                for (int q = 0; q < 8; ++q) Bv[q] = H1s[8 * g + q][16 * Nt + j];
+                acc[Mt][Nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A, Bv, acc[Mt][Nt], 0, 0, 0);
+            }
+        }
+        __syncthreads();
+    }
+
+    // Reduce the per-sample accumulators over the 16 lanes of a unit group.
+    auto red16 = [](float v) {
+#pragma unroll
+        for (int m = 1; m < 16; m <<= 1) v += __shfl_xor(v, m, 64);
+        return v;
+    };
+    float *out = partial + int64_t(blockIdx.x) * (kNParam + 1);
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+        const int u = unit_of(g, q);
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const float v = red16(gW1[q][k]);
+            if (j == 0) out[oW1 + u * 4 + k] = v;
+        }
+        const float vb1 = red16(gb1[q]), vb2 = red16(gb2[q]), vw3 = red16(gW3[q]);
+        if (j == 0) {
+            out[oB1 + u] = vb1;
+            out[oB2 + u] = vb2;
+            out[oW3 + u] = vw3;
+        }
+    }
+    // acc[Mt][Nt][r] = dW2[16 Mt + 4 g + r][16 Nt + j]
+#pragma unroll
+    for (int Mt = 0; Mt < 2; ++Mt)
+#pragma unroll
+        for (int Nt = 0; Nt < 2; ++Nt)
+#pragma unroll
+            for (int r = 0; r < 4; ++r)
+                out[oW2 + (16 * Mt + 4 * g + r) * 32 + 16 * Nt + j] = acc[Mt][Nt][r];
+    float v3 = red16(gb3), vl = red16(loss);
+    v3 += __shfl_xor(v3, 16, 64);
+    v3 += __shfl_xor(v3, 32, 64);
+    vl += __shfl_xor(vl, 16, 64);
+    vl += __shfl_xor(vl, 32, 64);
+    if (lane == 0) {
+        out[oB3] = v3;
+        out[kNParam] = vl;
+    }
+}
+
+__global__ void k_mlp_reduce(const float *__restrict__ partial, int nparts, float *__restrict__ grad,
+                             float *__restrict__ loss_out, float loss_scale) {
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e > kNParam) return;
+    float s = 0.0f;
+    for (int p = 0; p < nparts; ++p) s += partial[int64_t(p) * (kNParam + 1) + e];
+    if (e < kNParam) grad[e] = s;
+    else loss_out[0] = s * loss_scale;
+}
+
+__global__ void k_adam(float *__restrict__ P, float *__restrict__ m, float *__restrict__ v,
+                       const float *__restrict__ grad, float lr, float b1c, float b2c) {
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= kNParam) return;
+    const float gr = grad[e];
+    const float mm = 0.9f * m[e] + 0.1f * gr;
+    const float vv = 0.999f * v[e] + 0.001f * gr * gr;
+    m[e] = mm;
+    v[e] = vv;
+    P[e] -= lr * (mm / b1c) / (sqrtf(vv / b2c) + 1e-8f);
+}
+
+// Forward on explicit features (16 samples per wave).
+__global__ void __launch_bounds__(256)
+k_mlp_forward(const float *__restrict__ P, const float *__restrict__ phi, int64_t count,
+              float *__restrict__ y) {
+    LaneNet N;
+    load_net(N, P);
+    const int lane = threadIdx.x & 63, j = lane & 15, g = lane >> 4;
+    const int64_t wave = (int64_t(blockIdx.x) * blockDim.x + threadIdx.x) >> 6;
+    const int64_t nwaves = (int64_t(gridDim.x) * blockDim.x) >> 6;
+    for (int64_t grp = wave; grp * 16 < count; grp += nwaves) {
+        const int64_t s = grp * 16 + j;
+        const int64_t e = s < count ? s : 0;
+        float f[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) f[k] = bf16r(phi[4 * e + k]);
+        Fwd F;
+        forward(N, f, F);
+        if (g == 0 && s < count) y[s] = F.y;
+    }
+}
+
+// Warm-start inference straight into the schedule-ordered dual array: one
+// workgroup per tile, every slot of the tile (padding gets 0).  The network
+// predicts the dual times n - 2, the number of triplets through a pair: a
+// pair's share of the total pull A'y is spread over n - 2 rows, so this is
+// the scale on which one network serves instances of every size.
+template <typename T>
+__global__ void __launch_bounds__(256)
+k_mlp_infer(GraphView G, const float *__restrict__ P, T *__restrict__ y) {
+    LaneNet N;
+    load_net(N, P);
+    const int lane = threadIdx.x & 63, j = lane & 15, g = lane >> 4;
+    const int wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    const Tile tl = G.tiles[blockIdx.x];
+    const int64_t bb = int64_t(G.b) * G.b;
+    const int64_t nslots = int64_t(tl.Q - tl.P + 1) * G.b * 3 * bb;
+    for (int64_t grp = wave; grp * 16 < nslots; grp += nw) {
+        const int64_t s = tl.ybase + grp * 16 + j;
+        const bool in = grp * 16 + j < nslots;
+        int64_t i, jj, k;
+        int o;
+        const bool ok = in && decode_slot(tl, s, G.b, G.n, i, jj, k, o);
+        float phi[4] = {0.f, 0.f, 0.f, 0.f};
+        if (ok) row_features(G, i, jj, k, o, phi);
+        Fwd F;
+        forward(N, phi, F);
+        if (g == 0 && in) y[s] = ok ? T(F.y / float(G.n - 2)) : T(0);
+    }
+}
+
+// Features of given slots (for checks against the reference).
+__global__ void k_mlp_slot_features(GraphView G, const int64_t *__restrict__ slots, int64_t count,
+                                    float *__restrict__ phi) {
+    for (int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; e < count;
+         e += int64_t(gridDim.x) * blockDim.x) {
+        const int64_t s = slots[e];
+        int64_t lo = 0, hi = G.ntiles - 1;
+        while (lo < hi) {
+            const int64_t mid = (lo + hi + 1) / 2;
+            if (G.tiles[mid].ybase <= s) lo = mid; else hi = mid - 1;
+        }
+        int64_t i, j, k;
+        int o;
+        float f[4] = {0.f, 0.f, 0.f, 0.f};
+        if (decode_slot(G.tiles[lo], s, G.b, G.n, i, j, k, o)) row_features(G, i, j, k, o, f);
+        for (int q = 0; q < 4; ++q) phi[4 * e + q] = f[q];
+    }
+}
+
+__global__ void k_mean_deg(const float *__restrict__ deg, int64_t n, float *__restrict__ out) {
+    __shared__ double red[256];
+    double s = 0.0;
+    for (int64_t v = threadIdx.x; v < n; v += blockDim.x) s += deg[v];
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int h = blockDim.x / 2; h > 0; h >>= 1) {
+        if (threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) out[0] = float(red[0] / double(n));
+}
+
+// ---------------------------------------------------------------------------
+// Launchers.
+// ---------------------------------------------------------------------------
+int mlp_num_params() { return kNParam; }
+int mlp_grad_blocks(int64_t count) {
+    int64_t c = (count + 31) / 32;
+    return int(c < 1 ? 1 : (c > 1024 ? 1024 : c));
+}
+size_t mlp_workspace_bytes(int64_t count) {
+    return size_t(mlp_grad_blocks(count)) * (kNParam + 1) * sizeof(float) +
+           size_t(kNParam + 1) * sizeof(float) + 64;
+}
+
+static int finish_step(float *partial, int nparts, float *P, float *m, float *v, int step, float lr,
+                       float *grad_out, float *ws_grad, float *loss_dev, float loss_scale,
+                       hipStream_t s) {
+    float *grad = grad_out ? grad_out : ws_grad;
+    hipLaunchKernelGGL(k_mlp_reduce, dim3((kNParam + 1 + 255) / 256), dim3(256), 0, s, partial,
+                       nparts, grad, loss_dev, loss_scale);
+    CCP_LAUNCH_CHECK("k_mlp_reduce");
+    if (lr > 0.0f && m && v) {
+        const float b1c = 1.0f - powf(0.9f, float(step));
+        const float b2c = 1.0f - powf(0.999f, float(step));
+        hipLaunchKernelGGL(k_adam, dim3((kNParam + 255) / 256), dim3(256), 0, s, P, m, v, grad,
+                           lr, b1c, b2c);
+        CCP_LAUNCH_CHECK("k_adam");
+    }
+    return CC_OK;
+}
+
+int launch_mlp_train_explicit(const float *phi, const float *target, int64_t count, float *P,
+                              float *m, float *v, int step, float lr, float *grad_out,
+                              void *workspace, float *loss_dev, hipStream_t s) {
+    const int nb = mlp_grad_blocks(count);
+    float *partial = static_cast<float *>(workspace);
+    float *ws_grad = partial + size_t(nb) * (kNParam + 1);
+    ExplicitSource src{phi, target, count};
+    hipLaunchKernelGGL(k_mlp_grad<ExplicitSource>, dim3(nb), dim3(64), 0, s, src, count,
+                       1.0f / float(count), (const float *)P, partial);
+    CCP_LAUNCH_CHECK("k_mlp_grad");
+    return finish_step(partial, nb, P, m, v, step, lr, grad_out, ws_grad, loss_dev,
+                       1.0f / float(count), s);
+}
+
+template <typename T>
+int launch_mlp_train_graph(const GraphView &G, const T *ystar, int64_t slots, uint64_t seed,
+                           int64_t batch, float *P, float *m, float *v, int step, float lr,
+                           void *workspace, float *loss_dev, hipStream_t s) {
+    const int nb = mlp_grad_blocks(batch);
+    float *partial = static_cast<float *>(workspace);
+    float *ws_grad = partial + size_t(nb) * (kNParam + 1);
+    GraphSource<T> src{G, ystar, slots, seed, batch};
+    hipLaunchKernelGGL(k_mlp_grad<GraphSource<T>>, dim3(nb), dim3(64), 0, s, src, batch,
+                       1.0f / float(batch), (const float *)P, partial);
+    CCP_LAUNCH_CHECK("k_mlp_grad");
+    return finish_step(partial, nb, P, m, v, step, lr, nullptr, ws_grad, loss_dev,
+                       1.0f / float(batch), s);
+}
+
+int launch_mlp_forward(const float *P, const float *phi, int64_t count, float *y, hipStream_t s) {
+    if (count <= 0) return CC_OK;
+    int64_t waves = (count + 15) / 16;
+    int64_t blocks = (waves + 3) / 4;
+    if (blocks > 4096) blocks = 4096;
+    hipLaunchKernelGGL(k_mlp_forward, dim3(unsigned(blocks)), dim3(256), 0, s, P, phi, count, y);
+    CCP_LAUNCH_CHECK("k_mlp_forward");
+    return CC_OK;
+}
+
+template <typename T>
+int launch_mlp_infer(const GraphView &G, const float *P, T *y, hipStream_t s) {
+    hipLaunchKernelGGL(k_mlp_infer<T>, dim3(unsigned(G.ntiles)), dim3(256), 0, s, G, P, y);
+    CCP_LAUNCH_CHECK("k_mlp_infer");
+    return CC_OK;
+}
+
+int launch_mlp_slot_features(const GraphView &G, const int64_t *slots, int64_t count, float *phi,
+                             hipStream_t s) {
+    if (count <= 0) return CC_OK;
+    int64_t blocks = (count + 255) / 256;
+    if (blocks > 65536) blocks = 65536;
+    hipLaunchKernelGGL(k_mlp_slot_features, dim3(unsigned(blocks)), dim3(256), 0, s, G, slots, count,
+                       phi);
+    CCP_LAUNCH_CHECK("k_mlp_slot_features");
+    return CC_OK;
+}
+
+int launch_mean_deg(const float *deg, int64_t n, float *out, hipStream_t s) {
+    hipLaunchKernelGGL(k_mean_deg, dim3(1), dim3(256), 0, s, deg, n, out);
+    CCP_LAUNCH_CHECK("k_mean_deg");
+    return CC_OK;
+}
+
+template int launch_mlp_train_graph<double>(const GraphView &, const double *, int64_t, uint64_t,
+                                            int64_t, float *, float *, float *, int, float, void *,
+                                            float *, hipStream_t);
+template int launch_mlp_train_graph<float>(const GraphView &, const float *, int64_t, uint64_t,
+                                           int64_t, float *, float *, float *, int, float, void *,
+                                           float *, hipStream_t);
+template int launch_mlp_infer<double>(const GraphView &, const float *, double *, hipStream_t);
+template int launch_mlp_infer<float>(const GraphView &, const float *, float *, hipStream_t);
+
+}  // namespace ccp

@@ -1,0 +1,150 @@
+"""GPU warm-start network against its float64 reference, and the warm start
+itself (valid start, same optimum, what it gains)."""
+import numpy as np
+import pytest
+
+import oracle
+from conftest import gpu_available
+from oracle import mlp_ref as M
+from paper_1901_10084_amd import instances as I
+
+pytestmark = pytest.mark.gpu
+
+if gpu_available():
+    import torch
+    from paper_1901_10084_amd import ccproj as C
+    from paper_1901_10084_amd import warmstart as W
+
+
+def test_param_count_and_init():
+    assert W.NPARAM == M.NPARAM == 1249
+    p0, p1 = W.init_params(7), W.init_params(7)
+    assert np.array_equal(p0, p1) and np.isfinite(p0).all()
+
+
+@pytest.mark.parametrize("count", [1, 16, 17, 1000, 4099])
+def test_forward_matches_reference(count):
+    rng = np.random.default_rng(count)
+    p = M.init_params(11)
+    phi = rng.normal(0, 1, (count, 4)).astype(np.float32)
+    net = W.Network(params=p)
+    y = net.forward(torch.as_tensor(phi).cuda()).cpu().numpy()
+    yr, _ = M.forward(p, phi)
+    assert np.abs(y - yr).max() <= 1e-3 * max(1.0, np.abs(yr).max()), np.abs(y - yr).max()
+    assert (y >= 0).all()
+
+
+@pytest.mark.parametrize("count", [32, 100, 5000])
+def test_gradient_matches_reference(count):
+    rng = np.random.default_rng(count + 1)
+    p = M.init_params(12)
+    phi = rng.normal(0, 1, (count, 4)).astype(np.float32)
+    t = np.maximum(rng.normal(0.5, 0.5, count), 0).astype(np.float32)
+    net = W.Network(params=p)
+    g = torch.zeros(W.NPARAM, dtype=torch.float32, device="cuda")
+    loss = net.train_step(torch.as_tensor(phi).cuda(), torch.as_tensor(t).cuda(), lr=0.0,
+                          grad_out=g)
+    lr_, gr = M.loss_and_grad(p, phi, t)
+    g = g.cpu().numpy()
+    assert abs(float(loss) - lr_) <= 1e-4 * abs(lr_)
+    err = np.abs(g - gr).max() / np.abs(gr).max()
+    print("grad rel err", err, flush=True)
+    assert err <= 2e-3
+    # per block of parameters too
+    for lo, hi in ((0, 128), (128, 160), (160, 1184), (1184, 1216), (1216, 1248), (1248, 1249)):
+        assert np.abs(g[lo:hi] - gr[lo:hi]).max() <= 2e-3 * max(1e-6, np.abs(gr).max())
+
+
+def test_slot_features_match_reference():
+    inst = I.random_signed(23, seed=2, gamma=1.0, weighted=True)
+    s = C.Solver.from_instance(inst, b=8)
+    deg = W.degrees(inst)
+    slots = torch.arange(s.ctx.slots, device="cuda", dtype=torch.int64)
+    lex = torch.empty_like(slots)
+    s.ctx.slots_to_lex(slots, lex)
+    phi = W.slot_features(s, deg, slots).cpu().numpy()
+    lex = lex.cpu().numpy()
+    valid = lex >= 0
+    assert not phi[~valid].any()
+    t, o = lex[valid] // 3, lex[valid] % 3
+    # colex triplet index -> (i, j, k)
+    k = np.floor(np.cbrt(6.0 * t)).astype(np.int64) + 2
+    while True:
+        over = k * (k - 1) * (k - 2) // 6 > t
+        if not over.any():
+            break
+        k[over] -= 1
+    r = t - k * (k - 1) * (k - 2) // 6
+    j = np.floor(np.sqrt(2.0 * r)).astype(np.int64) + 1
+    while True:
+        over = j * (j - 1) // 2 > r
+        if not over.any():
+            break
+        j[over] -= 1
+    i = r - j * (j - 1) // 2
+    ref = M.bf16(M.features(inst.d, inst.w, inst.deg, i, j, k, o))
+    assert np.allclose(phi[valid], ref, rtol=0, atol=1e-6)
+
+
+def test_training_reduces_loss():
+    rng = np.random.default_rng(3)
+    phi = rng.normal(0, 1, (8192, 4)).astype(np.float32)
+    t = np.maximum(0.5 * phi[:, 0] - 0.3 * phi[:, 1] * phi[:, 2] + 0.2, 0).astype(np.float32)
+    net = W.Network(seed=1)
+    P, T = torch.as_tensor(phi).cuda(), torch.as_tensor(t).cuda()
+    first = float(net.train_step(P, T, lr=3e-3))
+    for _ in range(400):
+        last = float(net.train_step(P, T, lr=3e-3))
+    print("loss", first, "->", last, flush=True)
+    assert last < 0.2 * first
+
+
+def small_trained_network(n_graphs=8):
+    net, hist = W.train(seeds=range(1000, 1000 + n_graphs), tol=1e-5, steps_per_graph=60,
+                        batch=8192, lr=3e-3)
+    return net, hist
+
+
+def test_warm_start_is_valid_and_reaches_the_same_optimum():
+    net, hist = small_trained_network(4)
+    inst = I.training_graph(2000)                     # held out
+    deg = W.degrees(inst)
+    cold = C.Solver.from_instance(inst, b=16)
+    rc, conv_c, _ = cold.solve(tol=1e-6, executor=C.CC_EXEC_DATAFLOW)
+    warm = C.Solver.from_instance(inst, b=16)
+    info = W.warm_start(warm, net, deg)
+    print("warm start", info, flush=True)
+    assert float(warm.y.min()) >= 0.0
+    rw, conv_w, _ = warm.solve(tol=1e-6, executor=C.CC_EXEC_DATAFLOW)
+    assert conv_c and conv_w
+    assert rw["stat_resid"] < 1e-9
+    # unique primal optimum of the QP
+    assert abs(rw["primal_qp"] - rc["primal_qp"]) <= 1e-6 * abs(rc["primal_qp"])
+    assert float((warm.x - cold.x).abs().max()) <= 1e-4
+    print("sweeps to 1e-6: cold", cold.sweeps, "warm", warm.sweeps, flush=True)
+
+
+def test_warm_start_gain_report():
+    """What the trained network gains: sweeps and time to max violation
+    <= 1e-4 in FP32 on held-out graphs, learned start vs cold start."""
+    net, hist = small_trained_network(16)
+    rows = []
+    for seed in (2001, 2002):
+        inst = I.training_graph(seed)
+        deg = W.degrees(inst)
+        cold = C.Solver.from_instance(inst, b=16, prec="f32")
+        rc, cc, tc = cold.solve(tol=1e-4, executor=C.CC_EXEC_DATAFLOW)
+        warm = C.Solver.from_instance(inst, b=16, prec="f32")
+        torch.cuda.synchronize()
+        import time
+        t0 = time.perf_counter()
+        info = W.warm_start(warm, net, deg)
+        rw, cw, tw = warm.solve(tol=1e-4, executor=C.CC_EXEC_DATAFLOW)
+        tw = time.perf_counter() - t0
+        rows.append((seed, info["accepted"], cold.sweeps, warm.sweeps, tc, tw,
+                     rc["primal_qp"], rw["primal_qp"]))
+        assert cc and cw
+        assert abs(rw["primal_qp"] - rc["primal_qp"]) <= 1e-3 * abs(rc["primal_qp"])
+    for r in rows:
+        print("seed %d accepted %s sweeps cold %d warm %d time cold %.4f warm %.4f "
+              "obj %.6f %.6f" % r, flush=True)
