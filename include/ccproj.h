@@ -150,6 +150,13 @@ int cc_sweep(cc_ctx *ctx, void *x, void *f, void *y, void *y_pair, const void *g
  * enqueues only. */
 int cc_sweep_metric(cc_ctx *ctx, void *x, void *y, const void *g, int32_t exec);
 
+/* Diagnostic: one dataflow metric sweep (b = 8, 16, 32) with a time
+ * breakdown summed over all workgroups, in microseconds: out[0] waiting for
+ * the blocks a tile step needs, out[1] loading them into LDS, out[2] the
+ * sub-steps, out[3] publishing; out[4] tile steps run, out[5] workgroups.
+ * Synchronises. */
+int cc_dataflow_breakdown(cc_ctx *ctx, void *x, void *y, const void *g, double *out);
+
 /* Synchronise the context's stream and report a dataflow sweep aborted
  * since the last check (CC_EHIP), else CC_OK. */
 int cc_status(cc_ctx *ctx);

@@ -14,7 +14,7 @@ import numpy as np
 import torch
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libccproj.so")
+LIB_PATH = os.environ.get("CCPROJ_LIB") or os.path.join(_HERE, "libccproj.so")
 
 if not os.path.exists(LIB_PATH):
     raise ImportError(f"{LIB_PATH} is missing: build it with paper_1901_10084_amd/build.py")
@@ -67,6 +67,7 @@ _sig("cc_sweep", ctypes.c_int, _p, _p, _p, _p, _p, _p, _p, _i32, _i32)
 _sig("cc_sweep_rounds", ctypes.c_int, _p, _p, _p, _p, _i32, _i32)
 _sig("cc_sweep_metric", ctypes.c_int, _p, _p, _p, _p, _i32)
 _sig("cc_status", ctypes.c_int, _p)
+_sig("cc_dataflow_breakdown", ctypes.c_int, _p, _p, _p, _p, ctypes.POINTER(_dbl))
 _sig("cc_pair_pass", ctypes.c_int, _p, _p, _p, _p, _p, _p)
 _sig("cc_residuals", ctypes.c_int, _p, _p, _p, _p, _p, _p, _p, _dbl, _i32,
      ctypes.POINTER(Resid))
@@ -183,6 +184,12 @@ class Context:
 
     def status(self):
         check(_L.cc_status(self._h))
+
+    def dataflow_breakdown(self, x, y, g):
+        out = (_dbl * 8)()
+        check(_L.cc_dataflow_breakdown(self._h, _ptr(x), _ptr(y), _ptr(g), out))
+        keys = ("wait_us", "load_us", "substeps_us", "publish_us", "tile_steps", "workgroups")
+        return {k: out[e] for e, k in enumerate(keys)}
 
     def pair_pass(self, x, f, y_pair, g, d):
         check(_L.cc_pair_pass(self._h, _ptr(x), _ptr(f), _ptr(y_pair), _ptr(g), _ptr(d)))

@@ -50,6 +50,7 @@ struct DataflowArgs {
     uint32_t *ctl;
     uint32_t epoch;
     uint64_t wait_ticks;
+    unsigned long long *prof;
 };
 void build_dataflow_tables(int64_t n, int b, std::vector<DTile> &tiles, std::vector<uint32_t> &needs,
                            std::vector<uint32_t> &K);
@@ -223,14 +224,14 @@ int ensure_dataflow(cc_ctx *c) {
 }
 
 template <typename T>
-int sweep_metric_t(cc_ctx *c, T *x, T *y, const T *g, int exec);
+int sweep_metric_t(cc_ctx *c, T *x, T *y, const T *g, int exec, unsigned long long *prof);
 
 template <typename T>
 int sweep_dataflow_t(cc_ctx *c, T *x, T *f, T *y, T *yp, const T *g, const uint8_t *d,
                      int nsweeps) {
     int rc;
     for (int s = 0; s < nsweeps; ++s) {
-        if ((rc = sweep_metric_t<T>(c, x, y, g, CC_EXEC_DATAFLOW))) return rc;
+        if ((rc = sweep_metric_t<T>(c, x, y, g, CC_EXEC_DATAFLOW, nullptr))) return rc;
         if ((rc = launch_pair_pass<T>(num_pairs(c->n), x, f, yp, g, d, c->stream))) return rc;
     }
     return CC_OK;
@@ -253,7 +254,7 @@ int check_dataflow(cc_ctx *c) {
 }
 
 template <typename T>
-int sweep_metric_t(cc_ctx *c, T *x, T *y, const T *g, int exec) {
+int sweep_metric_t(cc_ctx *c, T *x, T *y, const T *g, int exec, unsigned long long *prof) {
     if (exec == CC_EXEC_ROUNDS) return sweep_rounds_t<T>(c, x, y, g, 0, c->nrounds);
     int rc = ensure_dataflow(c);
     if (rc) return rc;
@@ -262,7 +263,7 @@ int sweep_metric_t(cc_ctx *c, T *x, T *y, const T *g, int exec) {
         c->epoch = 0;
     }
     DataflowArgs a{c->d_dtiles, int(c->ntiles), c->d_needs, c->d_K, c->d_cnt, c->d_ctl,
-                   c->epoch, c->wait_ticks};
+                   c->epoch, c->wait_ticks, prof};
     if ((rc = launch_sweep_dataflow<T>(a, c->df_grid, c->b, c->n, x, g, y, c->stream))) return rc;
     c->epoch++;
     return CC_OK;
@@ -469,8 +470,35 @@ int cc_sweep_metric(cc_ctx *c, void *x, void *y, const void *g, int32_t exec) {
     if ((rc = check_ctx(c)) || (rc = need(x, "x")) || (rc = need(y, "y")) || (rc = need(g, "g")))
         return rc;
     if (exec != CC_EXEC_ROUNDS && exec != CC_EXEC_DATAFLOW) return fail(CC_EINVAL, "unknown executor");
-    if (c->prec == CC_F64) return sweep_metric_t<double>(c, (double *)x, (double *)y, (const double *)g, exec);
-    return sweep_metric_t<float>(c, (float *)x, (float *)y, (const float *)g, exec);
+    if (c->prec == CC_F64) return sweep_metric_t<double>(c, (double *)x, (double *)y, (const double *)g, exec, nullptr);
+    return sweep_metric_t<float>(c, (float *)x, (float *)y, (const float *)g, exec, nullptr);
+}
+
+int cc_dataflow_breakdown(cc_ctx *c, void *x, void *y, const void *g, double *out) {
+    int rc;
+    if ((rc = check_ctx(c)) || (rc = need(x, "x")) || (rc = need(y, "y")) || (rc = need(g, "g")) ||
+        (rc = need(out, "out")))
+        return rc;
+    DevTmp t;
+    if ((rc = t.alloc(8 * sizeof(unsigned long long)))) return rc;
+    CCP_HIP_CHECK(hipMemsetAsync(t.p, 0, 8 * sizeof(unsigned long long), c->stream));
+    unsigned long long *prof = (unsigned long long *)t.p;
+    rc = (c->prec == CC_F64)
+             ? sweep_metric_t<double>(c, (double *)x, (double *)y, (const double *)g, CC_EXEC_DATAFLOW, prof)
+             : sweep_metric_t<float>(c, (float *)x, (float *)y, (const float *)g, CC_EXEC_DATAFLOW, prof);
+    if (rc) return rc;
+    unsigned long long h[8];
+    CCP_HIP_CHECK(hipMemcpyAsync(h, prof, sizeof(h), hipMemcpyDeviceToHost, c->stream));
+    CCP_HIP_CHECK(hipStreamSynchronize(c->stream));
+    if ((rc = check_dataflow(c))) return rc;
+    int dev = 0, khz = 0;
+    CCP_HIP_CHECK(hipGetDevice(&dev));
+    CCP_HIP_CHECK(hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev));
+    const double us = 1e3 / double(khz > 0 ? khz : 100000);
+    for (int e = 0; e < 4; ++e) out[e] = double(h[e]) * us;
+    out[4] = double(h[4]);
+    out[5] = double(c->df_grid);
+    return CC_OK;
 }
 
 int cc_status(cc_ctx *c) {

@@ -88,6 +88,7 @@ struct DataflowArgs {
     uint32_t *ctl;       // [0] ticket counter, [1] abort flag
     uint32_t epoch;      // sweeps already run on these counters
     uint64_t wait_ticks; // wall-clock limit of one wait
+    unsigned long long *prof;  // optional: wall-clock ticks per phase, summed
 };
 
 // Thread 0 only.  True once cnt >= need; false on time-out or abort.
@@ -127,6 +128,18 @@ k_sweep_dataflow(DataflowArgs a, int64_t n, T *__restrict__ x, const T *__restri
     // (readfirstlane) before it steers a branch.  Branches around barriers
     // must be uniform; otherwise the compiler may merge thread-0 regions
     // across a loop back-edge and split a wave's lanes between barriers.
+    //
+    // Per tile step: sub-steps, publish the step's blocks, then one thread-0
+    // region that releases them and waits for the next step's blocks.  The
+    // dual ring is refilled for the next step only after that release, so
+    // the release's drain of the memory counter (agent-scope release waits
+    // for every outstanding access of the wave) covers the published stores
+    // rather than a full ring of prefetched duals.
+    //
+    // optional breakdown (thread 0): [0] waiting for blocks, [1] loading
+    // blocks into LDS, [2] sub-steps, [3] publishing, [4] tile steps
+    uint64_t pt[5] = {0, 0, 0, 0, 0};
+    uint64_t tmark = 0;
     if (tid == 0) s_tix = int(atomicAdd(&a.ctl[0], 1u));
     __syncthreads();
     for (;;) {
@@ -150,26 +163,53 @@ k_sweep_dataflow(DataflowArgs a, int64_t n, T *__restrict__ x, const T *__restri
             p = ok ? pidx(jj, kk) : 0;
             return ok;
         };
+        // blocks (P,J) and (J,Q) of step m, -1 where the step uses (P,Q)
+        auto step_ids = [&](int m, int &idA, int &idB) {
+            const int J = tile_J(P, Q, m, desc);
+            idA = (J != Q) ? block_id(P, J) : -1;
+            idB = (J != P) ? block_id(J, Q) : -1;
+        };
+        // thread 0: wait until step m's blocks have all earlier touches
+        auto wait_step = [&](int m) {
+            int idA, idB;
+            step_ids(m, idA, idB);
+            const uint32_t *nd = a.needs + 2 * int64_t(tl.jsbase + m);
+            bool ok = true;
+            if (idA >= 0)
+                ok = wait_count(&a.cnt[idA], a.epoch * a.K[idA] + nd[0], &a.ctl[1], a.wait_ticks);
+            if (ok && idB >= 0)
+                ok = wait_count(&a.cnt[idB], a.epoch * a.K[idB] + nd[1], &a.ctl[1], a.wait_ticks);
+            return ok;
+        };
 
-        // Duals are private to the tile: start their stream at once.
         const int U = (Q - P + 1) * b;
         T *const ylane = y + tl.ybase + tid;
         const int64_t ystep = int64_t(3) * bb;
         T yq[D][3];
+        // ring: the first D sub-steps of step m (all inside the step, D | b)
+        auto fill_ring = [&](int m) {
 #pragma unroll
-        for (int d = 0; d < D; ++d) {
-            const T *src = ylane + int64_t(d < U ? d : U - 1) * ystep;
-            yq[d][0] = src[0];
-            yq[d][1] = src[bb];
-            yq[d][2] = src[2 * bb];
-        }
+            for (int d = 0; d < D; ++d) {
+                const T *src = ylane + int64_t(m * b + d) * ystep;
+                yq[d][0] = src[0];
+                yq[d][1] = src[bb];
+                yq[d][2] = src[2 * bb];
+            }
+        };
+        fill_ring(0);
 
-        // Block (P,Q): wait for its earlier touches, then hold it.
+        // Block (P,Q) and the first step's blocks: wait, then hold (P,Q).
         if (tid == 0) {
-            const bool ok =
-                wait_count(&a.cnt[idC], a.epoch * a.K[idC] + tl.needC, &a.ctl[1], a.wait_ticks);
+            if (a.prof) tmark = wall_clock64();
+            bool ok = wait_count(&a.cnt[idC], a.epoch * a.K[idC] + tl.needC, &a.ctl[1], a.wait_ticks);
+            ok = ok && wait_step(0);
             if (ok) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
             s_ok = ok;
+            if (a.prof) {
+                const uint64_t t1 = wall_clock64();
+                pt[0] += t1 - tmark;
+                tmark = t1;
+            }
         }
         __syncthreads();
         if (!__builtin_amdgcn_readfirstlane(s_ok)) break;
@@ -183,26 +223,12 @@ k_sweep_dataflow(DataflowArgs a, int64_t n, T *__restrict__ x, const T *__restri
         bool aborted = false;
         for (int m = 0; m <= Q - P; ++m) {
             const int J = tile_J(P, Q, m, desc);
-            const int idA = (J != Q) ? block_id(P, J) : -1;
-            const int idB = (J != P) ? block_id(J, Q) : -1;
+            int idA, idB;
+            step_ids(m, idA, idB);
             XG<T> *const As = (J == Q) ? Cs : lds;
             XG<T> *const Bs = (J == P) ? Cs : lds + 2 * bb;
 
-            if (tid == 0) {
-                const uint32_t *nd = a.needs + 2 * int64_t(tl.jsbase + m);
-                bool ok = true;
-                if (idA >= 0)
-                    ok = wait_count(&a.cnt[idA], a.epoch * a.K[idA] + nd[0], &a.ctl[1], a.wait_ticks);
-                if (ok && idB >= 0)
-                    ok = wait_count(&a.cnt[idB], a.epoch * a.K[idB] + nd[1], &a.ctl[1], a.wait_ticks);
-                if (ok && (idA >= 0 || idB >= 0)) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-                s_ok = ok;
-            }
-            __syncthreads();
-            if (!__builtin_amdgcn_readfirstlane(s_ok)) {
-                aborted = true;
-                break;
-            }
+            // Stage the step's blocks (their waits are done).
             int64_t pa = 0, pbp = 0;
             const bool aok = idA >= 0 && a_pair(J, pa);
             const bool bok = idB >= 0 && b_pair(J, pbp);
@@ -215,6 +241,11 @@ k_sweep_dataflow(DataflowArgs a, int64_t n, T *__restrict__ x, const T *__restri
                 Bs[tid] = XG<T>{bok ? vx : T(0), bok ? vg : T(0)};
             }
             lds_barrier();
+            if (tid == 0 && a.prof) {
+                const uint64_t t1 = wall_clock64();
+                pt[1] += t1 - tmark;
+                tmark = t1;
+            }
 
             auto qof = [&](int t) {
                 const int jl = mid_offset(t, il, kl, b);
@@ -222,6 +253,7 @@ k_sweep_dataflow(DataflowArgs a, int64_t n, T *__restrict__ x, const T *__restri
                 return recip<T>(s > T(0) ? s : T(1));
             };
             T qn = qof(0);
+            const int ulast = m * b + b - 1;
             for (int t0 = 0; t0 < b; t0 += D) {
 #pragma unroll
                 for (int d = 0; d < D; ++d) {
@@ -229,7 +261,9 @@ k_sweep_dataflow(DataflowArgs a, int64_t n, T *__restrict__ x, const T *__restri
                     const int u = m * b + t;
                     T y0 = yq[d][0], y1 = yq[d][1], y2 = yq[d][2];
                     {
-                        const int un = u + D < U ? u + D : U - 1;
+                        // prefetch inside this step only (the last D sub-steps
+                        // reload a slot of the step; the value is not used)
+                        const int un = u + D <= ulast ? u + D : ulast;
                         const T *src = ylane + int64_t(un) * ystep;
                         yq[d][0] = src[0];
                         yq[d][1] = src[bb];
@@ -258,29 +292,56 @@ k_sweep_dataflow(DataflowArgs a, int64_t n, T *__restrict__ x, const T *__restri
                     lds_barrier();
                 }
             }
+            if (tid == 0 && a.prof) {
+                const uint64_t t1 = wall_clock64();
+                pt[2] += t1 - tmark;
+                tmark = t1;
+            }
 
-            // Publish this step's (P,J) and (J,Q) blocks.
+            // Publish this step's (P,J) and (J,Q) blocks (and (P,Q) after the
+            // last step); release them; wait for the next step's blocks.
+            const bool last = (m == Q - P);
             if (aok) x[pa] = As[tid].x;
             if (bok) x[pbp] = Bs[tid].x;
+            if (last && c_ok) x[pc] = Cs[tid].x;
             __syncthreads();
             if (tid == 0) {
                 if (idA >= 0) __hip_atomic_fetch_add(&a.cnt[idA], 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
                 if (idB >= 0) __hip_atomic_fetch_add(&a.cnt[idB], 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+                bool ok = true;
+                if (last) {
+                    __hip_atomic_fetch_add(&a.cnt[idC], uint32_t(Q - P + 1), __ATOMIC_RELEASE,
+                                           __HIP_MEMORY_SCOPE_AGENT);
+                    s_tix = int(atomicAdd(&a.ctl[0], 1u));
+                }
+                if (a.prof) {
+                    const uint64_t t1 = wall_clock64();
+                    pt[3] += t1 - tmark;
+                    pt[4] += 1;
+                    tmark = t1;
+                }
+                if (!last) {
+                    ok = wait_step(m + 1);
+                    if (ok) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+                    if (a.prof) {
+                        const uint64_t t1 = wall_clock64();
+                        pt[0] += t1 - tmark;
+                        tmark = t1;
+                    }
+                }
+                s_ok = ok;
             }
             __syncthreads();
+            if (!__builtin_amdgcn_readfirstlane(s_ok)) {
+                aborted = true;
+                break;
+            }
+            if (!last) fill_ring(m + 1);
         }
         if (aborted) break;
-
-        // Publish block (P,Q), then take the next ticket.
-        if (c_ok) x[pc] = Cs[tid].x;
-        __syncthreads();
-        if (tid == 0) {
-            __hip_atomic_fetch_add(&a.cnt[idC], uint32_t(Q - P + 1), __ATOMIC_RELEASE,
-                                   __HIP_MEMORY_SCOPE_AGENT);
-            s_tix = int(atomicAdd(&a.ctl[0], 1u));
-        }
-        __syncthreads();
     }
+    if (tid == 0 && a.prof)
+        for (int e = 0; e < 5; ++e) atomicAdd(&a.prof[e], (unsigned long long)pt[e]);
 }
 
 __global__ void k_dataflow_reset(uint32_t *ctl) {
