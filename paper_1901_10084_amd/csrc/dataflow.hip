@@ -138,8 +138,16 @@ k_sweep_dataflow(DataflowArgs a, int64_t n, T *__restrict__ x, const T *__restri
     //
     // optional breakdown (thread 0): [0] waiting for blocks, [1] loading
     // blocks into LDS, [2] sub-steps, [3] publishing, [4] tile steps
-    uint64_t pt[5] = {0, 0, 0, 0, 0};
-    uint64_t tmark = 0;
+    // kept in LDS: per-thread 64-bit counters would hold registers for the
+    // whole kernel
+    __shared__ uint64_t s_pt[6];  // [0..4] as above, [5] the last mark
+    auto mark = [&](int e) {      // thread 0 only
+        const uint64_t t1 = wall_clock64();
+        s_pt[e] += t1 - s_pt[5];
+        s_pt[5] = t1;
+    };
+    if (tid == 0)
+        for (int e = 0; e < 6; ++e) s_pt[e] = 0;
     if (tid == 0) s_tix = int(atomicAdd(&a.ctl[0], 1u));
     __syncthreads();
     for (;;) {
@@ -182,34 +190,33 @@ k_sweep_dataflow(DataflowArgs a, int64_t n, T *__restrict__ x, const T *__restri
             return ok;
         };
 
-        const int U = (Q - P + 1) * b;
-        T *const ylane = y + tl.ybase + tid;
+        // Dual addresses: a wave-uniform base per sub-step plus a 32-bit
+        // lane offset, so the accesses take a scalar base register.  Each
+        // dual is read and written once per sweep: non-temporal accesses.
+        T *const ytile = y + tl.ybase;
         const int64_t ystep = int64_t(3) * bb;
+        const unsigned lane = unsigned(tid);
         T yq[D][3];
         // ring: the first D sub-steps of step m (all inside the step, D | b)
         auto fill_ring = [&](int m) {
 #pragma unroll
             for (int d = 0; d < D; ++d) {
-                const T *src = ylane + int64_t(m * b + d) * ystep;
-                yq[d][0] = src[0];
-                yq[d][1] = src[bb];
-                yq[d][2] = src[2 * bb];
+                const T *src = ytile + int64_t(m * b + d) * ystep;
+                yq[d][0] = __builtin_nontemporal_load(&src[lane]);
+                yq[d][1] = __builtin_nontemporal_load(&src[lane + bb]);
+                yq[d][2] = __builtin_nontemporal_load(&src[lane + 2 * bb]);
             }
         };
         fill_ring(0);
 
         // Block (P,Q) and the first step's blocks: wait, then hold (P,Q).
         if (tid == 0) {
-            if (a.prof) tmark = wall_clock64();
+            if (a.prof) s_pt[5] = wall_clock64();
             bool ok = wait_count(&a.cnt[idC], a.epoch * a.K[idC] + tl.needC, &a.ctl[1], a.wait_ticks);
             ok = ok && wait_step(0);
             if (ok) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
             s_ok = ok;
-            if (a.prof) {
-                const uint64_t t1 = wall_clock64();
-                pt[0] += t1 - tmark;
-                tmark = t1;
-            }
+            if (a.prof) mark(0);
         }
         __syncthreads();
         if (!__builtin_amdgcn_readfirstlane(s_ok)) break;
@@ -241,11 +248,7 @@ k_sweep_dataflow(DataflowArgs a, int64_t n, T *__restrict__ x, const T *__restri
                 Bs[tid] = XG<T>{bok ? vx : T(0), bok ? vg : T(0)};
             }
             lds_barrier();
-            if (tid == 0 && a.prof) {
-                const uint64_t t1 = wall_clock64();
-                pt[1] += t1 - tmark;
-                tmark = t1;
-            }
+            if (tid == 0 && a.prof) mark(1);
 
             auto qof = [&](int t) {
                 const int jl = mid_offset(t, il, kl, b);
@@ -254,49 +257,68 @@ k_sweep_dataflow(DataflowArgs a, int64_t n, T *__restrict__ x, const T *__restri
             };
             T qn = qof(0);
             const int ulast = m * b + b - 1;
-            for (int t0 = 0; t0 < b; t0 += D) {
+            // D sub-steps, one per ring slot.  The first group is peeled off
+            // the loop so that the loop is entered with the ring in the
+            // state it has at every later iteration; the compiler's memory
+            // waits at the loop head are then exact (a wait of 6D-3 accesses
+            // per slot) rather than those of a freshly filled ring.
+            auto group = [&](const int t0) {
 #pragma unroll
                 for (int d = 0; d < D; ++d) {
                     const int t = t0 + d;
                     const int u = m * b + t;
                     T y0 = yq[d][0], y1 = yq[d][1], y2 = yq[d][2];
-                    {
-                        // prefetch inside this step only (the last D sub-steps
-                        // reload a slot of the step; the value is not used)
-                        const int un = u + D <= ulast ? u + D : ulast;
-                        const T *src = ylane + int64_t(un) * ystep;
-                        yq[d][0] = src[0];
-                        yq[d][1] = src[bb];
-                        yq[d][2] = src[2 * bb];
-                    }
                     const T q = qn;
                     if (t + 1 < b) qn = qof(t + 1);
                     const int jl = mid_offset(t, il, kl, b);
                     const int j = J * b + jl;
-                    if (i < j && j < k && k < nn) {
+                    {
+                        // Every lane runs the step; a lane whose (i,j,k) is
+                        // padding takes q = 0 and floor -inf, which leaves its
+                        // dual and the three distances exactly as read.  Only
+                        // triplet lanes write the distances back: where the
+                        // middle block is P or Q, the A or B block is the
+                        // resident (P,Q) block, and a padding lane's entry can
+                        // be a triplet lane's entry of the same sub-step.
+                        const bool ok = i < j && j < k && k < nn;
+                        const T qm = ok ? q : T(0);
+                        const T floor_ = ok ? T(0) : T(-__builtin_huge_val());
                         XG<T> ea = As[il * b + jl];
                         XG<T> eb = Bs[jl * b + kl];
                         XG<T> ec = Cs[tid];
                         T xa = ea.x, xb = eb.x, xc = ec.x;
-                        project(xa, xc, xb, ea.g, ec.g, eb.g, q, y0);
-                        project(xc, xa, xb, ec.g, ea.g, eb.g, q, y1);
-                        project(xb, xa, xc, eb.g, ea.g, ec.g, q, y2);
-                        As[il * b + jl].x = xa;
-                        Bs[jl * b + kl].x = xb;
-                        Cs[tid].x = xc;
+                        project_lo(xa, xc, xb, ea.g, ec.g, eb.g, qm, floor_, y0);
+                        project_lo(xc, xa, xb, ec.g, ea.g, eb.g, qm, floor_, y1);
+                        project_lo(xb, xa, xc, eb.g, ea.g, ec.g, qm, floor_, y2);
+                        if (ok) {
+                            As[il * b + jl].x = xa;
+                            Bs[jl * b + kl].x = xb;
+                            Cs[tid].x = xc;
+                        }
                     }
-                    T *dst = ylane + int64_t(u) * ystep;
-                    dst[0] = y0;
-                    dst[bb] = y1;
-                    dst[2 * bb] = y2;
+                    T *dst = ytile + int64_t(__builtin_amdgcn_readfirstlane(u)) * ystep;
+                    __builtin_nontemporal_store(y0, &dst[lane]);
+                    __builtin_nontemporal_store(y1, &dst[lane + bb]);
+                    __builtin_nontemporal_store(y2, &dst[lane + 2 * bb]);
+                    {
+                        // Refill slot d after its duals are consumed, so the
+                        // old and new values never live at once (no register
+                        // copies of loads in flight).  Prefetch stays inside
+                        // the step: the last D sub-steps reload a slot of the
+                        // step, whose value is not used.
+                        const int un = u + D <= ulast ? u + D : ulast;
+                        const T *src = ytile + int64_t(un) * ystep;
+                        yq[d][0] = __builtin_nontemporal_load(&src[lane]);
+                        yq[d][1] = __builtin_nontemporal_load(&src[lane + bb]);
+                        yq[d][2] = __builtin_nontemporal_load(&src[lane + 2 * bb]);
+                    }
                     lds_barrier();
                 }
-            }
-            if (tid == 0 && a.prof) {
-                const uint64_t t1 = wall_clock64();
-                pt[2] += t1 - tmark;
-                tmark = t1;
-            }
+            };
+            group(0);
+#pragma nounroll
+            for (int t0 = D; t0 < b; t0 += D) group(t0);
+            if (tid == 0 && a.prof) mark(2);
 
             // Publish this step's (P,J) and (J,Q) blocks (and (P,Q) after the
             // last step); release them; wait for the next step's blocks.
@@ -306,28 +328,28 @@ k_sweep_dataflow(DataflowArgs a, int64_t n, T *__restrict__ x, const T *__restri
             if (last && c_ok) x[pc] = Cs[tid].x;
             __syncthreads();
             if (tid == 0) {
-                if (idA >= 0) __hip_atomic_fetch_add(&a.cnt[idA], 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-                if (idB >= 0) __hip_atomic_fetch_add(&a.cnt[idB], 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+                // One release fence covers every block of the step; the
+                // counter increments after it are relaxed (a release fence
+                // before an atomic write synchronises with the reader's
+                // acquire fence).  Each release-ordered atomic would repeat
+                // the L2 write-back and the drain.
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+                if (idA >= 0) __hip_atomic_fetch_add(&a.cnt[idA], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                if (idB >= 0) __hip_atomic_fetch_add(&a.cnt[idB], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                 bool ok = true;
                 if (last) {
-                    __hip_atomic_fetch_add(&a.cnt[idC], uint32_t(Q - P + 1), __ATOMIC_RELEASE,
+                    __hip_atomic_fetch_add(&a.cnt[idC], uint32_t(Q - P + 1), __ATOMIC_RELAXED,
                                            __HIP_MEMORY_SCOPE_AGENT);
                     s_tix = int(atomicAdd(&a.ctl[0], 1u));
                 }
                 if (a.prof) {
-                    const uint64_t t1 = wall_clock64();
-                    pt[3] += t1 - tmark;
-                    pt[4] += 1;
-                    tmark = t1;
+                    mark(3);
+                    s_pt[4] += 1;
                 }
                 if (!last) {
                     ok = wait_step(m + 1);
                     if (ok) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-                    if (a.prof) {
-                        const uint64_t t1 = wall_clock64();
-                        pt[0] += t1 - tmark;
-                        tmark = t1;
-                    }
+                    if (a.prof) mark(0);
                 }
                 s_ok = ok;
             }
@@ -341,7 +363,7 @@ k_sweep_dataflow(DataflowArgs a, int64_t n, T *__restrict__ x, const T *__restri
         if (aborted) break;
     }
     if (tid == 0 && a.prof)
-        for (int e = 0; e < 5; ++e) atomicAdd(&a.prof[e], (unsigned long long)pt[e]);
+        for (int e = 0; e < 5; ++e) atomicAdd(&a.prof[e], (unsigned long long)s_pt[e]);
 }
 
 __global__ void k_dataflow_reset(uint32_t *ctl) {
