@@ -114,13 +114,23 @@ k_sweep_dataflow(DataflowArgs a, int64_t n, T *__restrict__ x, const T *__restri
     constexpr int b = B;
     constexpr int bb = B * B;
     const int tid = threadIdx.x;
+    // sub-step lane (il, kl); its dual slot is il*b + kl
     const int il = tid / b, kl = tid % b;
+    // stage/publish element (sr, sc) of a block: the row index runs fastest
+    // across threads, so the accesses are contiguous in the packed upper
+    // triangle
+    const int sr = tid % b, sc = tid / b;
     const int nn = int(n);
     const int nb = (nn + b - 1) / b;
 
+    // LDS: x and g of blocks A = (P,J), B = (J,Q) and C = (P,Q) in separate
+    // arrays, each row-major [row*b + col].  With 4-byte elements every
+    // sub-step access is free of bank conflicts; only the transposing
+    // stage/publish accesses conflict, once per tile step.
     extern __shared__ __align__(16) unsigned char smem_raw[];
-    XG<T> *lds = reinterpret_cast<XG<T> *>(smem_raw);
-    XG<T> *const Cs = lds + 4 * bb;
+    T *const lds = reinterpret_cast<T *>(smem_raw);
+    T *const Ax0 = lds, *const Ag0 = lds + bb, *const Bx0 = lds + 2 * bb, *const Bg0 = lds + 3 * bb;
+    T *const Cx = lds + 4 * bb, *const Cg = lds + 5 * bb;
     __shared__ int s_tix, s_ok;
 
     // Control structure: every `if (tid == 0)` region is closed by a
@@ -159,17 +169,19 @@ k_sweep_dataflow(DataflowArgs a, int64_t n, T *__restrict__ x, const T *__restri
         const int i = P * b + il, k = Q * b + kl;
         const int idC = block_id(P, Q);
 
-        auto a_pair = [&](int J, int64_t &p) {
-            const int ii = P * b + il, jj = J * b + kl;
+        // element (sr, sc) of block (R, S): pair (R*b+sr, S*b+sc) when it is one
+        // (zeros elsewhere); the loads are unconditional
+        auto stage = [&](int R, int S, T *X, T *G) {
+            const int ii = R * b + sr, jj = S * b + sc;
             const bool ok = ii < jj && jj < nn;
-            p = ok ? pidx(ii, jj) : 0;
-            return ok;
+            const int64_t p = ok ? pidx(ii, jj) : 0;
+            const T vx = x[p], vg = g[p];
+            X[sr * b + sc] = ok ? vx : T(0);
+            G[sr * b + sc] = ok ? vg : T(0);
         };
-        auto b_pair = [&](int J, int64_t &p) {
-            const int jj = J * b + il, kk = Q * b + kl;
-            const bool ok = jj < kk && kk < nn;
-            p = ok ? pidx(jj, kk) : 0;
-            return ok;
+        auto publish = [&](int R, int S, const T *X) {
+            const int ii = R * b + sr, jj = S * b + sc;
+            if (ii < jj && jj < nn) x[pidx(ii, jj)] = X[sr * b + sc];
         };
         // blocks (P,J) and (J,Q) of step m, -1 where the step uses (P,Q)
         auto step_ids = [&](int m, int &idA, int &idB) {
@@ -220,42 +232,34 @@ k_sweep_dataflow(DataflowArgs a, int64_t n, T *__restrict__ x, const T *__restri
         }
         __syncthreads();
         if (!__builtin_amdgcn_readfirstlane(s_ok)) break;
-        const bool c_ok = (i < k) && (k < nn);
-        const int64_t pc = c_ok ? pidx(i, k) : 0;
-        {
-            const T cx = x[pc], cg = g[pc];
-            Cs[tid] = XG<T>{c_ok ? cx : T(0), c_ok ? cg : T(0)};
-        }
+        stage(P, Q, Cx, Cg);
 
         bool aborted = false;
         for (int m = 0; m <= Q - P; ++m) {
             const int J = tile_J(P, Q, m, desc);
             int idA, idB;
             step_ids(m, idA, idB);
-            XG<T> *const As = (J == Q) ? Cs : lds;
-            XG<T> *const Bs = (J == P) ? Cs : lds + 2 * bb;
+            // A or B is the resident C block where the middle block is Q or P
+            T *const Ax = (J == Q) ? Cx : Ax0, *const Ag = (J == Q) ? Cg : Ag0;
+            T *const Bx = (J == P) ? Cx : Bx0, *const Bg = (J == P) ? Cg : Bg0;
 
             // Stage the step's blocks (their waits are done).
-            int64_t pa = 0, pbp = 0;
-            const bool aok = idA >= 0 && a_pair(J, pa);
-            const bool bok = idB >= 0 && b_pair(J, pbp);
-            if (idA >= 0) {
-                const T vx = x[pa], vg = g[pa];
-                As[tid] = XG<T>{aok ? vx : T(0), aok ? vg : T(0)};
-            }
-            if (idB >= 0) {
-                const T vx = x[pbp], vg = g[pbp];
-                Bs[tid] = XG<T>{bok ? vx : T(0), bok ? vg : T(0)};
-            }
+            if (idA >= 0) stage(P, J, Ax0, Ag0);
+            if (idB >= 0) stage(J, Q, Bx0, Bg0);
             lds_barrier();
+            const T gC = Cg[tid];
             if (tid == 0 && a.prof) mark(1);
 
-            auto qof = [&](int t) {
+            // q of sub-step t (1 / sum of the three g), with the g of A and B
+            auto gq = [&](int t, T &ga, T &gb) {
                 const int jl = mid_offset(t, il, kl, b);
-                const T s = (As[il * b + jl].g + Cs[tid].g) + Bs[jl * b + kl].g;
+                ga = Ag[il * b + jl];
+                gb = Bg[jl * b + kl];
+                const T s = (ga + gC) + gb;
                 return recip<T>(s > T(0) ? s : T(1));
             };
-            T qn = qof(0);
+            T gan, gbn;
+            T qn = gq(0, gan, gbn);
             const int ulast = m * b + b - 1;
             // D sub-steps, one per ring slot.  The first group is peeled off
             // the loop so that the loop is entered with the ring in the
@@ -268,8 +272,8 @@ k_sweep_dataflow(DataflowArgs a, int64_t n, T *__restrict__ x, const T *__restri
                     const int t = t0 + d;
                     const int u = m * b + t;
                     T y0 = yq[d][0], y1 = yq[d][1], y2 = yq[d][2];
-                    const T q = qn;
-                    if (t + 1 < b) qn = qof(t + 1);
+                    const T q = qn, ga = gan, gb = gbn;
+                    if (t + 1 < b) qn = gq(t + 1, gan, gbn);
                     const int jl = mid_offset(t, il, kl, b);
                     const int j = J * b + jl;
                     {
@@ -283,17 +287,14 @@ k_sweep_dataflow(DataflowArgs a, int64_t n, T *__restrict__ x, const T *__restri
                         const bool ok = i < j && j < k && k < nn;
                         const T qm = ok ? q : T(0);
                         const T floor_ = ok ? T(0) : T(-__builtin_huge_val());
-                        XG<T> ea = As[il * b + jl];
-                        XG<T> eb = Bs[jl * b + kl];
-                        XG<T> ec = Cs[tid];
-                        T xa = ea.x, xb = eb.x, xc = ec.x;
-                        project_lo(xa, xc, xb, ea.g, ec.g, eb.g, qm, floor_, y0);
-                        project_lo(xc, xa, xb, ec.g, ea.g, eb.g, qm, floor_, y1);
-                        project_lo(xb, xa, xc, eb.g, ea.g, ec.g, qm, floor_, y2);
+                        T xa = Ax[il * b + jl], xb = Bx[jl * b + kl], xc = Cx[tid];
+                        project_lo(xa, xc, xb, ga, gC, gb, qm, floor_, y0);
+                        project_lo(xc, xa, xb, gC, ga, gb, qm, floor_, y1);
+                        project_lo(xb, xa, xc, gb, ga, gC, qm, floor_, y2);
                         if (ok) {
-                            As[il * b + jl].x = xa;
-                            Bs[jl * b + kl].x = xb;
-                            Cs[tid].x = xc;
+                            Ax[il * b + jl] = xa;
+                            Bx[jl * b + kl] = xb;
+                            Cx[tid] = xc;
                         }
                     }
                     T *dst = ytile + int64_t(__builtin_amdgcn_readfirstlane(u)) * ystep;
@@ -323,9 +324,9 @@ k_sweep_dataflow(DataflowArgs a, int64_t n, T *__restrict__ x, const T *__restri
             // Publish this step's (P,J) and (J,Q) blocks (and (P,Q) after the
             // last step); release them; wait for the next step's blocks.
             const bool last = (m == Q - P);
-            if (aok) x[pa] = As[tid].x;
-            if (bok) x[pbp] = Bs[tid].x;
-            if (last && c_ok) x[pc] = Cs[tid].x;
+            if (idA >= 0) publish(P, J, Ax0);
+            if (idB >= 0) publish(J, Q, Bx0);
+            if (last) publish(P, Q, Cx);
             __syncthreads();
             if (tid == 0) {
                 // One release fence covers every block of the step; the
@@ -380,7 +381,7 @@ __global__ void k_fill_u32(int64_t count, uint32_t *a) {
 
 template <typename T>
 size_t dataflow_lds_bytes(int b) {
-    return size_t(5) * b * b * sizeof(XG<T>);
+    return size_t(6) * b * b * sizeof(T);
 }
 
 template <typename T, int B, int D>
