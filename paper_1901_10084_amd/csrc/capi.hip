@@ -56,6 +56,8 @@ void build_dataflow_tables(int64_t n, int b, std::vector<DTile> &tiles, std::vec
                            std::vector<uint32_t> &K);
 template <typename T> int launch_sweep_dataflow(const DataflowArgs &, int, int, int64_t, T *, const T *, T *, hipStream_t);
 template <typename T> int dataflow_occupancy(int, int *);
+template <typename T> int launch_aty_dataflow(const DataflowArgs &, int, int, int64_t, const T *, double *, hipStream_t);
+template <typename T> int aty_dataflow_occupancy(int, int *);
 int launch_fill_u32(int64_t, uint32_t *, hipStream_t);
 
 struct GraphView {
@@ -111,6 +113,7 @@ struct cc_ctx {
     uint32_t kmax = 0;
     uint32_t epoch = 0;
     int df_grid = 0;
+    int aty_grid = 0;
     uint64_t wait_ticks = 0;
     float *d_mean_deg = nullptr;  // warm-start features
 };
@@ -219,6 +222,11 @@ int ensure_dataflow(cc_ctx *c) {
     CCP_HIP_CHECK(hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev));
     if (per_cu < 1) return fail(CC_EHIP, "dataflow kernel does not fit on a compute unit");
     c->df_grid = int(std::min<int64_t>(c->ntiles, int64_t(per_cu) * cus));
+    rc = (c->prec == CC_F64) ? aty_dataflow_occupancy<double>(c->b, &per_cu)
+                             : aty_dataflow_occupancy<float>(c->b, &per_cu);
+    if (rc) return rc;
+    if (per_cu < 1) return fail(CC_EHIP, "dataflow A'y kernel does not fit on a compute unit");
+    c->aty_grid = int(std::min<int64_t>(c->ntiles, int64_t(per_cu) * cus));
     c->wait_ticks = uint64_t(khz > 0 ? khz : 100000) * 1000ull * 10ull;  // 10 s per wait
     return CC_OK;
 }
@@ -253,17 +261,26 @@ int check_dataflow(cc_ctx *c) {
     return CC_OK;
 }
 
-template <typename T>
-int sweep_metric_t(cc_ctx *c, T *x, T *y, const T *g, int exec, unsigned long long *prof) {
-    if (exec == CC_EXEC_ROUNDS) return sweep_rounds_t<T>(c, x, y, g, 0, c->nrounds);
+// Arguments of the next dataflow launch (each launch is one epoch of the
+// per-block touch counters).
+int dataflow_args(cc_ctx *c, unsigned long long *prof, DataflowArgs &a) {
     int rc = ensure_dataflow(c);
     if (rc) return rc;
     if (uint64_t(c->epoch + 1) * c->kmax >= (1ull << 31)) {
         if ((rc = launch_fill_u32(c->nblocks, c->d_cnt, c->stream))) return rc;
         c->epoch = 0;
     }
-    DataflowArgs a{c->d_dtiles, int(c->ntiles), c->d_needs, c->d_K, c->d_cnt, c->d_ctl,
-                   c->epoch, c->wait_ticks, prof};
+    a = DataflowArgs{c->d_dtiles, int(c->ntiles), c->d_needs, c->d_K, c->d_cnt, c->d_ctl,
+                     c->epoch, c->wait_ticks, prof};
+    return CC_OK;
+}
+
+template <typename T>
+int sweep_metric_t(cc_ctx *c, T *x, T *y, const T *g, int exec, unsigned long long *prof) {
+    if (exec == CC_EXEC_ROUNDS) return sweep_rounds_t<T>(c, x, y, g, 0, c->nrounds);
+    DataflowArgs a;
+    int rc = dataflow_args(c, prof, a);
+    if (rc) return rc;
     if ((rc = launch_sweep_dataflow<T>(a, c->df_grid, c->b, c->n, x, g, y, c->stream))) return rc;
     c->epoch++;
     return CC_OK;
@@ -284,6 +301,13 @@ int aty_t(cc_ctx *c, const T *y) {
     int rc = ensure_ax(c);
     if (rc) return rc;
     CCP_HIP_CHECK(hipMemsetAsync(c->d_ax, 0, size_t(num_pairs(c->n)) * sizeof(double), c->stream));
+    if (c->b == 8 || c->b == 16 || c->b == 32) {
+        DataflowArgs a;
+        if ((rc = dataflow_args(c, nullptr, a))) return rc;
+        if ((rc = launch_aty_dataflow<T>(a, c->aty_grid, c->b, c->n, y, c->d_ax, c->stream))) return rc;
+        c->epoch++;
+        return CC_OK;
+    }
     for (int r = 0; r < c->nrounds; ++r) {
         const int64_t a = c->round_start[r], e = c->round_start[r + 1];
         rc = launch_aty_round<T>(c->d_tiles + a, int(e - a), c->b, c->n, y, c->d_ax, c->stream);
@@ -313,6 +337,7 @@ int residuals_t(cc_ctx *c, const T *x, const T *f, const T *y, const T *yp, cons
     double h[14];
     CCP_HIP_CHECK(hipMemcpyAsync(h, c->d_out, sizeof(h), hipMemcpyDeviceToHost, c->stream));
     CCP_HIP_CHECK(hipStreamSynchronize(c->stream));
+    if (want_dual && (rc = check_dataflow(c))) return rc;
     const double nan = std::nan("");
     // h: 0 metric max viol, 1 metric cs sum, 2 metric cs max, 3 metric bad,
     //    4 pair max viol, 5 sum w f, 6 sum w (x^2+f^2), 7 lp, 8 pair cs max,
@@ -641,6 +666,7 @@ int dual_value(cc_ctx *c, const T *x, const T *f, const T *yp, const double *w, 
     double h[14];
     CCP_HIP_CHECK(hipMemcpyAsync(h, c->d_out, sizeof(h), hipMemcpyDeviceToHost, c->stream));
     CCP_HIP_CHECK(hipStreamSynchronize(c->stream));
+    if (ax && (rc = check_dataflow(c))) return rc;  // A'y may come from a dataflow launch
     *out = -h[11] - 0.5 * gamma * h[10];
     return CC_OK;
 }

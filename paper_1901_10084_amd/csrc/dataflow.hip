@@ -367,6 +367,157 @@ k_sweep_dataflow(DataflowArgs a, int64_t n, T *__restrict__ x, const T *__restri
         for (int e = 0; e < 5; ++e) atomicAdd(&a.prof[e], (unsigned long long)s_pt[e]);
 }
 
+// A'y on the dataflow schedule: every tile step adds each triplet's three
+// duals into the FP64 accumulators of its pairs (i,j): y0 - y1 - y2,
+// (i,k): y1 - y0 - y2, (j,k): y2 - y0 - y1, with the same waits and the same
+// order of additions per pair as the sweep, so the sums equal those of the
+// round-by-round kernel bit for bit.  ax must hold zeros (or a partial sum)
+// on entry.
+template <typename T, int B, int D>
+__global__ void __launch_bounds__(B * B)
+k_aty_dataflow(DataflowArgs a, int64_t n, const T *__restrict__ y, double *__restrict__ ax) {
+    constexpr int b = B;
+    constexpr int bb = B * B;
+    const int tid = threadIdx.x;
+    const int il = tid / b, kl = tid % b;
+    const int sr = tid % b, sc = tid / b;
+    const int nn = int(n);
+    const int nb = (nn + b - 1) / b;
+    __shared__ double Abuf[bb], Bbuf[bb], Cs[bb];
+    __shared__ int s_tix, s_ok;
+
+    if (tid == 0) s_tix = int(atomicAdd(&a.ctl[0], 1u));
+    __syncthreads();
+    for (;;) {
+        const int tix = __builtin_amdgcn_readfirstlane(s_tix);
+        if (tix >= a.ntiles) break;
+        const DTile tl = a.tiles[tix];
+        const int P = tl.P, Q = tl.Q;
+        const bool desc = tile_desc(P, Q, nb);
+        const int i = P * b + il, k = Q * b + kl;
+        const int idC = block_id(P, Q);
+
+        auto blk_ok = [&](int R, int S) {
+            const int ii = R * b + sr, jj = S * b + sc;
+            return ii < jj && jj < nn;
+        };
+        auto stage = [&](int R, int S, double *X) {
+            const bool ok = blk_ok(R, S);
+            const double v = ax[ok ? pidx(R * b + sr, S * b + sc) : 0];
+            X[sr * b + sc] = ok ? v : 0.0;
+        };
+        auto publish = [&](int R, int S, const double *X) {
+            if (blk_ok(R, S)) ax[pidx(R * b + sr, S * b + sc)] = X[sr * b + sc];
+        };
+        auto step_ids = [&](int m, int &idA, int &idB) {
+            const int J = tile_J(P, Q, m, desc);
+            idA = (J != Q) ? block_id(P, J) : -1;
+            idB = (J != P) ? block_id(J, Q) : -1;
+        };
+        auto wait_step = [&](int m) {
+            int idA, idB;
+            step_ids(m, idA, idB);
+            const uint32_t *nd = a.needs + 2 * int64_t(tl.jsbase + m);
+            bool ok = true;
+            if (idA >= 0)
+                ok = wait_count(&a.cnt[idA], a.epoch * a.K[idA] + nd[0], &a.ctl[1], a.wait_ticks);
+            if (ok && idB >= 0)
+                ok = wait_count(&a.cnt[idB], a.epoch * a.K[idB] + nd[1], &a.ctl[1], a.wait_ticks);
+            return ok;
+        };
+
+        const T *const ytile = y + tl.ybase;
+        const int64_t ystep = int64_t(3) * bb;
+        const unsigned lane = unsigned(tid);
+        T yq[D][3];
+        auto fill_ring = [&](int m) {
+#pragma unroll
+            for (int d = 0; d < D; ++d) {
+                const T *src = ytile + int64_t(m * b + d) * ystep;
+                yq[d][0] = __builtin_nontemporal_load(&src[lane]);
+                yq[d][1] = __builtin_nontemporal_load(&src[lane + bb]);
+                yq[d][2] = __builtin_nontemporal_load(&src[lane + 2 * bb]);
+            }
+        };
+        fill_ring(0);
+
+        if (tid == 0) {
+            bool ok = wait_count(&a.cnt[idC], a.epoch * a.K[idC] + tl.needC, &a.ctl[1], a.wait_ticks);
+            ok = ok && wait_step(0);
+            if (ok) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+            s_ok = ok;
+        }
+        __syncthreads();
+        if (!__builtin_amdgcn_readfirstlane(s_ok)) break;
+        stage(P, Q, Cs);
+
+        bool aborted = false;
+        for (int m = 0; m <= Q - P; ++m) {
+            const int J = tile_J(P, Q, m, desc);
+            int idA, idB;
+            step_ids(m, idA, idB);
+            double *const Ab = (J == Q) ? Cs : Abuf;
+            double *const Bb = (J == P) ? Cs : Bbuf;
+            if (idA >= 0) stage(P, J, Abuf);
+            if (idB >= 0) stage(J, Q, Bbuf);
+            lds_barrier();
+            const int ulast = m * b + b - 1;
+            auto group = [&](const int t0) {
+#pragma unroll
+                for (int d = 0; d < D; ++d) {
+                    const int t = t0 + d;
+                    const int u = m * b + t;
+                    const double y0 = double(yq[d][0]), y1 = double(yq[d][1]), y2 = double(yq[d][2]);
+                    const int jl = mid_offset(t, il, kl, b);
+                    const int j = J * b + jl;
+                    if (i < j && j < k && k < nn) {
+                        Ab[il * b + jl] += (y0 - y1) - y2;  // pair (i,j)
+                        Cs[tid] += (y1 - y0) - y2;          // pair (i,k)
+                        Bb[jl * b + kl] += (y2 - y0) - y1;  // pair (j,k)
+                    }
+                    const int un = u + D <= ulast ? u + D : ulast;
+                    const T *src = ytile + int64_t(un) * ystep;
+                    yq[d][0] = __builtin_nontemporal_load(&src[lane]);
+                    yq[d][1] = __builtin_nontemporal_load(&src[lane + bb]);
+                    yq[d][2] = __builtin_nontemporal_load(&src[lane + 2 * bb]);
+                    lds_barrier();
+                }
+            };
+            group(0);
+#pragma nounroll
+            for (int t0 = D; t0 < b; t0 += D) group(t0);
+
+            const bool last = (m == Q - P);
+            if (idA >= 0) publish(P, J, Abuf);
+            if (idB >= 0) publish(J, Q, Bbuf);
+            if (last) publish(P, Q, Cs);
+            __syncthreads();
+            if (tid == 0) {
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+                if (idA >= 0) __hip_atomic_fetch_add(&a.cnt[idA], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                if (idB >= 0) __hip_atomic_fetch_add(&a.cnt[idB], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                bool ok = true;
+                if (last) {
+                    __hip_atomic_fetch_add(&a.cnt[idC], uint32_t(Q - P + 1), __ATOMIC_RELAXED,
+                                           __HIP_MEMORY_SCOPE_AGENT);
+                    s_tix = int(atomicAdd(&a.ctl[0], 1u));
+                } else {
+                    ok = wait_step(m + 1);
+                    if (ok) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+                }
+                s_ok = ok;
+            }
+            __syncthreads();
+            if (!__builtin_amdgcn_readfirstlane(s_ok)) {
+                aborted = true;
+                break;
+            }
+            if (!last) fill_ring(m + 1);
+        }
+        if (aborted) break;
+    }
+}
+
 __global__ void k_dataflow_reset(uint32_t *ctl) {
     if (threadIdx.x == 0) {
         ctl[0] = 0u;
@@ -431,6 +582,40 @@ int dataflow_occupancy(int b, int *blocks_per_cu) {
     return CC_OK;
 }
 
+template <typename T, int B, int D>
+static int launch_aty_df_t(const DataflowArgs &a, int grid, int64_t n, const T *y, double *ax,
+                           hipStream_t s) {
+    hipLaunchKernelGGL(k_dataflow_reset, dim3(1), dim3(64), 0, s, a.ctl);
+    CCP_LAUNCH_CHECK("k_dataflow_reset");
+    hipLaunchKernelGGL((k_aty_dataflow<T, B, D>), dim3(grid), dim3(B * B), 0, s, a, n, y, ax);
+    CCP_LAUNCH_CHECK("k_aty_dataflow");
+    return CC_OK;
+}
+
+template <typename T>
+int launch_aty_dataflow(const DataflowArgs &a, int grid, int b, int64_t n, const T *y, double *ax,
+                        hipStream_t s) {
+    switch (b) {
+        case 8: return launch_aty_df_t<T, 8, 4>(a, grid, n, y, ax, s);
+        case 16: return launch_aty_df_t<T, 16, 8>(a, grid, n, y, ax, s);
+        case 32: return launch_aty_df_t<T, 32, 4>(a, grid, n, y, ax, s);
+        default: return fail(CC_EINVAL, "the dataflow executor supports b = 8, 16, 32");
+    }
+}
+
+template <typename T>
+int aty_dataflow_occupancy(int b, int *blocks_per_cu) {
+    hipError_t e = hipSuccess;
+    switch (b) {
+        case 8: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, k_aty_dataflow<T, 8, 4>, 64, 0); break;
+        case 16: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, k_aty_dataflow<T, 16, 8>, 256, 0); break;
+        case 32: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, k_aty_dataflow<T, 32, 4>, 1024, 0); break;
+        default: *blocks_per_cu = 0; return CC_OK;
+    }
+    if (e != hipSuccess) return fail(CC_EHIP, std::string("A'y occupancy: ") + hipGetErrorString(e));
+    return CC_OK;
+}
+
 int launch_fill_u32(int64_t count, uint32_t *a, hipStream_t s) {
     if (count <= 0) return CC_OK;
     int64_t grid = (count + 255) / 256;
@@ -444,6 +629,10 @@ template int launch_sweep_dataflow<double>(const DataflowArgs &, int, int, int64
                                            const double *, double *, hipStream_t);
 template int launch_sweep_dataflow<float>(const DataflowArgs &, int, int, int64_t, float *,
                                           const float *, float *, hipStream_t);
+template int launch_aty_dataflow<double>(const DataflowArgs &, int, int, int64_t, const double *, double *, hipStream_t);
+template int launch_aty_dataflow<float>(const DataflowArgs &, int, int, int64_t, const float *, double *, hipStream_t);
+template int aty_dataflow_occupancy<double>(int, int *);
+template int aty_dataflow_occupancy<float>(int, int *);
 template int dataflow_occupancy<double>(int, int *);
 template int dataflow_occupancy<float>(int, int *);
 

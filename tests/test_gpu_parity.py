@@ -152,6 +152,25 @@ def test_residuals_and_x_from_y(prec):
     assert rel_err(f.cpu().numpy(), fo) <= (1e-12 if prec == "f64" else 1e-5)
 
 
+@pytest.mark.parametrize("n,b,prec", [(45, 8, "f64"), (70, 16, "f64"), (100, 32, "f64"),
+                                      (70, 16, "f32")])
+def test_x_from_y_dataflow(n, b, prec):
+    """A'y runs on the dataflow schedule for b = 8, 16, 32: equal to the
+    oracle's x(y), and the same bits on every call (fixed summation order)."""
+    inst = I.random_signed(n, seed=n + b, gamma=1.5, weighted=True)
+    g = C.Solver.from_instance(inst, b=b, prec=prec)
+    o = oracle.State.from_instance(inst)
+    g.sweep(3)
+    o.sweep(3, b=b)
+    x1, f1 = g.x_from_y()
+    x2, f2 = g.x_from_y()
+    assert torch.equal(x1, x2) and torch.equal(f1, f2)
+    xo, fo = o.x_from_y()
+    tol = 1e-12 if prec == "f64" else 1e-5
+    assert rel_err(x1.cpu().numpy(), xo) <= tol
+    assert rel_err(f1.cpu().numpy(), fo) <= tol
+
+
 def test_f32_close_to_oracle():
     """FP32 sweeps against the FP64 oracle: the error stays at FP32 level."""
     inst = I.workload(0)
