@@ -326,9 +326,13 @@ class Solver:
         self.ctx.duals_to_lex(self.y, y_lex)
         return y_lex
 
-    def solve(self, tol=1e-6, max_sweeps=100000, check_every=1, executor=CC_EXEC_ROUNDS):
-        """Sweep until both max violations are <= tol (checked every
-        `check_every` sweeps).  Returns (residuals, converged, seconds)."""
+    def solve(self, tol=1e-6, max_sweeps=100000, check_every=None, executor=CC_EXEC_ROUNDS):
+        """Sweep until both max violations are <= tol, checked every
+        `check_every` sweeps (default as in cc_solve_cc_lp: every sweep up to
+        n = 1000, every 5 above; a check reads every triplet).  Returns
+        (residuals, converged, seconds)."""
+        if check_every is None:
+            check_every = 1 if self.n <= 1000 else 5
         t0 = time.perf_counter()
         r = None
         while self.sweeps < max_sweeps:
