@@ -259,6 +259,13 @@ int cc_mlp_train_graph(cc_ctx *ctx, const void *y_star, const double *w, const u
 int cc_mlp_slot_features(cc_ctx *ctx, const double *w, const uint8_t *d, const float *deg,
                          const int64_t *slots, int64_t count, float *phi_out);
 
+/* Network prediction for every metric row into y (schedule order, context
+ * precision, 0 on padding): the dual a warm start would take, i.e. the
+ * network output divided by n - 2 (its training targets are duals times
+ * n - 2, the number of triplets through a pair).  Enqueues only. */
+int cc_mlp_infer(cc_ctx *ctx, const float *params, const float *deg, const double *w,
+                 const uint8_t *d, void *y);
+
 /* Warm start: y = network prediction for every metric row (0 on padding),
  * y_pair = 0, (x, f) = v(y), then one pair pass (which gives the pair duals
  * their best values for this y: the two pair rows of a pair are

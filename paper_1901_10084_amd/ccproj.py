@@ -89,6 +89,7 @@ _sig("cc_mlp_train_step", ctypes.c_int, _p, _p, _i64, _p, _p, _p, _i32, ctypes.c
 _sig("cc_mlp_train_graph", ctypes.c_int, _p, _p, _p, _p, _p, _i64, ctypes.c_uint64, _p, _p, _p,
      _i32, ctypes.c_float, _p, _p)
 _sig("cc_mlp_slot_features", ctypes.c_int, _p, _p, _p, _p, _p, _i64, _p)
+_sig("cc_mlp_infer", ctypes.c_int, _p, _p, _p, _p, _p, _p)
 _sig("cc_warm_start_mlp", ctypes.c_int, _p, _p, _p, _p, _p, _dbl, _p, _p, _p, _p, _p,
      ctypes.POINTER(_i32), ctypes.POINTER(_dbl), ctypes.POINTER(_dbl))
 

@@ -784,6 +784,18 @@ int cc_mlp_slot_features(cc_ctx *c, const double *w, const uint8_t *d, const flo
     return launch_mlp_slot_features(G, slots, count, phi, c->stream);
 }
 
+int cc_mlp_infer(cc_ctx *c, const float *params, const float *deg, const double *w,
+                 const uint8_t *d, void *y) {
+    int rc;
+    if ((rc = check_ctx(c)) || (rc = need(params, "params")) || (rc = need(deg, "deg")) ||
+        (rc = need(w, "w")) || (rc = need(d, "d")) || (rc = need(y, "y")))
+        return rc;
+    GraphView G;
+    if ((rc = graph_view(c, w, d, deg, G))) return rc;
+    if (c->prec == CC_F64) return launch_mlp_infer<double>(G, params, (double *)y, c->stream);
+    return launch_mlp_infer<float>(G, params, (float *)y, c->stream);
+}
+
 int cc_warm_start_mlp(cc_ctx *c, const float *params, const float *deg, const double *w,
                       const uint8_t *d, double gamma, void *x, void *f, void *y, void *yp,
                       const void *g, int32_t *accepted, double *dual_warm, double *dual_cold) {

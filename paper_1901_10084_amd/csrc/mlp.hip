@@ -23,7 +23,9 @@
 namespace ccp {
 
 typedef __attribute__((ext_vector_type(8))) __bf16 bf16x8;
+typedef __attribute__((ext_vector_type(2))) __bf16 bf16x2;
 typedef __attribute__((ext_vector_type(4))) float f32x4;
+typedef __attribute__((ext_vector_type(2))) float f32x2;
 
 constexpr int kNParam = 1249;
 constexpr int oW1 = 0, oB1 = 128, oW2 = 160, oB2 = 1184, oW3 = 1216, oB3 = 1248;
@@ -32,16 +34,14 @@ __host__ __device__ __forceinline__ int unit_of(int g, int q) {
     return q < 4 ? 4 * g + q : 16 + 4 * g + (q - 4);
 }
 
-// Round to the nearest bfloat16 (ties to even), kept as a float.
-__device__ __forceinline__ float bf16r(float v) {
-    uint32_t u = __float_as_uint(v);
-    u = (u + 0x7FFFu + ((u >> 16) & 1u)) & 0xFFFF0000u;
-    return __uint_as_float(u);
+// Round to the nearest bfloat16 (ties to even): the hardware conversion,
+// two values per instruction.
+__device__ __forceinline__ bf16x2 tobf2(float a, float b) {
+    const f32x2 v = {a, b};
+    return __builtin_convertvector(v, bf16x2);
 }
-__device__ __forceinline__ __bf16 tobf(float v) {
-    const uint16_t h = uint16_t(__float_as_uint(bf16r(v)) >> 16);
-    return __builtin_bit_cast(__bf16, h);
-}
+__device__ __forceinline__ float bf16r(float v) { return float(tobf2(v, 0.0f)[0]); }
+__device__ __forceinline__ __bf16 tobf(float v) { return tobf2(v, 0.0f)[0]; }
 
 struct LaneNet {
     float w1[8][4];
@@ -86,8 +86,14 @@ __device__ __forceinline__ void forward(const LaneNet &N, const float phi[4], Fw
 #pragma unroll
         for (int k = 0; k < 4; ++k) z = fmaf(N.w1[q][k], phi[k], z);
         F.z1[q] = z;
-        F.h1[q] = bf16r(fmaxf(z, 0.0f));
-        bh[q] = tobf(F.h1[q]);
+    }
+#pragma unroll
+    for (int q = 0; q < 8; q += 2) {
+        const bf16x2 h = tobf2(fmaxf(F.z1[q], 0.0f), fmaxf(F.z1[q + 1], 0.0f));
+        bh[q] = h[0];
+        bh[q + 1] = h[1];
+        F.h1[q] = float(h[0]);
+        F.h1[q + 1] = float(h[1]);
     }
     const f32x4 zero = {0.f, 0.f, 0.f, 0.f};
     const f32x4 d0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(N.a2[0], bh, zero, 0, 0, 0);
@@ -99,10 +105,13 @@ __device__ __forceinline__ void forward(const LaneNet &N, const float phi[4], Fw
         F.z2[4 + r] = d1[r] + N.b2[4 + r];
     }
 #pragma unroll
-    for (int q = 0; q < 8; ++q) {
-        F.h2[q] = bf16r(fmaxf(F.z2[q], 0.0f));
-        part = fmaf(N.w3[q], F.h2[q], part);
+    for (int q = 0; q < 8; q += 2) {
+        const bf16x2 h = tobf2(fmaxf(F.z2[q], 0.0f), fmaxf(F.z2[q + 1], 0.0f));
+        F.h2[q] = float(h[0]);
+        F.h2[q + 1] = float(h[1]);
     }
+#pragma unroll
+    for (int q = 0; q < 8; ++q) part = fmaf(N.w3[q], F.h2[q], part);
     part += __shfl_xor(part, 16, 64);
     part += __shfl_xor(part, 32, 64);
     F.z3 = part + N.b3;
@@ -409,6 +418,89 @@ k_mlp_infer(GraphView G, const float *__restrict__ P, T *__restrict__ y) {
     }
 }
 
+// The same inference for b = 8, 16, 32, walking the tile's segment in its
+// own order instead of decoding every slot: per tile step the signed weights
+// of blocks (P,J), (J,Q), (P,Q) and the degrees of the three vertex blocks
+// sit in LDS, a wave takes 64 consecutive slots (one sub-step t, one
+// orientation o, lanes L0..L0+63) as four 16-row forward passes, and lane l
+// keeps the output of slot L0 + l, so the store is contiguous.  Features and
+// outputs are those of k_mlp_infer bit for bit.
+template <typename T, int B>
+__global__ void __launch_bounds__(256)
+k_mlp_infer_tiled(GraphView G, const float *__restrict__ P, T *__restrict__ y) {
+    constexpr int b = B, bb = B * B;
+    LaneNet N;
+    load_net(N, P);
+    const int lane = threadIdx.x & 63, si = lane & 15, g = lane >> 4;
+    const int wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    const Tile tl = G.tiles[blockIdx.x];
+    const int Pb = tl.P, Qb = tl.Q;
+    const int nn = int(G.n), nb = (nn + b - 1) / b;
+    const bool desc = tile_desc(Pb, Qb, nb);
+    __shared__ float swA[bb], swB[bb], swC[bb], fA[bb], fB[bb], fC[bb], dP[b], dJ[b], dQ[b];
+    const float md = G.mean_deg[0];
+    const float den = 2.0f * md;
+    const float outscale = float(G.n - 2);
+    auto sw = [&](int r, int c) {  // signed weight of pair (r, c), 0 if none
+        if (!(r < c && c < nn)) return 0.0f;
+        const int64_t p = pidx(r, c);
+        return bf16r(float(G.d[p] == 0 ? G.w[p] : -G.w[p]));
+    };
+    auto degv = [&](int v) { return v < nn ? G.deg[v] : 0.0f; };
+    // degree feature of the pair of block entries (r, c)
+    auto fdeg = [&](float da, float db) { return bf16r(md > 0.0f ? (da + db) / den : 0.0f); };
+    for (int e = threadIdx.x; e < b; e += blockDim.x) {
+        dP[e] = degv(Pb * b + e);
+        dQ[e] = degv(Qb * b + e);
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e < bb; e += blockDim.x) {
+        swC[e] = sw(Pb * b + e / b, Qb * b + e % b);
+        fC[e] = fdeg(dP[e / b], dQ[e % b]);
+    }
+    T *const ytile = y + tl.ybase;
+    constexpr int gps = 3 * bb / 64;  // 64-slot groups per sub-step
+    for (int m = 0; m <= Qb - Pb; ++m) {
+        const int J = tile_J(Pb, Qb, m, desc);
+        __syncthreads();  // the last step's readers are done
+        for (int e = threadIdx.x; e < b; e += blockDim.x) dJ[e] = degv(J * b + e);
+        __syncthreads();
+        for (int e = threadIdx.x; e < bb; e += blockDim.x) {
+            swA[e] = sw(Pb * b + e / b, J * b + e % b);
+            swB[e] = sw(J * b + e / b, Qb * b + e % b);
+            fA[e] = fdeg(dP[e / b], dJ[e % b]);
+            fB[e] = fdeg(dJ[e / b], dQ[e % b]);
+        }
+        __syncthreads();
+        for (int grp = wave; grp < b * gps; grp += nw) {
+            const int t = grp / gps, rem = grp - t * gps;
+            const int o = rem / (bb / 64), L0 = (rem - o * (bb / 64)) * 64;
+            float out = 0.0f;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int L = L0 + 16 * q + si;
+                const int il = L / b, kl = L % b;
+                const int jl = mid_offset(t, il, kl, b);
+                const int i = Pb * b + il, j = J * b + jl, k = Qb * b + kl;
+                const bool ok = i < j && j < k && k < nn;
+                const int eA = il * b + jl, eC = il * b + kl, eB = jl * b + kl;
+                const float wij = swA[eA], wik = swC[eC], wjk = swB[eB];
+                // o is the same for the whole group: long side ij, ik or jk
+                float phi[4];
+                phi[0] = o == 0 ? wij : (o == 1 ? wik : wjk);
+                phi[1] = o == 0 ? wik : wij;
+                phi[2] = o == 0 ? wjk : (o == 1 ? wjk : wik);
+                phi[3] = o == 0 ? fA[eA] : (o == 1 ? fC[eC] : fB[eB]);
+                if (!ok) phi[0] = phi[1] = phi[2] = phi[3] = 0.0f;
+                Fwd F;
+                forward(N, phi, F);
+                if (g == q) out = ok ? F.y : 0.0f;
+            }
+            ytile[(int64_t(m) * b + t) * 3 * bb + o * bb + L0 + lane] = T(out / outscale);
+        }
+    }
+}
+
 // Features of given slots (for checks against the reference).
 __global__ void k_mlp_slot_features(GraphView G, const int64_t *__restrict__ slots, int64_t count,
                                     float *__restrict__ phi) {
@@ -512,7 +604,12 @@ int launch_mlp_forward(const float *P, const float *phi, int64_t count, float *y
 
 template <typename T>
 int launch_mlp_infer(const GraphView &G, const float *P, T *y, hipStream_t s) {
-    hipLaunchKernelGGL(k_mlp_infer<T>, dim3(unsigned(G.ntiles)), dim3(256), 0, s, G, P, y);
+    switch (G.b) {
+        case 8: hipLaunchKernelGGL((k_mlp_infer_tiled<T, 8>), dim3(unsigned(G.ntiles)), dim3(256), 0, s, G, P, y); break;
+        case 16: hipLaunchKernelGGL((k_mlp_infer_tiled<T, 16>), dim3(unsigned(G.ntiles)), dim3(256), 0, s, G, P, y); break;
+        case 32: hipLaunchKernelGGL((k_mlp_infer_tiled<T, 32>), dim3(unsigned(G.ntiles)), dim3(256), 0, s, G, P, y); break;
+        default: hipLaunchKernelGGL(k_mlp_infer<T>, dim3(unsigned(G.ntiles)), dim3(256), 0, s, G, P, y); break;
+    }
     CCP_LAUNCH_CHECK("k_mlp_infer");
     return CC_OK;
 }

@@ -95,6 +95,12 @@ def slot_features(solver, deg, slots):
     return phi
 
 
+def infer(solver, net: Network, deg, y_out):
+    """Network prediction of every metric dual into y_out (schedule order)."""
+    C.check(C._L.cc_mlp_infer(solver.ctx.handle, net.params.data_ptr(), deg.data_ptr(),
+                              solver.w.data_ptr(), solver.d.data_ptr(), y_out.data_ptr()))
+
+
 def warm_start(solver, net: Network, deg) -> dict:
     """Gated learned warm start of a Solver in place (see cc_warm_start_mlp)."""
     acc = ctypes.c_int32()

@@ -86,6 +86,60 @@ def test_slot_features_match_reference():
     assert np.allclose(phi[valid], ref, rtol=0, atol=1e-6)
 
 
+def colex_triplets(t):
+    """(i, j, k) of colex triplet indices t (numpy int64 arrays)."""
+    k = np.floor(np.cbrt(6.0 * t)).astype(np.int64) + 2
+    while True:
+        over = k * (k - 1) * (k - 2) // 6 > t
+        if not over.any():
+            break
+        k[over] -= 1
+    r = t - k * (k - 1) * (k - 2) // 6
+    j = np.floor(np.sqrt(2.0 * r)).astype(np.int64) + 1
+    while True:
+        over = j * (j - 1) // 2 > r
+        if not over.any():
+            break
+        j[over] -= 1
+    return r - j * (j - 1) // 2, j, k
+
+
+@pytest.mark.parametrize("n,b,prec", [(23, 8, "f32"), (40, 16, "f32"), (70, 32, "f32"),
+                                      (37, 16, "f64"), (19, 5, "f32")])
+def test_inference_matches_reference(n, b, prec):
+    """cc_mlp_infer on every schedule slot against the float64 reference
+    network on the reference features, divided by n - 2; padding gets 0."""
+    inst = I.random_signed(n, seed=n, gamma=1.0, weighted=True)
+    s = C.Solver.from_instance(inst, b=b, prec=prec)
+    deg = W.degrees(inst)
+    p = M.init_params(5)
+    net = W.Network(params=p)
+    yv = torch.full_like(s.y, -1.0)
+    W.infer(s, net, deg, yv)
+    slots = torch.arange(s.ctx.slots, device="cuda", dtype=torch.int64)
+    lex = torch.empty_like(slots)
+    s.ctx.slots_to_lex(slots, lex)
+    yv, lex = yv.cpu().numpy().astype(np.float64), lex.cpu().numpy()
+    valid = lex >= 0
+    assert not yv[~valid].any()
+    t, o = lex[valid] // 3, lex[valid] % 3
+    i, j, k = colex_triplets(t)
+    phi = M.features(inst.d, inst.w, inst.deg, i, j, k, o)
+    yr, _ = M.forward(p, phi)
+    yr = yr / (n - 2)
+    e = np.abs(yv[valid] - yr) / max(1e-30, np.abs(yr).max())
+    q999 = np.quantile(e, 0.999)
+    print("inference rel err: max %.3g, 99.9%% %.3g, median %.3g, rows %d"
+          % (e.max(), q999, np.median(e), e.size), flush=True)
+    # The kernel accumulates in fp32 (MFMA) before each bf16 rounding of the
+    # hidden layers, the reference in float64: a hidden value on a bf16
+    # rounding boundary can land one bf16 step apart, which moves that row's
+    # output by up to a few 1e-3.  A wrong feature, orientation or slot moves
+    # a large share of rows.
+    assert q999 <= 1e-3
+    assert e.max() <= 2e-2
+
+
 def test_training_reduces_loss():
     rng = np.random.default_rng(3)
     phi = rng.normal(0, 1, (8192, 4)).astype(np.float32)
