@@ -119,6 +119,48 @@ def warm_report(config, b, tol=1e-4):
     return res
 
 
+def large_sweep(config=4, b=32, prec="f32", steps=5, warmup=2):
+    """Per-sweep time and HBM fraction of the dataflow metric sweep on the
+    largest single-GPU workload: the n = 4000 Chung-Lu graph (exponent 2.2,
+    mean degree 20, weights U[0.5, 1.5], gamma 10), FP32 duals (128 GB)
+    resident in HBM.  Same timing as the headline: HIP events around each
+    metric-sweep launch."""
+    import torch
+    from paper_1901_10084_amd import ccproj as C
+    from paper_1901_10084_amd import instances as I
+    inst = I.workload(config)
+    elem = 8 if prec == "f64" else 4
+    g = C.Solver.from_instance(inst, b=b, prec=prec)
+    for _ in range(warmup):
+        g.sweep(1, C.CC_EXEC_DATAFLOW)
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    e0 = [torch.cuda.Event(enable_timing=True) for _ in range(steps)]
+    e1 = [torch.cuda.Event(enable_timing=True) for _ in range(steps)]
+    for s in range(steps):
+        e0[s].record(stream)
+        g.sweep_metric(C.CC_EXEC_DATAFLOW)
+        e1[s].record(stream)
+        g.pair_pass()
+    torch.cuda.synchronize()
+    g.status()
+    ms = sum(a.elapsed_time(b_) for a, b_ in zip(e0, e1)) / steps
+    nbytes = metric_sweep_bytes(inst, elem)
+    achieved = nbytes / (ms / 1e3) / 1e9
+    out = {"workload": inst.name, "n": inst.n, "prec": prec, "b": b,
+           "metric_rows": inst.num_constraints, "sweeps_timed": steps,
+           "ms_per_metric_sweep": ms,
+           "constraint_projections_per_s": inst.num_constraints / (ms / 1e3),
+           "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
+                        "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+                        "traffic": recorded_traffic("k_sweep_dataflow", inst, b, prec),
+                        "kernel": "k_sweep_dataflow", "avg_launch_us": ms * 1e3,
+                        "algorithmic_bytes_per_launch": nbytes}}
+    del g
+    torch.cuda.empty_cache()
+    return out
+
+
 def cpu_baseline(inst, b, budget_s):
     import oracle
     s = oracle.State.from_instance(inst)
@@ -147,6 +189,8 @@ def main():
     ap.add_argument("--cpu-budget", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-solve", action="store_true")
+    ap.add_argument("--no-large", action="store_true",
+                    help="skip the n = 4000 FP32 sweep measurement (128 GB of duals)")
     ap.add_argument("--warm-report", action="store_true",
                     help="FP64 cold vs FP32 cold vs FP32 + learned warm start, each to max "
                          "violation <= 1e-4, on workload --warm-config (tile size 32)")
@@ -253,6 +297,11 @@ def main():
         log("timing the oracle ...")
         out["cpu_baseline"] = cpu_baseline(inst, args.b, args.cpu_budget)
         log(f"oracle: {out['cpu_baseline']}")
+
+    if not args.no_large:
+        log("n = 4000 FP32 sweep ...")
+        out["large_workload"] = large_sweep()
+        log(f"large: {out['large_workload']}")
 
     if args.warm_report:
         del g

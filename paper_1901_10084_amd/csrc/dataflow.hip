@@ -111,6 +111,9 @@ template <typename T, int B, int D>
 __global__ void __launch_bounds__(B * B)
 k_sweep_dataflow(DataflowArgs a, int64_t n, T *__restrict__ x, const T *__restrict__ g,
                  T *__restrict__ y) {
+    // the first and last groups of D sub-steps are peeled: refills of the
+    // other groups stay inside the step
+    static_assert(B % D == 0 && B >= 2 * D, "ring depth must divide b, twice at least");
     constexpr int b = B;
     constexpr int bb = B * B;
     const int tid = threadIdx.x;
@@ -260,13 +263,14 @@ k_sweep_dataflow(DataflowArgs a, int64_t n, T *__restrict__ x, const T *__restri
             };
             T gan, gbn;
             T qn = gq(0, gan, gbn);
-            const int ulast = m * b + b - 1;
             // D sub-steps, one per ring slot.  The first group is peeled off
             // the loop so that the loop is entered with the ring in the
             // state it has at every later iteration; the compiler's memory
             // waits at the loop head are then exact (a wait of 6D-3 accesses
-            // per slot) rather than those of a freshly filled ring.
-            auto group = [&](const int t0) {
+            // per slot) rather than those of a freshly filled ring.  The last
+            // group is peeled too: it refills nothing (the ring for the next
+            // step is loaded after the release).
+            auto group = [&](const int t0, const bool refill) {
 #pragma unroll
                 for (int d = 0; d < D; ++d) {
                     const int t = t0 + d;
@@ -301,14 +305,11 @@ k_sweep_dataflow(DataflowArgs a, int64_t n, T *__restrict__ x, const T *__restri
                     __builtin_nontemporal_store(y0, &dst[lane]);
                     __builtin_nontemporal_store(y1, &dst[lane + bb]);
                     __builtin_nontemporal_store(y2, &dst[lane + 2 * bb]);
-                    {
+                    if (refill) {
                         // Refill slot d after its duals are consumed, so the
                         // old and new values never live at once (no register
-                        // copies of loads in flight).  Prefetch stays inside
-                        // the step: the last D sub-steps reload a slot of the
-                        // step, whose value is not used.
-                        const int un = u + D <= ulast ? u + D : ulast;
-                        const T *src = ytile + int64_t(un) * ystep;
+                        // copies of loads in flight).
+                        const T *src = ytile + int64_t(u + D) * ystep;
                         yq[d][0] = __builtin_nontemporal_load(&src[lane]);
                         yq[d][1] = __builtin_nontemporal_load(&src[lane + bb]);
                         yq[d][2] = __builtin_nontemporal_load(&src[lane + 2 * bb]);
@@ -316,9 +317,10 @@ k_sweep_dataflow(DataflowArgs a, int64_t n, T *__restrict__ x, const T *__restri
                     lds_barrier();
                 }
             };
-            group(0);
+            group(0, true);
 #pragma nounroll
-            for (int t0 = D; t0 < b; t0 += D) group(t0);
+            for (int t0 = D; t0 < b - D; t0 += D) group(t0, true);
+            group(b - D, false);
             if (tid == 0 && a.prof) mark(2);
 
             // Publish this step's (P,J) and (J,Q) blocks (and (P,Q) after the
@@ -376,6 +378,7 @@ k_sweep_dataflow(DataflowArgs a, int64_t n, T *__restrict__ x, const T *__restri
 template <typename T, int B, int D>
 __global__ void __launch_bounds__(B * B)
 k_aty_dataflow(DataflowArgs a, int64_t n, const T *__restrict__ y, double *__restrict__ ax) {
+    static_assert(B % D == 0 && B >= 2 * D, "ring depth must divide b, twice at least");
     constexpr int b = B;
     constexpr int bb = B * B;
     const int tid = threadIdx.x;
@@ -461,8 +464,7 @@ k_aty_dataflow(DataflowArgs a, int64_t n, const T *__restrict__ y, double *__res
             if (idA >= 0) stage(P, J, Abuf);
             if (idB >= 0) stage(J, Q, Bbuf);
             lds_barrier();
-            const int ulast = m * b + b - 1;
-            auto group = [&](const int t0) {
+            auto group = [&](const int t0, const bool refill) {
 #pragma unroll
                 for (int d = 0; d < D; ++d) {
                     const int t = t0 + d;
@@ -475,17 +477,19 @@ k_aty_dataflow(DataflowArgs a, int64_t n, const T *__restrict__ y, double *__res
                         Cs[tid] += (y1 - y0) - y2;          // pair (i,k)
                         Bb[jl * b + kl] += (y2 - y0) - y1;  // pair (j,k)
                     }
-                    const int un = u + D <= ulast ? u + D : ulast;
-                    const T *src = ytile + int64_t(un) * ystep;
-                    yq[d][0] = __builtin_nontemporal_load(&src[lane]);
-                    yq[d][1] = __builtin_nontemporal_load(&src[lane + bb]);
-                    yq[d][2] = __builtin_nontemporal_load(&src[lane + 2 * bb]);
+                    if (refill) {
+                        const T *src = ytile + int64_t(u + D) * ystep;
+                        yq[d][0] = __builtin_nontemporal_load(&src[lane]);
+                        yq[d][1] = __builtin_nontemporal_load(&src[lane + bb]);
+                        yq[d][2] = __builtin_nontemporal_load(&src[lane + 2 * bb]);
+                    }
                     lds_barrier();
                 }
             };
-            group(0);
+            group(0, true);
 #pragma nounroll
-            for (int t0 = D; t0 < b; t0 += D) group(t0);
+            for (int t0 = D; t0 < b - D; t0 += D) group(t0, true);
+            group(b - D, false);
 
             const bool last = (m == Q - P);
             if (idA >= 0) publish(P, J, Abuf);
