@@ -46,7 +46,7 @@ def recorded_traffic(kernel, inst, b, prec):
     """HBM bytes per launch from a committed PMC record, if the kernel's
     sources are unchanged since the counters were taken; else None."""
     import hashlib
-    wl = {"sbm_n500_k10": "sbm_n500"}.get(inst.name, inst.name)
+    wl = {"sbm_n500_k10": "sbm_n500", "chunglu_n4000_b2.2": "chunglu_n4000"}.get(inst.name, inst.name)
     path = os.path.join(ROOT, "profiles", f"{kernel}_{wl}_{prec}.traffic.json")
     if not os.path.exists(path):
         return None
@@ -157,6 +157,37 @@ def large_sweep(config=4, b=32, prec="f32", steps=5, warmup=2):
                         "kernel": "k_sweep_dataflow", "avg_launch_us": ms * 1e3,
                         "algorithmic_bytes_per_launch": nbytes}}
     del g
+    torch.cuda.empty_cache()
+    return out
+
+
+def stream_ceilings(gib=4, reps=5):
+    """Practical HBM rates of plain streaming kernels (torch ops on float32
+    buffers of `gib` GiB, HIP events): the ceilings a bandwidth-bound kernel
+    can reach on this machine, beside the 8 TB/s data-sheet peak."""
+    import torch
+    n = gib << 28
+    a = torch.ones(n, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+
+    def rate(fn, nbytes):
+        fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return nbytes / (e0.elapsed_time(e1) / reps / 1e3) / 1e9
+
+    out = {"unit": "GB/s", "buffer_bytes": 4 * n,
+           "fill": rate(lambda: b.fill_(2.0), 4 * n),
+           "read_sum": rate(lambda: a.sum(), 4 * n),
+           "add_out_of_place": rate(lambda: torch.add(a, 1.0, out=b), 8 * n),
+           "add_in_place": rate(lambda: a.add_(1.0), 8 * n),
+           "copy": rate(lambda: b.copy_(a), 8 * n)}
+    del a, b
     torch.cuda.empty_cache()
     return out
 
@@ -297,6 +328,9 @@ def main():
         log("timing the oracle ...")
         out["cpu_baseline"] = cpu_baseline(inst, args.b, args.cpu_budget)
         log(f"oracle: {out['cpu_baseline']}")
+
+    out["stream_ceilings"] = stream_ceilings()
+    log(f"stream ceilings: {out['stream_ceilings']}")
 
     if not args.no_large:
         log("n = 4000 FP32 sweep ...")
