@@ -161,6 +161,48 @@ def large_sweep(config=4, b=32, prec="f32", steps=5, warmup=2):
     return out
 
 
+def polish_report(config=2, b=32):
+    """FP32 sweeps + FP64 polish against the FP64-only solve on the n = 1500
+    Chung-Lu workload (exponent 2.5, mean degree 10, unit weights, gamma 5):
+    one-shot solves to max violation 1e-6 (cc_solve_cc_lp, host arrays in and
+    out), the FP32 phase alone to 1e-4, and the per-sweep time of each
+    precision.  Errors are against the FP64-only solution."""
+    import numpy as np
+    import torch
+    from paper_1901_10084_amd import ccproj as C
+    from paper_1901_10084_amd import instances as I
+    inst = I.workload(config)
+    res = {"workload": inst.name, "n": inst.n, "b": b}
+    for prec in ("f32", "f64"):
+        g = C.Solver.from_instance(inst, b=b, prec=prec)
+        g.sweep(2, C.CC_EXEC_DATAFLOW)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        g.sweep(5, C.CC_EXEC_DATAFLOW)
+        g.status()
+        res[f"ms_per_sweep_{prec}"] = (time.perf_counter() - t0) / 5 * 1e3
+        del g
+        torch.cuda.empty_cache()
+    runs = {}
+    for name, mode, tol in (("f64", C.CC_MODE_F64, 1e-6), ("f32_polish", C.CC_MODE_F32_POLISH, 1e-6),
+                            ("f32_only", C.CC_MODE_F32, 1e-4)):
+        t0 = time.perf_counter()
+        rc, x, _, info = C.solve_cc_lp(inst.n, inst.w, inst.d, inst.gamma, tol=tol, b=b, mode=mode)
+        wall = time.perf_counter() - t0
+        r = info["resid"]
+        runs[name] = (x, {"tol": tol, "status": rc, "seconds": wall, "sweeps": info["sweeps"],
+                          "sweeps_f32": info["sweeps_f32"], "primal_qp": r["primal_qp"],
+                          "max_viol": max(r["max_viol_metric"], r["max_viol_pair"])})
+        log(f"polish report {name}: {runs[name][1]}")
+    x64, r64 = runs["f64"]
+    for name, (x, rr) in runs.items():
+        if name != "f64":
+            rr["objective_rel_err"] = abs(rr["primal_qp"] - r64["primal_qp"]) / abs(r64["primal_qp"])
+            rr["x_max_abs_err"] = float(np.abs(x - x64).max())
+        res[name] = rr
+    return res
+
+
 def stream_ceilings(gib=4, reps=5):
     """Practical HBM rates of plain streaming kernels (torch ops on float32
     buffers of `gib` GiB, HIP events): the ceilings a bandwidth-bound kernel
@@ -225,6 +267,8 @@ def main():
     ap.add_argument("--warm-report", action="store_true",
                     help="FP64 cold vs FP32 cold vs FP32 + learned warm start, each to max "
                          "violation <= 1e-4, on workload --warm-config (tile size 32)")
+    ap.add_argument("--polish-report", action="store_true",
+                    help="n = 1500 Chung-Lu: FP32 sweeps + FP64 polish vs the FP64-only solve")
     ap.add_argument("--warm-config", type=int, default=3, choices=[3, 4],
                     help="3: n = 2000 planted partition; 4: n = 4000 Chung-Lu")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MiB",
@@ -336,6 +380,9 @@ def main():
         log("n = 4000 FP32 sweep ...")
         out["large_workload"] = large_sweep()
         log(f"large: {out['large_workload']}")
+
+    if args.polish_report:
+        out["polish"] = polish_report()
 
     if args.warm_report:
         del g
