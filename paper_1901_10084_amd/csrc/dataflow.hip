@@ -174,13 +174,26 @@ k_sweep_dataflow(DataflowArgs a, int64_t n, T *__restrict__ x, const T *__restri
 
         // element (sr, sc) of block (R, S): pair (R*b+sr, S*b+sc) when it is one
         // (zeros elsewhere); the loads are unconditional
-        auto stage = [&](int R, int S, T *X, T *G) {
+        // split in a load and a store half, so that other loads can be
+        // issued between them; padding is masked at the store
+        auto blk_ok = [&](int R, int S) {
             const int ii = R * b + sr, jj = S * b + sc;
-            const bool ok = ii < jj && jj < nn;
-            const int64_t p = ok ? pidx(ii, jj) : 0;
-            const T vx = x[p], vg = g[p];
+            return ii < jj && jj < nn;
+        };
+        auto blk_load = [&](int R, int S, T &vx, T &vg) {
+            const int64_t p = blk_ok(R, S) ? pidx(R * b + sr, S * b + sc) : 0;
+            vx = x[p];
+            vg = g[p];
+        };
+        auto blk_store = [&](int R, int S, T vx, T vg, T *X, T *G) {
+            const bool ok = blk_ok(R, S);
             X[sr * b + sc] = ok ? vx : T(0);
             G[sr * b + sc] = ok ? vg : T(0);
+        };
+        auto stage = [&](int R, int S, T *X, T *G) {
+            T vx, vg;
+            blk_load(R, S, vx, vg);
+            blk_store(R, S, vx, vg, X, G);
         };
         auto publish = [&](int R, int S, const T *X) {
             const int ii = R * b + sr, jj = S * b + sc;
@@ -222,7 +235,6 @@ k_sweep_dataflow(DataflowArgs a, int64_t n, T *__restrict__ x, const T *__restri
                 yq[d][2] = __builtin_nontemporal_load(&src[lane + 2 * bb]);
             }
         };
-        fill_ring(0);
 
         // Block (P,Q) and the first step's blocks: wait, then hold (P,Q).
         if (tid == 0) {
@@ -246,9 +258,20 @@ k_sweep_dataflow(DataflowArgs a, int64_t n, T *__restrict__ x, const T *__restri
             T *const Ax = (J == Q) ? Cx : Ax0, *const Ag = (J == Q) ? Cg : Ag0;
             T *const Bx = (J == P) ? Cx : Bx0, *const Bg = (J == P) ? Cg : Bg0;
 
-            // Stage the step's blocks (their waits are done).
-            if (idA >= 0) stage(P, J, Ax0, Ag0);
-            if (idB >= 0) stage(J, Q, Bx0, Bg0);
+            // Stage the step's blocks (their waits are done).  The step's
+            // dual ring is issued between the block loads and their use:
+            // loads complete in order, so the ring's HBM latency then
+            // overlaps the staging rather than delaying it.
+            // Loads and stores are unconditional: where A or B is the
+            // resident C block, the staging buffer it would use is idle this
+            // step and takes a copy nobody reads.  (A load under a branch is
+            // sunk behind the ring's loads, and its wait then drains them.)
+            T vax, vag, vbx, vbg;
+            blk_load(P, J, vax, vag);
+            blk_load(J, Q, vbx, vbg);
+            fill_ring(m);
+            blk_store(P, J, vax, vag, Ax0, Ag0);
+            blk_store(J, Q, vbx, vbg, Bx0, Bg0);
             lds_barrier();
             const T gC = Cg[tid];
             if (tid == 0 && a.prof) mark(1);
@@ -361,7 +384,6 @@ k_sweep_dataflow(DataflowArgs a, int64_t n, T *__restrict__ x, const T *__restri
                 aborted = true;
                 break;
             }
-            if (!last) fill_ring(m + 1);
         }
         if (aborted) break;
     }
@@ -404,11 +426,9 @@ k_aty_dataflow(DataflowArgs a, int64_t n, const T *__restrict__ y, double *__res
             const int ii = R * b + sr, jj = S * b + sc;
             return ii < jj && jj < nn;
         };
-        auto stage = [&](int R, int S, double *X) {
-            const bool ok = blk_ok(R, S);
-            const double v = ax[ok ? pidx(R * b + sr, S * b + sc) : 0];
-            X[sr * b + sc] = ok ? v : 0.0;
-        };
+        auto blk_load = [&](int R, int S) { return ax[blk_ok(R, S) ? pidx(R * b + sr, S * b + sc) : 0]; };
+        auto blk_store = [&](int R, int S, double v, double *X) { X[sr * b + sc] = blk_ok(R, S) ? v : 0.0; };
+        auto stage = [&](int R, int S, double *X) { blk_store(R, S, blk_load(R, S), X); };
         auto publish = [&](int R, int S, const double *X) {
             if (blk_ok(R, S)) ax[pidx(R * b + sr, S * b + sc)] = X[sr * b + sc];
         };
@@ -442,7 +462,6 @@ k_aty_dataflow(DataflowArgs a, int64_t n, const T *__restrict__ y, double *__res
                 yq[d][2] = __builtin_nontemporal_load(&src[lane + 2 * bb]);
             }
         };
-        fill_ring(0);
 
         if (tid == 0) {
             bool ok = wait_count(&a.cnt[idC], a.epoch * a.K[idC] + tl.needC, &a.ctl[1], a.wait_ticks);
@@ -461,8 +480,12 @@ k_aty_dataflow(DataflowArgs a, int64_t n, const T *__restrict__ y, double *__res
             step_ids(m, idA, idB);
             double *const Ab = (J == Q) ? Cs : Abuf;
             double *const Bb = (J == P) ? Cs : Bbuf;
-            if (idA >= 0) stage(P, J, Abuf);
-            if (idB >= 0) stage(J, Q, Bbuf);
+            // unconditional, as in the sweep (Abuf / Bbuf are idle where A
+            // or B is the resident block)
+            const double va = blk_load(P, J), vb = blk_load(J, Q);
+            fill_ring(m);
+            blk_store(P, J, va, Abuf);
+            blk_store(J, Q, vb, Bbuf);
             lds_barrier();
             auto group = [&](const int t0, const bool refill) {
 #pragma unroll
@@ -516,7 +539,6 @@ k_aty_dataflow(DataflowArgs a, int64_t n, const T *__restrict__ y, double *__res
                 aborted = true;
                 break;
             }
-            if (!last) fill_ring(m + 1);
         }
         if (aborted) break;
     }
