@@ -306,7 +306,9 @@ k_sweep_dataflow(DataflowArgs a, int64_t n, T *__restrict__ x, const T *__restri
                     {
                         // Every lane runs the step; a lane whose (i,j,k) is
                         // padding takes q = 0 and floor -inf, which leaves its
-                        // dual and the three distances exactly as read.  Only
+                        // dual and the three distances exactly as read (the
+                        // max returns its first operand's value whenever the
+                        // floor is 0 and that operand is not below it).  Only
                         // triplet lanes write the distances back: where the
                         // middle block is P or Q, the A or B block is the
                         // resident (P,Q) block, and a padding lane's entry can
@@ -332,7 +334,7 @@ k_sweep_dataflow(DataflowArgs a, int64_t n, T *__restrict__ x, const T *__restri
                         // Refill slot d after its duals are consumed, so the
                         // old and new values never live at once (no register
                         // copies of loads in flight).
-                        const T *src = ytile + int64_t(u + D) * ystep;
+                        const T *src = ytile + int64_t(__builtin_amdgcn_readfirstlane(u + D)) * ystep;
                         yq[d][0] = __builtin_nontemporal_load(&src[lane]);
                         yq[d][1] = __builtin_nontemporal_load(&src[lane + bb]);
                         yq[d][2] = __builtin_nontemporal_load(&src[lane + 2 * bb]);

@@ -48,15 +48,15 @@ __device__ __forceinline__ void project(T &xL, T &xS1, T &xS2, T gL, T gS1, T gS
     y = th;
 }
 
-// The same step with a per-row floor: lo = 0 gives the step above; a padding
-// lane passes q = 0 and lo = -inf, so th = y exactly and nothing moves.
-// Lets every lane run the step without a branch.
+// The same step with a per-row floor: lo = 0 gives the step above (up to the
+// sign of a zero theta); a padding lane passes q = 0 and lo = -inf, so
+// th = y exactly and nothing moves.  Lets every lane run the step without a
+// branch.
 template <typename T>
 __device__ __forceinline__ void project_lo(T &xL, T &xS1, T &xS2, T gL, T gS1, T gS2, T q,
                                            T lo, T &y) {
     T delta = (xL - xS1) - xS2;
-    T th = fma(delta, q, y);
-    th = th > lo ? th : lo;
+    T th = fmax(fma(delta, q, y), lo);
     T dlt = th - y;
     xL = fma(-dlt, gL, xL);
     xS1 = fma(dlt, gS1, xS1);
