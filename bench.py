@@ -66,7 +66,8 @@ def warm_report(config, b, tol=1e-4):
     FP32 + learned warm start.  Workload 3: the n = 2000 planted partition
     (20 blocks, p_in 0.25, p_out 0.01, gamma 5); workload 4: the n = 4000
     Chung-Lu graph (128 GB of FP32 duals; its FP64 cold solve is not run,
-    the duals would not fit twice).  Wall times include inference, the
+    the duals would not fit twice), where a network trained on n = 300
+    Chung-Lu graphs also runs if its weights exist.  Wall times include inference, the
     x-from-y pass and every residual check.  Objective errors are against an
     FP64 solve to 1e-7 (n = 4000: FP64 to 1e-6 if its 256 GB of duals can be
     allocated, else FP32 to 1e-6, as recorded in the result)."""
@@ -76,14 +77,16 @@ def warm_report(config, b, tol=1e-4):
     from paper_1901_10084_amd import warmstart as W
     inst = I.workload(config)
     deg = W.degrees(inst)
-    net = W.load()
+    nets = {"sbm300": W.load()}
+    if config == 4 and os.path.exists(W.weights_path("chunglu300")):
+        nets["chunglu300"] = W.load(W.weights_path("chunglu300"))
     res = {"workload": inst.name, "n": inst.n, "tol": tol, "b": b}
 
     def run(prec, warm, tol_run=tol):
         s = C.Solver.from_instance(inst, b=b, prec=prec)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        info = W.warm_start(s, net, deg) if warm else None
+        info = W.warm_start(s, nets[warm], deg) if warm else None
         t_warm = time.perf_counter() - t0
         r, conv, _ = s.solve(tol=tol_run, max_sweeps=20000, executor=C.CC_EXEC_DATAFLOW)
         dt = time.perf_counter() - t0
@@ -96,20 +99,23 @@ def warm_report(config, b, tol=1e-4):
         torch.cuda.empty_cache()
         return out
 
-    runs = [("f32_cold", "f32", False), ("f32_warm", "f32", True)]
+    # warm: the network (by training family) or None for the cold start
+    runs = [("f32_cold", "f32", None), ("f32_warm", "f32", "sbm300")]
+    if "chunglu300" in nets:
+        runs.append(("f32_warm_chunglu300", "f32", "chunglu300"))
     if config != 4:
-        runs.insert(0, ("f64_cold", "f64", False))
+        runs.insert(0, ("f64_cold", "f64", None))
     for name, prec, warm in runs:
         res[name] = run(prec, warm)
         log(f"warm report {name}: {res[name]}")
     ref_tol = 1e-7 if config != 4 else 1e-6
     try:
-        rr = run("f64", False, ref_tol)
+        rr = run("f64", None, ref_tol)
         res["reference"] = f"FP64 cold solve to max violation {ref_tol:g}"
     except (C.CCError, RuntimeError, torch.cuda.OutOfMemoryError) as exc:
         log(f"FP64 reference not run ({exc}); FP32 reference instead")
         torch.cuda.empty_cache()
-        rr = run("f32", False, ref_tol)
+        rr = run("f32", None, ref_tol)
         res["reference"] = f"FP32 cold solve to max violation {ref_tol:g} (FP64 did not fit)"
     pstar = rr["primal_qp"]
     for name, _, _ in runs:

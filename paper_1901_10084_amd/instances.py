@@ -169,6 +169,18 @@ def workload(idx: int) -> Instance:
     raise ValueError(idx)
 
 
-def training_graph(seed: int) -> Instance:
-    """Warm-start training instance: n=300, 3 blocks of 100, p_in=0.25, p_out=0.01."""
-    return planted_partition(300, 3, 0.25, 0.01, seed=seed, gamma=5.0)
+TRAINING_FAMILIES = ("sbm300", "chunglu300")
+
+
+def training_graph(seed: int, family: str = "sbm300") -> Instance:
+    """Warm-start training instance.
+
+    sbm300: n=300, 3 blocks of 100, p_in=0.25, p_out=0.01, unit weights,
+    gamma=5 (the n=2000 planted partition's densities).
+    chunglu300: n=300 Chung-Lu, exponent 2.2, mean degree 20, weights
+    U[0.5, 1.5], gamma=10 (the n=4000 Chung-Lu workload's shape)."""
+    if family == "sbm300":
+        return planted_partition(300, 3, 0.25, 0.01, seed=seed, gamma=5.0)
+    if family == "chunglu300":
+        return chung_lu(300, 2.2, 20.0, seed=seed, gamma=10.0, weights="uniform_0.5_1.5")
+    raise ValueError(family)

@@ -18,6 +18,10 @@ from . import instances as I
 
 WEIGHTS_DIR = os.path.join(os.path.dirname(os.path.abspath(__file__)), "weights")
 DEFAULT_WEIGHTS = os.path.join(WEIGHTS_DIR, "warm_start_sbm300.npy")
+
+
+def weights_path(family: str = "sbm300") -> str:
+    return os.path.join(WEIGHTS_DIR, f"warm_start_{family}.npy")
 NPARAM = int(C._L.cc_mlp_num_params())
 
 
@@ -119,14 +123,14 @@ def degrees(inst, device="cuda"):
 
 
 def train(seeds=range(1000, 1200), tol=1e-6, b=16, batch=8192, steps_per_graph=40, lr=2e-3,
-          net_seed=0, log=None):
+          net_seed=0, log=None, family="sbm300"):
     """Train on the converged FP64 duals of the warm-start training graphs
-    (planted partitions, n = 300), one graph at a time."""
+    (n = 300, see instances.training_graph), one graph at a time."""
     net = Network(seed=net_seed)
     t0 = time.perf_counter()
     hist = []
     for e, seed in enumerate(seeds):
-        inst = I.training_graph(seed)
+        inst = I.training_graph(seed, family)
         s = C.Solver.from_instance(inst, b=b, prec="f64")
         r, conv, _ = s.solve(tol=tol, max_sweeps=20000, executor=C.CC_EXEC_DATAFLOW)
         losses = net.train_on_graph(s, s.y, degrees(inst), batch, steps_per_graph, lr, seed)
@@ -148,7 +152,12 @@ def load(path=DEFAULT_WEIGHTS) -> Network:
 
 
 if __name__ == "__main__":
-    import sys
-    net, hist = train(log=lambda m: print(m, flush=True))
-    save(net)
-    print("saved", DEFAULT_WEIGHTS, file=sys.stderr)
+    import argparse
+    ap = argparse.ArgumentParser(description="train the warm-start network on solved graphs")
+    ap.add_argument("--family", default="sbm300", choices=I.TRAINING_FAMILIES)
+    ap.add_argument("--out", default=None, help="weights file (default: weights/warm_start_<family>.npy)")
+    args = ap.parse_args()
+    net, hist = train(log=lambda m: print(m, flush=True), family=args.family)
+    out = args.out or weights_path(args.family)
+    save(net, out)
+    print("saved", out, flush=True)
