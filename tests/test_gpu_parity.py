@@ -235,6 +235,8 @@ def test_duals_nonnegative_and_stationary():
 # --------------------------------------------------------------------------
 @pytest.mark.parametrize("n,b,prec,K", [(60, 8, "f64", 3), (61, 8, "f64", 2), (100, 16, "f64", 3),
                                         (130, 32, "f64", 2), (200, 16, "f32", 3),
+                                        (150, 32, "f32", 2), (3, 8, "f64", 2), (5, 8, "f64", 2),
+                                        (16, 16, "f64", 2), (17, 16, "f32", 2), (33, 32, "f64", 2),
                                         (500, 16, "f64", 2)])
 def test_dataflow_equals_rounds(n, b, prec, K):
     inst = I.workload(1) if n == 500 else I.random_signed(n, seed=n, gamma=2.0, weighted=True)
@@ -247,6 +249,23 @@ def test_dataflow_equals_rounds(n, b, prec, K):
     for name in ("x", "f", "y", "y_pair"):
         a, bb = getattr(r, name), getattr(d, name)
         assert torch.equal(a, bb), (name, float((a - bb).abs().max()))
+
+
+def test_dataflow_breakdown_counts_every_step():
+    """The diagnostic sweep runs the same updates (same bits as a plain
+    dataflow sweep) and counts every tile step once."""
+    n, b = 100, 16
+    inst = I.random_signed(n, seed=3, gamma=1.0, weighted=True)
+    a = C.Solver.from_instance(inst, b=b)
+    c = C.Solver.from_instance(inst, b=b)
+    a.sweep_metric(C.CC_EXEC_DATAFLOW)
+    a.status()
+    br = c.ctx.dataflow_breakdown(c.x, c.y, c.g)
+    nb = (n + b - 1) // b
+    assert br["tile_steps"] == nb * (nb + 1) * (nb + 2) // 6
+    assert br["workgroups"] >= 1
+    assert all(br[k] >= 0 for k in ("wait_us", "load_us", "substeps_us", "publish_us"))
+    assert torch.equal(a.x, c.x) and torch.equal(a.y, c.y)
 
 
 def test_dataflow_parity_oracle():
