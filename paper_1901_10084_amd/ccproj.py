@@ -156,6 +156,13 @@ class Context:
     def handle(self):
         return self._h
 
+    def executor(self, executor=None):
+        """The given executor, or by default the dataflow executor where it
+        exists (b = 8, 16, 32) and the round-by-round one elsewhere."""
+        if executor is not None:
+            return int(executor)
+        return CC_EXEC_DATAFLOW if self.b in (8, 16, 32) else CC_EXEC_ROUNDS
+
     def close(self):
         if getattr(self, "_h", None):
             _L.cc_destroy(self._h)
@@ -173,15 +180,15 @@ class Context:
     def init_cold(self, x, f, y, y_pair, gamma):
         check(_L.cc_init_cold(self._h, _ptr(x), _ptr(f), _ptr(y), _ptr(y_pair), float(gamma)))
 
-    def sweep(self, x, f, y, y_pair, g, d, nsweeps=1, executor=CC_EXEC_ROUNDS):
+    def sweep(self, x, f, y, y_pair, g, d, nsweeps=1, executor=None):
         check(_L.cc_sweep(self._h, _ptr(x), _ptr(f), _ptr(y), _ptr(y_pair), _ptr(g), _ptr(d),
-                          int(nsweeps), int(executor)))
+                          int(nsweeps), self.executor(executor)))
 
     def sweep_rounds(self, x, y, g, first, count):
         check(_L.cc_sweep_rounds(self._h, _ptr(x), _ptr(y), _ptr(g), int(first), int(count)))
 
-    def sweep_metric(self, x, y, g, executor=CC_EXEC_ROUNDS):
-        check(_L.cc_sweep_metric(self._h, _ptr(x), _ptr(y), _ptr(g), int(executor)))
+    def sweep_metric(self, x, y, g, executor=None):
+        check(_L.cc_sweep_metric(self._h, _ptr(x), _ptr(y), _ptr(g), self.executor(executor)))
 
     def status(self):
         check(_L.cc_status(self._h))
@@ -296,14 +303,14 @@ class Solver:
         self.ctx.init_cold(self.x, self.f, self.y, self.y_pair, self.gamma)
         self.sweeps = 0
 
-    def sweep(self, nsweeps=1, executor=CC_EXEC_ROUNDS):
+    def sweep(self, nsweeps=1, executor=None):
         self.ctx.sweep(self.x, self.f, self.y, self.y_pair, self.g, self.d, nsweeps, executor)
         self.sweeps += nsweeps
 
     def sweep_rounds(self, first, count):
         self.ctx.sweep_rounds(self.x, self.y, self.g, first, count)
 
-    def sweep_metric(self, executor=CC_EXEC_ROUNDS):
+    def sweep_metric(self, executor=None):
         self.ctx.sweep_metric(self.x, self.y, self.g, executor)
 
     def status(self):
@@ -327,7 +334,7 @@ class Solver:
         self.ctx.duals_to_lex(self.y, y_lex)
         return y_lex
 
-    def solve(self, tol=1e-6, max_sweeps=100000, check_every=None, executor=CC_EXEC_ROUNDS):
+    def solve(self, tol=1e-6, max_sweeps=100000, check_every=None, executor=None):
         """Sweep until both max violations are <= tol, checked every
         `check_every` sweeps (default as in cc_solve_cc_lp: every sweep up to
         n = 1000, every 5 above; a check reads every triplet).  Returns
