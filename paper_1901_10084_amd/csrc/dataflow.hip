@@ -15,10 +15,13 @@
 // wall-clock limit; a timed-out wait raises an abort flag that every other
 // wait also checks, so the grid always drains.
 //
-// Memory ordering across the chip's L2 slices: a tile step writes its x
-// blocks back, then one thread releases (agent-scope release: L2 write-back)
-// before bumping the counters; a waiting tile acquires (agent-scope acquire:
-// L2 invalidate) before reading them.
+// Memory ordering across the chip's per-XCD L2 caches: the shared x blocks
+// are read and written only with agent-scope atomic loads and stores, which
+// every CU observes coherently.  A tile step stores its blocks, every wave
+// waits until its stores are complete, and then one thread bumps the
+// counters; a waiting tile polls the counters (agent-scope loads) before it
+// loads the blocks.  No L2 write-back is needed: the dual stream, which is
+// private to its tile, stays out of the release.
 #include <vector>
 
 #include "common.hpp"
@@ -145,9 +148,9 @@ k_sweep_dataflow(DataflowArgs a, int64_t n, T *__restrict__ x, const T *__restri
     // Per tile step: sub-steps, publish the step's blocks, then one thread-0
     // region that releases them and waits for the next step's blocks.  The
     // dual ring is refilled for the next step only after that release, so
-    // the release's drain of the memory counter (agent-scope release waits
-    // for every outstanding access of the wave) covers the published stores
-    // rather than a full ring of prefetched duals.
+    // the release's drain of the memory counter (each wave waits for every
+    // outstanding access) covers the published stores rather than a full
+    // ring of prefetched duals.
     //
     // optional breakdown (thread 0): [0] waiting for blocks, [1] loading
     // blocks into LDS, [2] sub-steps, [3] publishing, [4] tile steps
@@ -180,9 +183,11 @@ k_sweep_dataflow(DataflowArgs a, int64_t n, T *__restrict__ x, const T *__restri
             const int ii = R * b + sr, jj = S * b + sc;
             return ii < jj && jj < nn;
         };
+        // x of a block is read and written with agent-scope atomic accesses
+        // (coherent across the chip's L2 caches); g never changes.
         auto blk_load = [&](int R, int S, T &vx, T &vg) {
             const int64_t p = blk_ok(R, S) ? pidx(R * b + sr, S * b + sc) : 0;
-            vx = x[p];
+            vx = __hip_atomic_load(&x[p], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             vg = g[p];
         };
         auto blk_store = [&](int R, int S, T vx, T vg, T *X, T *G) {
@@ -197,7 +202,8 @@ k_sweep_dataflow(DataflowArgs a, int64_t n, T *__restrict__ x, const T *__restri
         };
         auto publish = [&](int R, int S, const T *X) {
             const int ii = R * b + sr, jj = S * b + sc;
-            if (ii < jj && jj < nn) x[pidx(ii, jj)] = X[sr * b + sc];
+            if (ii < jj && jj < nn)
+                __hip_atomic_store(&x[pidx(ii, jj)], X[sr * b + sc], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         };
         // blocks (P,J) and (J,Q) of step m, -1 where the step uses (P,Q)
         auto step_ids = [&](int m, int &idA, int &idB) {
@@ -354,14 +360,16 @@ k_sweep_dataflow(DataflowArgs a, int64_t n, T *__restrict__ x, const T *__restri
             if (idA >= 0) publish(P, J, Ax0);
             if (idB >= 0) publish(J, Q, Bx0);
             if (last) publish(P, Q, Cx);
+            // Release: every wave waits until its agent-scope stores are
+            // complete (performed where every CU's agent-scope loads read),
+            // then thread 0 raises the counters.  The readers poll the
+            // counters and then load the blocks with agent-scope loads.  An
+            // agent-scope release fence would add a write-back of every dirty
+            // line in this XCD's L2, the dual stream's included, on every
+            // tile step; that cost a quarter of the sweep time.
+            __builtin_amdgcn_s_waitcnt(0);
             __syncthreads();
             if (tid == 0) {
-                // One release fence covers every block of the step; the
-                // counter increments after it are relaxed (a release fence
-                // before an atomic write synchronises with the reader's
-                // acquire fence).  Each release-ordered atomic would repeat
-                // the L2 write-back and the drain.
-                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
                 if (idA >= 0) __hip_atomic_fetch_add(&a.cnt[idA], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                 if (idB >= 0) __hip_atomic_fetch_add(&a.cnt[idB], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                 bool ok = true;
@@ -428,11 +436,18 @@ k_aty_dataflow(DataflowArgs a, int64_t n, const T *__restrict__ y, double *__res
             const int ii = R * b + sr, jj = S * b + sc;
             return ii < jj && jj < nn;
         };
-        auto blk_load = [&](int R, int S) { return ax[blk_ok(R, S) ? pidx(R * b + sr, S * b + sc) : 0]; };
+        // ax is read and written with agent-scope atomic accesses, released
+        // as in the sweep: stores complete in every wave, then the counters.
+        auto blk_load = [&](int R, int S) {
+            return __hip_atomic_load(&ax[blk_ok(R, S) ? pidx(R * b + sr, S * b + sc) : 0], __ATOMIC_RELAXED,
+                                     __HIP_MEMORY_SCOPE_AGENT);
+        };
         auto blk_store = [&](int R, int S, double v, double *X) { X[sr * b + sc] = blk_ok(R, S) ? v : 0.0; };
         auto stage = [&](int R, int S, double *X) { blk_store(R, S, blk_load(R, S), X); };
         auto publish = [&](int R, int S, const double *X) {
-            if (blk_ok(R, S)) ax[pidx(R * b + sr, S * b + sc)] = X[sr * b + sc];
+            if (blk_ok(R, S))
+                __hip_atomic_store(&ax[pidx(R * b + sr, S * b + sc)], X[sr * b + sc], __ATOMIC_RELAXED,
+                                   __HIP_MEMORY_SCOPE_AGENT);
         };
         auto step_ids = [&](int m, int &idA, int &idB) {
             const int J = tile_J(P, Q, m, desc);
@@ -520,9 +535,9 @@ k_aty_dataflow(DataflowArgs a, int64_t n, const T *__restrict__ y, double *__res
             if (idA >= 0) publish(P, J, Abuf);
             if (idB >= 0) publish(J, Q, Bbuf);
             if (last) publish(P, Q, Cs);
+            __builtin_amdgcn_s_waitcnt(0);
             __syncthreads();
             if (tid == 0) {
-                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
                 if (idA >= 0) __hip_atomic_fetch_add(&a.cnt[idA], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                 if (idB >= 0) __hip_atomic_fetch_add(&a.cnt[idB], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                 bool ok = true;
