@@ -397,7 +397,8 @@ def main():
         torch.cuda.empty_cache()
         out["warm_start"] = warm_report(args.warm_config, 32)
 
-    out["gpu"] = torch.cuda.get_device_name(0)
+    props = torch.cuda.get_device_properties(0)
+    out["gpu"] = torch.cuda.get_device_name(0) or getattr(props, "gcnArchName", "")
     print(json.dumps(out), flush=True)
 
 

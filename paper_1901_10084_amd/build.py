@@ -16,6 +16,9 @@ HIPCC_FLAGS = [
     "-ffp-contract=off",
     # no packed FP32 instructions anywhere
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    # MFMA accumulators in VGPRs: the network's layers feed each other
+    # through VALU work, which cannot read AGPRs (saves a copy per value)
+    "-mllvm", "-amdgpu-mfma-vgpr-form",
     "-Wall", "-Wno-unused-function",
 ]
 

@@ -60,16 +60,6 @@ template <typename T> int launch_aty_dataflow(const DataflowArgs &, int, int, in
 template <typename T> int aty_dataflow_occupancy(int, int *);
 int launch_fill_u32(int64_t, uint32_t *, hipStream_t);
 
-struct GraphView {
-    const Tile *tiles;
-    int64_t ntiles;
-    int b;
-    int64_t n;
-    const double *w;
-    const uint8_t *d;
-    const float *deg;
-    const float *mean_deg;
-};
 int mlp_num_params();
 size_t mlp_workspace_bytes(int64_t count);
 int mlp_grad_blocks(int64_t count);
@@ -116,6 +106,8 @@ struct cc_ctx {
     int aty_grid = 0;
     uint64_t wait_ticks = 0;
     float *d_mean_deg = nullptr;  // warm-start features
+    int32_t *d_chunks = nullptr;  // warm-start inference chunks (built on first use)
+    int64_t nchunks = 0;
 };
 
 namespace {
@@ -431,6 +423,7 @@ int cc_destroy(cc_ctx *c) {
     (void)hipFree(c->d_cnt);
     (void)hipFree(c->d_ctl);
     (void)hipFree(c->d_mean_deg);
+    (void)hipFree(c->d_chunks);
     delete c;
     return CC_OK;
 }
@@ -649,9 +642,29 @@ int graph_view(cc_ctx *c, const double *w, const uint8_t *d, const float *deg, G
         c->d_mean_deg = nullptr;
         return fail(CC_ENOMEM, "hipMalloc failed");
     }
+    if (!c->d_chunks) {
+        std::vector<Tile> tiles(size_t(c->ntiles));
+        if (hipMemcpy(tiles.data(), c->d_tiles, tiles.size() * sizeof(Tile), hipMemcpyDeviceToHost) !=
+            hipSuccess)
+            return fail(CC_EHIP, "hipMemcpy failed");
+        std::vector<int32_t> ch;
+        for (int64_t t = 0; t < c->ntiles; ++t)
+            for (int m0 = 0; m0 <= tiles[t].Q - tiles[t].P; m0 += kInferChunk) {
+                ch.push_back(int32_t(t));
+                ch.push_back(m0);
+            }
+        if (hipMalloc(&c->d_chunks, ch.size() * sizeof(int32_t)) != hipSuccess) {
+            c->d_chunks = nullptr;
+            return fail(CC_ENOMEM, "hipMalloc failed");
+        }
+        if (hipMemcpy(c->d_chunks, ch.data(), ch.size() * sizeof(int32_t), hipMemcpyHostToDevice) !=
+            hipSuccess)
+            return fail(CC_EHIP, "hipMemcpy failed");
+        c->nchunks = int64_t(ch.size() / 2);
+    }
     int rc = launch_mean_deg(deg, c->n, c->d_mean_deg, c->stream);
     if (rc) return rc;
-    G = GraphView{c->d_tiles, c->ntiles, c->b, c->n, w, d, deg, c->d_mean_deg};
+    G = GraphView{c->d_tiles, c->ntiles, c->b, c->n, w, d, deg, c->d_mean_deg, c->d_chunks, c->nchunks};
     return CC_OK;
 }
 

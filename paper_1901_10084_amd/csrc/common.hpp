@@ -18,6 +18,25 @@ struct Tile {
     int64_t ybase;
 };
 
+// Warm-start inference walks each tile in chunks of at most this many tile
+// steps, one workgroup per chunk: whole tiles (1 to nb steps) leave most of
+// the chip idle behind the longest ones.
+constexpr int kInferChunk = 4;
+
+// What the warm-start kernels read of the graph and the schedule.
+struct GraphView {
+    const Tile *tiles;
+    int64_t ntiles;
+    int b;
+    int64_t n;
+    const double *w;
+    const uint8_t *d;
+    const float *deg;
+    const float *mean_deg;
+    const int32_t *chunks;  // (tile, first step) per inference chunk
+    int64_t nchunks;
+};
+
 // Packed column-major upper-triangular pair index, i < j.
 __host__ __device__ __forceinline__ int64_t pidx(int64_t i, int64_t j) {
     return j * (j - 1) / 2 + i;

@@ -124,16 +124,6 @@ __device__ __forceinline__ void forward(const LaneNet &N, const float phi[4], Fw
 // (s_ab w_ab, s_ac w_ac, s_bc w_bc, (deg_a + deg_b) / (2 mean deg)),
 // s = +1 for a positive pair, -1 for a negative one.  Rounded to bf16.
 // ---------------------------------------------------------------------------
-struct GraphView {
-    const Tile *tiles;
-    int64_t ntiles;
-    int b;
-    int64_t n;
-    const double *w;
-    const uint8_t *d;
-    const float *deg;
-    const float *mean_deg;
-};
 
 // Decodes schedule slot s of tile tl; false for padding.
 __device__ __forceinline__ bool decode_slot(const Tile &tl, int64_t s, int b, int64_t n, int64_t &i,
@@ -418,25 +408,108 @@ k_mlp_infer(GraphView G, const float *__restrict__ P, T *__restrict__ y) {
     }
 }
 
-// The same inference for b = 8, 16, 32, walking the tile's segment in its
-// own order instead of decoding every slot: per tile step the signed weights
-// of blocks (P,J), (J,Q), (P,Q) and the degrees of the three vertex blocks
-// sit in LDS, a wave takes 64 consecutive slots (one sub-step t, one
-// orientation o, lanes L0..L0+63) as four 16-row forward passes, and lane l
-// keeps the output of slot L0 + l, so the store is contiguous.  Features and
-// outputs are those of k_mlp_infer bit for bit.
+// Inference-only form of the network: all three layers on
+// v_mfma_f32_16x16x32_bf16, biases entering as the accumulator input.
+//   layer 1: A = W1 with K padded from 4 to 32, the 4 real columns repeated
+//            in every lane group's K slots; B = the features of the pass's
+//            16 samples in the K slots of one lane group, zero elsewhere.
+//            Lane l receives units U_g of sample l % 16: layer 2's B operand.
+//   layer 2: as in forward().
+//   layer 3: A = W3 (permuted like K) on every row, so every row of the
+//            output is the sample's pre-activation.
+// A 64-slot group runs as four passes; in pass q the samples are those of
+// lane group q, and lane l of that group holds sample l itself.  Each lane
+// therefore computes the features of its own sample once and keeps the
+// output of its own sample.
+struct InferNet {
+    bf16x8 a1[2];  // a1[t][c] = W1[16t + i][c] for c < 4, else 0 (c = K slot in the lane group)
+    bf16x8 a2[2];  // as LaneNet::a2
+    bf16x8 a3;     // a3[c] = W3[U_g[c]]
+    f32x4 c1[2];   // c1[t][r] = b1[16t + 4g + r]
+    f32x4 c2[2];   // c2[t][r] = b2[16t + 4g + r]
+    float b3;
+};
+
+__device__ __forceinline__ void load_infer_net(InferNet &N, const float *__restrict__ P) {
+    const int lane = threadIdx.x & 63, i = lane & 15, g = lane >> 4;
+#pragma unroll
+    for (int t = 0; t < 2; ++t) {
+#pragma unroll
+        for (int c = 0; c < 8; ++c) {
+            N.a1[t][c] = tobf(c < 4 ? P[oW1 + (16 * t + i) * 4 + c] : 0.0f);
+            N.a2[t][c] = tobf(P[oW2 + (16 * t + i) * 32 + unit_of(g, c)]);
+        }
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            N.c1[t][r] = P[oB1 + 16 * t + 4 * g + r];
+            N.c2[t][r] = P[oB2 + 16 * t + 4 * g + r];
+        }
+    }
+#pragma unroll
+    for (int c = 0; c < 8; ++c) N.a3[c] = tobf(P[oW3 + unit_of(g, c)]);
+    N.b3 = P[oB3];
+}
+
+// ReLU of a rounded bf16 pair: as 16-bit integers, negative values (and -0)
+// are exactly those below 0, so one packed integer max clears them.
+// Rounding commutes with ReLU (a negative value rounds to a value <= 0).
+__device__ __forceinline__ bf16x2 relu2(const bf16x2 h) {
+    typedef __attribute__((ext_vector_type(2))) short s16x2;
+    const s16x2 zero = {0, 0};
+    return __builtin_bit_cast(bf16x2, __builtin_elementwise_max(__builtin_bit_cast(s16x2, h), zero));
+}
+
+// ReLU of two 4-row accumulators, rounded to bf16, in the K order U_g.
+__device__ __forceinline__ bf16x8 relu_bf16(const f32x4 lo, const f32x4 hi) {
+    bf16x8 h;
+#pragma unroll
+    for (int r = 0; r < 4; r += 2) {
+        const bf16x2 u = relu2(tobf2(lo[r], lo[r + 1]));
+        const bf16x2 v = relu2(tobf2(hi[r], hi[r + 1]));
+        h[r] = u[0];
+        h[r + 1] = u[1];
+        h[4 + r] = v[0];
+        h[5 + r] = v[1];
+    }
+    return h;
+}
+
+// One pass: the network's output for sample l % 16 of the lane group whose
+// features x carries (x is zero in the other lane groups).
+__device__ __forceinline__ float infer_pass(const InferNet &N, const bf16x8 x) {
+    const f32x4 z10 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(N.a1[0], x, N.c1[0], 0, 0, 0);
+    const f32x4 z11 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(N.a1[1], x, N.c1[1], 0, 0, 0);
+    const bf16x8 h1 = relu_bf16(z10, z11);
+    const f32x4 z20 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(N.a2[0], h1, N.c2[0], 0, 0, 0);
+    const f32x4 z21 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(N.a2[1], h1, N.c2[1], 0, 0, 0);
+    const bf16x8 h2 = relu_bf16(z20, z21);
+    const f32x4 c3 = {N.b3, N.b3, N.b3, N.b3};
+    const f32x4 z3 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(N.a3, h2, c3, 0, 0, 0);
+    return z3[0] > 0.0f ? z3[0] : 0.0f;
+}
+
+// The inference for b = 8, 16, 32, walking the tile's segment in its own
+// order instead of decoding every slot.  A workgroup takes one chunk of a
+// tile's steps.  Per tile step the signed weights of blocks (P,J), (J,Q),
+// (P,Q) and the degrees of the three vertex blocks sit in LDS, and a wave
+// takes 64 consecutive slots (one sub-step t, one orientation o, lanes
+// L0..L0+63), lane l computing the features and the output of slot L0 + l,
+// so the store is contiguous.  Features are those of k_mlp_infer bit for
+// bit; outputs differ only in fp32 summation order.
 template <typename T, int B>
 __global__ void __launch_bounds__(256)
 k_mlp_infer_tiled(GraphView G, const float *__restrict__ P, T *__restrict__ y) {
     constexpr int b = B, bb = B * B;
-    LaneNet N;
-    load_net(N, P);
-    const int lane = threadIdx.x & 63, si = lane & 15, g = lane >> 4;
+    InferNet N;
+    load_infer_net(N, P);
+    const int lane = threadIdx.x & 63, g = lane >> 4;
     const int wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
-    const Tile tl = G.tiles[blockIdx.x];
+    const int m0 = G.chunks[2 * int64_t(blockIdx.x) + 1];
+    const Tile tl = G.tiles[G.chunks[2 * int64_t(blockIdx.x)]];
     const int Pb = tl.P, Qb = tl.Q;
     const int nn = int(G.n), nb = (nn + b - 1) / b;
     const bool desc = tile_desc(Pb, Qb, nb);
+    const int m1 = min(m0 + kInferChunk, Qb - Pb + 1);  // this chunk's steps: [m0, m1)
     __shared__ float swA[bb], swB[bb], swC[bb], fA[bb], fB[bb], fC[bb], dP[b], dJ[b], dQ[b];
     const float md = G.mean_deg[0];
     const float den = 2.0f * md;
@@ -460,7 +533,8 @@ k_mlp_infer_tiled(GraphView G, const float *__restrict__ P, T *__restrict__ y) {
     }
     T *const ytile = y + tl.ybase;
     constexpr int gps = 3 * bb / 64;  // 64-slot groups per sub-step
-    for (int m = 0; m <= Qb - Pb; ++m) {
+    const bf16x8 zero8 = {};
+    for (int m = m0; m < m1; ++m) {
         const int J = tile_J(Pb, Qb, m, desc);
         __syncthreads();  // the last step's readers are done
         for (int e = threadIdx.x; e < b; e += blockDim.x) dJ[e] = degv(J * b + e);
@@ -475,28 +549,32 @@ k_mlp_infer_tiled(GraphView G, const float *__restrict__ P, T *__restrict__ y) {
         for (int grp = wave; grp < b * gps; grp += nw) {
             const int t = grp / gps, rem = grp - t * gps;
             const int o = rem / (bb / 64), L0 = (rem - o * (bb / 64)) * 64;
+            const int L = L0 + lane;
+            const int il = L / b, kl = L % b;
+            const int jl = mid_offset(t, il, kl, b);
+            const int i = Pb * b + il, j = J * b + jl, k = Qb * b + kl;
+            const bool ok = i < j && j < k && k < nn;
+            const int eA = il * b + jl, eC = il * b + kl, eB = jl * b + kl;
+            const float wij = swA[eA], wik = swC[eC], wjk = swB[eB];
+            // o is the same for the whole group: long side ij, ik or jk
+            const float p0 = o == 0 ? wij : (o == 1 ? wik : wjk);
+            const float p1 = o == 0 ? wik : wij;
+            const float p2 = o == 0 ? wjk : (o == 1 ? wjk : wik);
+            const float p3 = o == 0 ? fA[eA] : (o == 1 ? fC[eC] : fB[eB]);
+            const bf16x2 f01 = tobf2(ok ? p0 : 0.0f, ok ? p1 : 0.0f);
+            const bf16x2 f23 = tobf2(ok ? p2 : 0.0f, ok ? p3 : 0.0f);
+            bf16x8 feat = zero8;
+            feat[0] = f01[0];
+            feat[1] = f01[1];
+            feat[2] = f23[0];
+            feat[3] = f23[1];
             float out = 0.0f;
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
-                const int L = L0 + 16 * q + si;
-                const int il = L / b, kl = L % b;
-                const int jl = mid_offset(t, il, kl, b);
-                const int i = Pb * b + il, j = J * b + jl, k = Qb * b + kl;
-                const bool ok = i < j && j < k && k < nn;
-                const int eA = il * b + jl, eC = il * b + kl, eB = jl * b + kl;
-                const float wij = swA[eA], wik = swC[eC], wjk = swB[eB];
-                // o is the same for the whole group: long side ij, ik or jk
-                float phi[4];
-                phi[0] = o == 0 ? wij : (o == 1 ? wik : wjk);
-                phi[1] = o == 0 ? wik : wij;
-                phi[2] = o == 0 ? wjk : (o == 1 ? wjk : wik);
-                phi[3] = o == 0 ? fA[eA] : (o == 1 ? fC[eC] : fB[eB]);
-                if (!ok) phi[0] = phi[1] = phi[2] = phi[3] = 0.0f;
-                Fwd F;
-                forward(N, phi, F);
-                if (g == q) out = ok ? F.y : 0.0f;
+                const float yq = infer_pass(N, g == q ? feat : zero8);
+                if (g == q) out = yq;
             }
-            ytile[(int64_t(m) * b + t) * 3 * bb + o * bb + L0 + lane] = T(out / outscale);
+            ytile[(int64_t(m) * b + t) * 3 * bb + o * bb + L] = T(ok ? out / outscale : 0.0f);
         }
     }
 }
@@ -605,9 +683,9 @@ int launch_mlp_forward(const float *P, const float *phi, int64_t count, float *y
 template <typename T>
 int launch_mlp_infer(const GraphView &G, const float *P, T *y, hipStream_t s) {
     switch (G.b) {
-        case 8: hipLaunchKernelGGL((k_mlp_infer_tiled<T, 8>), dim3(unsigned(G.ntiles)), dim3(256), 0, s, G, P, y); break;
-        case 16: hipLaunchKernelGGL((k_mlp_infer_tiled<T, 16>), dim3(unsigned(G.ntiles)), dim3(256), 0, s, G, P, y); break;
-        case 32: hipLaunchKernelGGL((k_mlp_infer_tiled<T, 32>), dim3(unsigned(G.ntiles)), dim3(256), 0, s, G, P, y); break;
+        case 8: hipLaunchKernelGGL((k_mlp_infer_tiled<T, 8>), dim3(unsigned(G.nchunks)), dim3(256), 0, s, G, P, y); break;
+        case 16: hipLaunchKernelGGL((k_mlp_infer_tiled<T, 16>), dim3(unsigned(G.nchunks)), dim3(256), 0, s, G, P, y); break;
+        case 32: hipLaunchKernelGGL((k_mlp_infer_tiled<T, 32>), dim3(unsigned(G.nchunks)), dim3(256), 0, s, G, P, y); break;
         default: hipLaunchKernelGGL(k_mlp_infer<T>, dim3(unsigned(G.ntiles)), dim3(256), 0, s, G, P, y); break;
     }
     CCP_LAUNCH_CHECK("k_mlp_infer");
