@@ -196,13 +196,13 @@ int ensure_dataflow(cc_ctx *c) {
     if (hipMalloc(&c->d_dtiles, tiles.size() * sizeof(DTile)) != hipSuccess ||
         hipMalloc(&c->d_needs, needs.size() * sizeof(uint32_t)) != hipSuccess ||
         hipMalloc(&c->d_K, K.size() * sizeof(uint32_t)) != hipSuccess ||
-        hipMalloc(&c->d_cnt, K.size() * sizeof(uint32_t)) != hipSuccess ||
+        hipMalloc(&c->d_cnt, K.size() * kCntStride * sizeof(uint32_t)) != hipSuccess ||
         hipMalloc(&c->d_ctl, 4 * sizeof(uint32_t)) != hipSuccess)
         return fail(CC_ENOMEM, "hipMalloc of dataflow tables failed");
     CCP_HIP_CHECK(hipMemcpy(c->d_dtiles, tiles.data(), tiles.size() * sizeof(DTile), hipMemcpyHostToDevice));
     CCP_HIP_CHECK(hipMemcpy(c->d_needs, needs.data(), needs.size() * sizeof(uint32_t), hipMemcpyHostToDevice));
     CCP_HIP_CHECK(hipMemcpy(c->d_K, K.data(), K.size() * sizeof(uint32_t), hipMemcpyHostToDevice));
-    int rc = launch_fill_u32(c->nblocks, c->d_cnt, c->stream);
+    int rc = launch_fill_u32(c->nblocks * kCntStride, c->d_cnt, c->stream);
     if (rc) return rc;
     if ((rc = launch_fill_u32(4, c->d_ctl, c->stream))) return rc;
     c->epoch = 0;
@@ -213,12 +213,19 @@ int ensure_dataflow(cc_ctx *c) {
     CCP_HIP_CHECK(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
     CCP_HIP_CHECK(hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev));
     if (per_cu < 1) return fail(CC_EHIP, "dataflow kernel does not fit on a compute unit");
-    c->df_grid = int(std::min<int64_t>(c->ntiles, int64_t(per_cu) * cus));
+    // Workgroups beyond the schedule's average parallelism only wait, and
+    // their polls slow the handoffs on the critical path: at most about
+    // (total tile steps) / (critical path) = nb(nb+1)(nb+2)/6 / (4 nb) are
+    // useful at once.
+    const int64_t nbl = c->nb;
+    const int64_t useful = std::max<int64_t>(1, (nbl + 1) * (nbl + 2) / 24);
+    const int64_t need_per_cu = std::max<int64_t>(1, (useful + cus - 1) / cus);
+    c->df_grid = int(std::min<int64_t>(c->ntiles, std::min<int64_t>(per_cu, need_per_cu) * cus));
     rc = (c->prec == CC_F64) ? aty_dataflow_occupancy<double>(c->b, &per_cu)
                              : aty_dataflow_occupancy<float>(c->b, &per_cu);
     if (rc) return rc;
     if (per_cu < 1) return fail(CC_EHIP, "dataflow A'y kernel does not fit on a compute unit");
-    c->aty_grid = int(std::min<int64_t>(c->ntiles, int64_t(per_cu) * cus));
+    c->aty_grid = int(std::min<int64_t>(c->ntiles, std::min<int64_t>(per_cu, need_per_cu) * cus));
     c->wait_ticks = uint64_t(khz > 0 ? khz : 100000) * 1000ull * 10ull;  // 10 s per wait
     return CC_OK;
 }
@@ -245,7 +252,7 @@ int check_dataflow(cc_ctx *c) {
     CCP_HIP_CHECK(hipStreamSynchronize(c->stream));
     if (ctl[1]) {
         // a wait timed out: the state is incomplete; reset the counters
-        (void)launch_fill_u32(c->nblocks, c->d_cnt, c->stream);
+        (void)launch_fill_u32(c->nblocks * kCntStride, c->d_cnt, c->stream);
         (void)launch_fill_u32(4, c->d_ctl, c->stream);
         c->epoch = 0;
         return fail(CC_EHIP, "dataflow sweep aborted: a dependency wait timed out");
@@ -259,7 +266,7 @@ int dataflow_args(cc_ctx *c, unsigned long long *prof, DataflowArgs &a) {
     int rc = ensure_dataflow(c);
     if (rc) return rc;
     if (uint64_t(c->epoch + 1) * c->kmax >= (1ull << 31)) {
-        if ((rc = launch_fill_u32(c->nblocks, c->d_cnt, c->stream))) return rc;
+        if ((rc = launch_fill_u32(c->nblocks * kCntStride, c->d_cnt, c->stream))) return rc;
         c->epoch = 0;
     }
     a = DataflowArgs{c->d_dtiles, int(c->ntiles), c->d_needs, c->d_K, c->d_cnt, c->d_ctl,

@@ -18,6 +18,11 @@ struct Tile {
     int64_t ybase;
 };
 
+// Dataflow executor: each block's touch counter sits alone in a 128-byte
+// line, so polls of different counters go to different memory channels
+// instead of queueing on a few shared lines.
+constexpr int kCntStride = 32;
+
 // Warm-start inference walks each tile in chunks of at most this many tile
 // steps, one workgroup per chunk: whole tiles (1 to nb steps) leave most of
 // the chip idle behind the longest ones.

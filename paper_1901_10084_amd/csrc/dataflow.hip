@@ -87,7 +87,7 @@ struct DataflowArgs {
     int ntiles;
     const uint32_t *needs;
     const uint32_t *K;
-    uint32_t *cnt;       // completed touches per block (cumulative over epochs)
+    uint32_t *cnt;       // completed touches per block (cumulative over epochs), stride kCntStride
     uint32_t *ctl;       // [0] ticket counter, [1] abort flag
     uint32_t epoch;      // sweeps already run on these counters
     uint64_t wait_ticks; // wall-clock limit of one wait
@@ -218,9 +218,9 @@ k_sweep_dataflow(DataflowArgs a, int64_t n, T *__restrict__ x, const T *__restri
             const uint32_t *nd = a.needs + 2 * int64_t(tl.jsbase + m);
             bool ok = true;
             if (idA >= 0)
-                ok = wait_count(&a.cnt[idA], a.epoch * a.K[idA] + nd[0], &a.ctl[1], a.wait_ticks);
+                ok = wait_count(&a.cnt[int64_t(idA) * kCntStride], a.epoch * a.K[idA] + nd[0], &a.ctl[1], a.wait_ticks);
             if (ok && idB >= 0)
-                ok = wait_count(&a.cnt[idB], a.epoch * a.K[idB] + nd[1], &a.ctl[1], a.wait_ticks);
+                ok = wait_count(&a.cnt[int64_t(idB) * kCntStride], a.epoch * a.K[idB] + nd[1], &a.ctl[1], a.wait_ticks);
             return ok;
         };
 
@@ -245,7 +245,7 @@ k_sweep_dataflow(DataflowArgs a, int64_t n, T *__restrict__ x, const T *__restri
         // Block (P,Q) and the first step's blocks: wait, then hold (P,Q).
         if (tid == 0) {
             if (a.prof) s_pt[5] = wall_clock64();
-            bool ok = wait_count(&a.cnt[idC], a.epoch * a.K[idC] + tl.needC, &a.ctl[1], a.wait_ticks);
+            bool ok = wait_count(&a.cnt[int64_t(idC) * kCntStride], a.epoch * a.K[idC] + tl.needC, &a.ctl[1], a.wait_ticks);
             ok = ok && wait_step(0);
             if (ok) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
             s_ok = ok;
@@ -370,11 +370,11 @@ k_sweep_dataflow(DataflowArgs a, int64_t n, T *__restrict__ x, const T *__restri
             __builtin_amdgcn_s_waitcnt(0);
             __syncthreads();
             if (tid == 0) {
-                if (idA >= 0) __hip_atomic_fetch_add(&a.cnt[idA], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                if (idB >= 0) __hip_atomic_fetch_add(&a.cnt[idB], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                if (idA >= 0) __hip_atomic_fetch_add(&a.cnt[int64_t(idA) * kCntStride], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                if (idB >= 0) __hip_atomic_fetch_add(&a.cnt[int64_t(idB) * kCntStride], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                 bool ok = true;
                 if (last) {
-                    __hip_atomic_fetch_add(&a.cnt[idC], uint32_t(Q - P + 1), __ATOMIC_RELAXED,
+                    __hip_atomic_fetch_add(&a.cnt[int64_t(idC) * kCntStride], uint32_t(Q - P + 1), __ATOMIC_RELAXED,
                                            __HIP_MEMORY_SCOPE_AGENT);
                     s_tix = int(atomicAdd(&a.ctl[0], 1u));
                 }
@@ -460,9 +460,9 @@ k_aty_dataflow(DataflowArgs a, int64_t n, const T *__restrict__ y, double *__res
             const uint32_t *nd = a.needs + 2 * int64_t(tl.jsbase + m);
             bool ok = true;
             if (idA >= 0)
-                ok = wait_count(&a.cnt[idA], a.epoch * a.K[idA] + nd[0], &a.ctl[1], a.wait_ticks);
+                ok = wait_count(&a.cnt[int64_t(idA) * kCntStride], a.epoch * a.K[idA] + nd[0], &a.ctl[1], a.wait_ticks);
             if (ok && idB >= 0)
-                ok = wait_count(&a.cnt[idB], a.epoch * a.K[idB] + nd[1], &a.ctl[1], a.wait_ticks);
+                ok = wait_count(&a.cnt[int64_t(idB) * kCntStride], a.epoch * a.K[idB] + nd[1], &a.ctl[1], a.wait_ticks);
             return ok;
         };
 
@@ -481,7 +481,7 @@ k_aty_dataflow(DataflowArgs a, int64_t n, const T *__restrict__ y, double *__res
         };
 
         if (tid == 0) {
-            bool ok = wait_count(&a.cnt[idC], a.epoch * a.K[idC] + tl.needC, &a.ctl[1], a.wait_ticks);
+            bool ok = wait_count(&a.cnt[int64_t(idC) * kCntStride], a.epoch * a.K[idC] + tl.needC, &a.ctl[1], a.wait_ticks);
             ok = ok && wait_step(0);
             if (ok) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
             s_ok = ok;
@@ -538,11 +538,11 @@ k_aty_dataflow(DataflowArgs a, int64_t n, const T *__restrict__ y, double *__res
             __builtin_amdgcn_s_waitcnt(0);
             __syncthreads();
             if (tid == 0) {
-                if (idA >= 0) __hip_atomic_fetch_add(&a.cnt[idA], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                if (idB >= 0) __hip_atomic_fetch_add(&a.cnt[idB], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                if (idA >= 0) __hip_atomic_fetch_add(&a.cnt[int64_t(idA) * kCntStride], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                if (idB >= 0) __hip_atomic_fetch_add(&a.cnt[int64_t(idB) * kCntStride], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                 bool ok = true;
                 if (last) {
-                    __hip_atomic_fetch_add(&a.cnt[idC], uint32_t(Q - P + 1), __ATOMIC_RELAXED,
+                    __hip_atomic_fetch_add(&a.cnt[int64_t(idC) * kCntStride], uint32_t(Q - P + 1), __ATOMIC_RELAXED,
                                            __HIP_MEMORY_SCOPE_AGENT);
                     s_tix = int(atomicAdd(&a.ctl[0], 1u));
                 } else {
