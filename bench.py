@@ -167,7 +167,7 @@ def large_sweep(config=4, b=32, prec="f32", steps=5, warmup=2):
     return out
 
 
-def polish_report(config=2, b=32):
+def polish_report(config=2, b=16):
     """FP32 sweeps + FP64 polish against the FP64-only solve on the n = 1500
     Chung-Lu workload (exponent 2.5, mean degree 10, unit weights, gamma 5):
     one-shot solves to max violation 1e-6 (cc_solve_cc_lp, host arrays in and
@@ -395,7 +395,9 @@ def main():
         if "g2" in locals():
             del g2
         torch.cuda.empty_cache()
-        out["warm_start"] = warm_report(args.warm_config, 32)
+        # b = 16 keeps every CU busy at n = 2000 (about 670 tiles in flight
+        # against 170 at b = 32); at n = 4000 b = 32 has enough
+        out["warm_start"] = warm_report(args.warm_config, 16 if args.warm_config == 3 else 32)
 
     props = torch.cuda.get_device_properties(0)
     out["gpu"] = torch.cuda.get_device_name(0) or getattr(props, "gcnArchName", "")

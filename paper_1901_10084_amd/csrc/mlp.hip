@@ -474,18 +474,38 @@ __device__ __forceinline__ bf16x8 relu_bf16(const f32x4 lo, const f32x4 hi) {
     return h;
 }
 
-// One pass: the network's output for sample l % 16 of the lane group whose
-// features x carries (x is zero in the other lane groups).
-__device__ __forceinline__ float infer_pass(const InferNet &N, const bf16x8 x) {
-    const f32x4 z10 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(N.a1[0], x, N.c1[0], 0, 0, 0);
-    const f32x4 z11 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(N.a1[1], x, N.c1[1], 0, 0, 0);
-    const bf16x8 h1 = relu_bf16(z10, z11);
-    const f32x4 z20 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(N.a2[0], h1, N.c2[0], 0, 0, 0);
-    const f32x4 z21 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(N.a2[1], h1, N.c2[1], 0, 0, 0);
-    const bf16x8 h2 = relu_bf16(z20, z21);
+// The four passes of a 64-row group, layer by layer: lane group q carries
+// pass q's features in x (zero in the other lane groups), and lane l of
+// group q receives row l's output.  The passes are independent, so running
+// them layer by layer puts one pass's VALU work in another's MFMA latency.
+__device__ __forceinline__ float infer_group(const InferNet &N, const bf16x8 feat) {
+    const int g = (threadIdx.x & 63) >> 4;
+    const bf16x8 zero8 = {};
+    f32x4 z[4][2];
+    bf16x8 h[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const bf16x8 x = g == q ? feat : zero8;
+        z[q][0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(N.a1[0], x, N.c1[0], 0, 0, 0);
+        z[q][1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(N.a1[1], x, N.c1[1], 0, 0, 0);
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) h[q] = relu_bf16(z[q][0], z[q][1]);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        z[q][0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(N.a2[0], h[q], N.c2[0], 0, 0, 0);
+        z[q][1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(N.a2[1], h[q], N.c2[1], 0, 0, 0);
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) h[q] = relu_bf16(z[q][0], z[q][1]);
     const f32x4 c3 = {N.b3, N.b3, N.b3, N.b3};
-    const f32x4 z3 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(N.a3, h2, c3, 0, 0, 0);
-    return z3[0] > 0.0f ? z3[0] : 0.0f;
+    float out = 0.0f;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const f32x4 z3 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(N.a3, h[q], c3, 0, 0, 0);
+        if (g == q) out = z3[0];
+    }
+    return out > 0.0f ? out : 0.0f;
 }
 
 // The inference for b = 8, 16, 32, walking the tile's segment in its own
@@ -568,12 +588,7 @@ k_mlp_infer_tiled(GraphView G, const float *__restrict__ P, T *__restrict__ y) {
             feat[1] = f01[1];
             feat[2] = f23[0];
             feat[3] = f23[1];
-            float out = 0.0f;
-#pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                const float yq = infer_pass(N, g == q ? feat : zero8);
-                if (g == q) out = yq;
-            }
+            const float out = infer_group(N, feat);
             ytile[(int64_t(m) * b + t) * 3 * bb + o * bb + L] = T(ok ? out / outscale : 0.0f);
         }
     }
