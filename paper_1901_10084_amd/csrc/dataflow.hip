@@ -94,20 +94,39 @@ struct DataflowArgs {
     unsigned long long *prof;  // optional: wall-clock ticks per phase, summed
 };
 
-// Thread 0 only.  True once cnt >= need; false on time-out or abort.
-__device__ __forceinline__ bool wait_count(const uint32_t *cnt, uint32_t need, uint32_t *abort_flag,
-                                           uint64_t ticks) {
+// Thread 0 only.  True once each of the three counters has reached its
+// need; false on time-out or abort.  The counters and the abort flag are
+// read in the same round trip; an unused slot reads the abort flag with
+// need 0, which it always meets (the flag is 0 or 1).
+__device__ __forceinline__ bool wait_counts(const uint32_t *c0, uint32_t n0, const uint32_t *c1, uint32_t n1,
+                                            const uint32_t *c2, uint32_t n2, uint32_t *abort_flag,
+                                            uint64_t ticks) {
     const uint64_t start = wall_clock64();
+    bool res;
     for (;;) {
-        const uint32_t v = __hip_atomic_load(cnt, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        if (int32_t(v - need) >= 0) return true;
-        if (__hip_atomic_load(abort_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) return false;
+        const uint32_t v0 = __hip_atomic_load(c0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        const uint32_t v1 = __hip_atomic_load(c1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        const uint32_t v2 = __hip_atomic_load(c2, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        const uint32_t ab = __hip_atomic_load(abort_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (int32_t(v0 - n0) >= 0 && int32_t(v1 - n1) >= 0 && int32_t(v2 - n2) >= 0) {
+            res = true;
+            break;
+        }
+        if (ab) {
+            res = false;
+            break;
+        }
         if (wall_clock64() - start > ticks) {
             __hip_atomic_store(abort_flag, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            return false;
+            res = false;
+            break;
         }
-        __builtin_amdgcn_s_sleep(2);
+        __builtin_amdgcn_s_sleep(1);
     }
+    // No poll may stay in flight: a load pending at the step loop's head
+    // makes the compiler drain every wave's stores before the next loads.
+    __builtin_amdgcn_s_waitcnt(0);
+    return res;
 }
 
 template <typename T, int B, int D>
@@ -212,16 +231,18 @@ k_sweep_dataflow(DataflowArgs a, int64_t n, T *__restrict__ x, const T *__restri
             idB = (J != P) ? block_id(J, Q) : -1;
         };
         // thread 0: wait until step m's blocks have all earlier touches
-        auto wait_step = [&](int m) {
+        // thread 0: wait for step m's blocks (and, with withC, for (P,Q))
+        auto wait_step = [&](int m, bool withC) {
             int idA, idB;
             step_ids(m, idA, idB);
             const uint32_t *nd = a.needs + 2 * int64_t(tl.jsbase + m);
-            bool ok = true;
-            if (idA >= 0)
-                ok = wait_count(&a.cnt[int64_t(idA) * kCntStride], a.epoch * a.K[idA] + nd[0], &a.ctl[1], a.wait_ticks);
-            if (ok && idB >= 0)
-                ok = wait_count(&a.cnt[int64_t(idB) * kCntStride], a.epoch * a.K[idB] + nd[1], &a.ctl[1], a.wait_ticks);
-            return ok;
+            uint32_t *const none = &a.ctl[1];
+            return wait_counts(idA >= 0 ? &a.cnt[int64_t(idA) * kCntStride] : none,
+                               idA >= 0 ? a.epoch * a.K[idA] + nd[0] : 0u,
+                               idB >= 0 ? &a.cnt[int64_t(idB) * kCntStride] : none,
+                               idB >= 0 ? a.epoch * a.K[idB] + nd[1] : 0u,
+                               withC ? &a.cnt[int64_t(idC) * kCntStride] : none,
+                               withC ? a.epoch * a.K[idC] + tl.needC : 0u, &a.ctl[1], a.wait_ticks);
         };
 
         // Dual addresses: a wave-uniform base per sub-step plus a 32-bit
@@ -245,8 +266,7 @@ k_sweep_dataflow(DataflowArgs a, int64_t n, T *__restrict__ x, const T *__restri
         // Block (P,Q) and the first step's blocks: wait, then hold (P,Q).
         if (tid == 0) {
             if (a.prof) s_pt[5] = wall_clock64();
-            bool ok = wait_count(&a.cnt[int64_t(idC) * kCntStride], a.epoch * a.K[idC] + tl.needC, &a.ctl[1], a.wait_ticks);
-            ok = ok && wait_step(0);
+            const bool ok = wait_step(0, true);
             if (ok) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
             s_ok = ok;
             if (a.prof) mark(0);
@@ -383,7 +403,7 @@ k_sweep_dataflow(DataflowArgs a, int64_t n, T *__restrict__ x, const T *__restri
                     s_pt[4] += 1;
                 }
                 if (!last) {
-                    ok = wait_step(m + 1);
+                    ok = wait_step(m + 1, false);
                     if (ok) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
                     if (a.prof) mark(0);
                 }
@@ -454,16 +474,18 @@ k_aty_dataflow(DataflowArgs a, int64_t n, const T *__restrict__ y, double *__res
             idA = (J != Q) ? block_id(P, J) : -1;
             idB = (J != P) ? block_id(J, Q) : -1;
         };
-        auto wait_step = [&](int m) {
+        // thread 0: wait for step m's blocks (and, with withC, for (P,Q))
+        auto wait_step = [&](int m, bool withC) {
             int idA, idB;
             step_ids(m, idA, idB);
             const uint32_t *nd = a.needs + 2 * int64_t(tl.jsbase + m);
-            bool ok = true;
-            if (idA >= 0)
-                ok = wait_count(&a.cnt[int64_t(idA) * kCntStride], a.epoch * a.K[idA] + nd[0], &a.ctl[1], a.wait_ticks);
-            if (ok && idB >= 0)
-                ok = wait_count(&a.cnt[int64_t(idB) * kCntStride], a.epoch * a.K[idB] + nd[1], &a.ctl[1], a.wait_ticks);
-            return ok;
+            uint32_t *const none = &a.ctl[1];
+            return wait_counts(idA >= 0 ? &a.cnt[int64_t(idA) * kCntStride] : none,
+                               idA >= 0 ? a.epoch * a.K[idA] + nd[0] : 0u,
+                               idB >= 0 ? &a.cnt[int64_t(idB) * kCntStride] : none,
+                               idB >= 0 ? a.epoch * a.K[idB] + nd[1] : 0u,
+                               withC ? &a.cnt[int64_t(idC) * kCntStride] : none,
+                               withC ? a.epoch * a.K[idC] + tl.needC : 0u, &a.ctl[1], a.wait_ticks);
         };
 
         const T *const ytile = y + tl.ybase;
@@ -481,8 +503,7 @@ k_aty_dataflow(DataflowArgs a, int64_t n, const T *__restrict__ y, double *__res
         };
 
         if (tid == 0) {
-            bool ok = wait_count(&a.cnt[int64_t(idC) * kCntStride], a.epoch * a.K[idC] + tl.needC, &a.ctl[1], a.wait_ticks);
-            ok = ok && wait_step(0);
+            const bool ok = wait_step(0, true);
             if (ok) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
             s_ok = ok;
         }
@@ -546,7 +567,7 @@ k_aty_dataflow(DataflowArgs a, int64_t n, const T *__restrict__ y, double *__res
                                            __HIP_MEMORY_SCOPE_AGENT);
                     s_tix = int(atomicAdd(&a.ctl[0], 1u));
                 } else {
-                    ok = wait_step(m + 1);
+                    ok = wait_step(m + 1, false);
                     if (ok) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
                 }
                 s_ok = ok;
