@@ -238,7 +238,8 @@ def test_duals_nonnegative_and_stationary():
                                         (150, 32, "f32", 2), (3, 8, "f64", 2), (5, 8, "f64", 2),
                                         (16, 16, "f64", 2), (17, 16, "f32", 2), (33, 32, "f64", 2),
                                         (500, 16, "f64", 2), (300, 8, "f32", 2),
-                                        (1000, 32, "f32", 1)])
+                                        (1000, 32, "f32", 1), (200, 8, "f64", 10),
+                                        (600, 16, "f32", 5)])
 def test_dataflow_equals_rounds(n, b, prec, K):
     inst = I.workload(1) if n == 500 else I.random_signed(n, seed=n, gamma=2.0, weighted=True)
     print(f"dataflow n={n} b={b} {prec} K={K}", flush=True)
