@@ -289,7 +289,7 @@ def main():
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
         print("bench.py runs on one GPU only: the solver has no multi-GPU path "
-              "(see DESIGN.md for how it would shard); use --gpus 1", file=sys.stderr)
+              "(one GPU holds the n = 4000 instance's 128 GB of duals); use --gpus 1", file=sys.stderr)
         sys.exit(2)
 
     import torch
