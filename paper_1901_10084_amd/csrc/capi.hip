@@ -26,7 +26,7 @@ template <typename T> int launch_pair_pass(int64_t, T *, T *, T *, const T *, co
 template <typename T> int launch_prepare(int64_t, const double *, double, T *, int *, hipStream_t);
 template <typename T> int launch_init_cold(int64_t, int64_t, T *, T *, T *, T *, double, hipStream_t);
 template <typename S, typename D> int launch_convert(int64_t, const S *, D *, hipStream_t);
-template <typename T> int launch_metric_resid(const Tile *, int64_t, int, int64_t, const T *, const T *, double *, hipStream_t);
+template <typename T> int launch_metric_resid(const Tile *, const int32_t *, int64_t, int, int64_t, const T *, const T *, double *, hipStream_t);
 template <typename T> int launch_pair_resid(int64_t, const T *, const T *, const T *, const double *, const uint8_t *, const double *, double, double *, hipStream_t);
 int launch_final_reduce(const double *, int64_t, const double *, double *, hipStream_t);
 int pair_partial_blocks();
@@ -88,7 +88,7 @@ struct cc_ctx {
     int64_t slots = 0;
     std::vector<int64_t> round_start;  // tiles of round r: [round_start[r], round_start[r+1])
     Tile *d_tiles = nullptr;
-    double *d_mpart = nullptr;  // metric residual partials, 4 per tile
+    double *d_mpart = nullptr;  // metric residual partials, 4 per chunk
     double *d_ppart = nullptr;  // pair residual partials
     double *d_out = nullptr;    // final reduction, 14 doubles
     int *d_flag = nullptr;
@@ -106,7 +106,7 @@ struct cc_ctx {
     int aty_grid = 0;
     uint64_t wait_ticks = 0;
     float *d_mean_deg = nullptr;  // warm-start features
-    int32_t *d_chunks = nullptr;  // warm-start inference chunks (built on first use)
+    int32_t *d_chunks = nullptr;  // (tile, first step) per chunk of kChunkSteps tile steps
     int64_t nchunks = 0;
 };
 
@@ -325,13 +325,13 @@ int residuals_t(cc_ctx *c, const T *x, const T *f, const T *y, const T *yp, cons
         rc = aty_t<T>(c, y);
         if (rc) return rc;
     }
-    rc = launch_metric_resid<T>(c->d_tiles, c->ntiles, c->b, c->n, x, want_cs ? y : nullptr,
+    rc = launch_metric_resid<T>(c->d_tiles, c->d_chunks, c->nchunks, c->b, c->n, x, want_cs ? y : nullptr,
                                 c->d_mpart, c->stream);
     if (rc) return rc;
     rc = launch_pair_resid<T>(num_pairs(c->n), x, f, (want_cs || want_dual) ? yp : nullptr, w, d,
                               want_dual ? c->d_ax : nullptr, gamma, c->d_ppart, c->stream);
     if (rc) return rc;
-    rc = launch_final_reduce(c->d_mpart, c->ntiles, c->d_ppart, c->d_out, c->stream);
+    rc = launch_final_reduce(c->d_mpart, c->nchunks, c->d_ppart, c->d_out, c->stream);
     if (rc) return rc;
     double h[14];
     CCP_HIP_CHECK(hipMemcpyAsync(h, c->d_out, sizeof(h), hipMemcpyDeviceToHost, c->stream));
@@ -393,9 +393,17 @@ int cc_create(cc_ctx **out, int64_t n, int32_t b, int32_t prec, void *stream) {
     c->nrounds = 2 * c->nb - 1;
     std::vector<Tile> tiles;
     build_schedule(c, tiles);
+    std::vector<int32_t> chunks;
+    for (size_t t = 0; t < tiles.size(); ++t)
+        for (int m0 = 0; m0 <= tiles[t].Q - tiles[t].P; m0 += kChunkSteps) {
+            chunks.push_back(int32_t(t));
+            chunks.push_back(m0);
+        }
+    c->nchunks = int64_t(chunks.size() / 2);
     int rc = CC_OK;
     if (hipMalloc(&c->d_tiles, tiles.size() * sizeof(Tile)) != hipSuccess ||
-        hipMalloc(&c->d_mpart, size_t(c->ntiles) * 4 * sizeof(double)) != hipSuccess ||
+        hipMalloc(&c->d_chunks, chunks.size() * sizeof(int32_t)) != hipSuccess ||
+        hipMalloc(&c->d_mpart, size_t(c->nchunks) * 4 * sizeof(double)) != hipSuccess ||
         hipMalloc(&c->d_ppart, size_t(pair_partial_blocks()) * 10 * sizeof(double)) != hipSuccess ||
         hipMalloc(&c->d_out, 16 * sizeof(double)) != hipSuccess ||
         hipMalloc(&c->d_flag, sizeof(int)) != hipSuccess) {
@@ -403,7 +411,9 @@ int cc_create(cc_ctx **out, int64_t n, int32_t b, int32_t prec, void *stream) {
         return fail(CC_ENOMEM, "hipMalloc of schedule tables failed");
     }
     if (hipMemcpy(c->d_tiles, tiles.data(), tiles.size() * sizeof(Tile), hipMemcpyHostToDevice) !=
-        hipSuccess) {
+            hipSuccess ||
+        hipMemcpy(c->d_chunks, chunks.data(), chunks.size() * sizeof(int32_t), hipMemcpyHostToDevice) !=
+            hipSuccess) {
         cc_destroy(c);
         return fail(CC_EHIP, "copy of schedule tables failed");
     }
@@ -648,26 +658,6 @@ int graph_view(cc_ctx *c, const double *w, const uint8_t *d, const float *deg, G
     if (!c->d_mean_deg && hipMalloc(&c->d_mean_deg, sizeof(float)) != hipSuccess) {
         c->d_mean_deg = nullptr;
         return fail(CC_ENOMEM, "hipMalloc failed");
-    }
-    if (!c->d_chunks) {
-        std::vector<Tile> tiles(size_t(c->ntiles));
-        if (hipMemcpy(tiles.data(), c->d_tiles, tiles.size() * sizeof(Tile), hipMemcpyDeviceToHost) !=
-            hipSuccess)
-            return fail(CC_EHIP, "hipMemcpy failed");
-        std::vector<int32_t> ch;
-        for (int64_t t = 0; t < c->ntiles; ++t)
-            for (int m0 = 0; m0 <= tiles[t].Q - tiles[t].P; m0 += kInferChunk) {
-                ch.push_back(int32_t(t));
-                ch.push_back(m0);
-            }
-        if (hipMalloc(&c->d_chunks, ch.size() * sizeof(int32_t)) != hipSuccess) {
-            c->d_chunks = nullptr;
-            return fail(CC_ENOMEM, "hipMalloc failed");
-        }
-        if (hipMemcpy(c->d_chunks, ch.data(), ch.size() * sizeof(int32_t), hipMemcpyHostToDevice) !=
-            hipSuccess)
-            return fail(CC_EHIP, "hipMemcpy failed");
-        c->nchunks = int64_t(ch.size() / 2);
     }
     int rc = launch_mean_deg(deg, c->n, c->d_mean_deg, c->stream);
     if (rc) return rc;

@@ -23,10 +23,10 @@ struct Tile {
 // instead of queueing on a few shared lines.
 constexpr int kCntStride = 32;
 
-// Warm-start inference walks each tile in chunks of at most this many tile
-// steps, one workgroup per chunk: whole tiles (1 to nb steps) leave most of
-// the chip idle behind the longest ones.
-constexpr int kInferChunk = 4;
+// The residual and warm-start inference kernels walk each tile in chunks of
+// at most this many tile steps, one workgroup per chunk: whole tiles (1 to
+// nb steps) leave most of the chip idle behind the longest ones.
+constexpr int kChunkSteps = 4;
 
 // What the warm-start kernels read of the graph and the schedule.
 struct GraphView {
@@ -38,7 +38,7 @@ struct GraphView {
     const uint8_t *d;
     const float *deg;
     const float *mean_deg;
-    const int32_t *chunks;  // (tile, first step) per inference chunk
+    const int32_t *chunks;  // (tile, first step) per chunk of kChunkSteps steps
     int64_t nchunks;
 };
 

@@ -529,7 +529,7 @@ k_mlp_infer_tiled(GraphView G, const float *__restrict__ P, T *__restrict__ y) {
     const int Pb = tl.P, Qb = tl.Q;
     const int nn = int(G.n), nb = (nn + b - 1) / b;
     const bool desc = tile_desc(Pb, Qb, nb);
-    const int m1 = min(m0 + kInferChunk, Qb - Pb + 1);  // this chunk's steps: [m0, m1)
+    const int m1 = min(m0 + kChunkSteps, Qb - Pb + 1);  // this chunk's steps: [m0, m1)
     __shared__ float swA[bb], swB[bb], swC[bb], fA[bb], fB[bb], fC[bb], dP[b], dJ[b], dQ[b];
     const float md = G.mean_deg[0];
     const float den = 2.0f * md;

@@ -54,21 +54,24 @@ __device__ void block_reduce(double (&v)[NV], const int (&op)[NV], double *scrat
 __device__ __forceinline__ bool finite(double v) { return v - v == 0.0; }
 
 // ---------------------------------------------------------------------------
-// Metric rows: violation and complementary slackness, one workgroup per tile
-// (all tiles in one launch; read-only, so no ordering between tiles).
-// partial[tile*4 + 0..3] = {max violation, sum y*slack, max |y*slack|,
+// Metric rows: violation and complementary slackness, one workgroup per
+// chunk of at most kChunkSteps tile steps (all chunks in one launch;
+// read-only, so no ordering between them).
+// partial[chunk*4 + 0..3] = {max violation, sum y*slack, max |y*slack|,
 // non-finite flag}.
 // ---------------------------------------------------------------------------
 template <typename T, int B>
 __global__ void __launch_bounds__(B ? B * B : 1024)
-k_metric_resid(const Tile *__restrict__ tiles, int b_rt, int64_t n, const T *__restrict__ x,
-               const T *__restrict__ y, double *__restrict__ partial) {
+k_metric_resid(const Tile *__restrict__ tiles, const int32_t *__restrict__ chunks, int b_rt, int64_t n,
+               const T *__restrict__ x, const T *__restrict__ y, double *__restrict__ partial) {
     const int b = B ? B : b_rt;
     const int bb = b * b;
     const int tid = threadIdx.x;
     const int il = tid / b, kl = tid - (tid / b) * b;
-    const Tile tl = tiles[blockIdx.x];
+    const Tile tl = tiles[chunks[2 * int64_t(blockIdx.x)]];
+    const int m0 = chunks[2 * int64_t(blockIdx.x) + 1];
     const int P = tl.P, Q = tl.Q;
+    const int m1 = min(m0 + kChunkSteps, Q - P + 1);  // this chunk's tile steps: [m0, m1)
     __shared__ double As[1024], Bs[1024], Cs[1024];
     __shared__ double red[4 * 16];
     const int64_t i = int64_t(P) * b + il, k = int64_t(Q) * b + kl;
@@ -78,7 +81,7 @@ k_metric_resid(const Tile *__restrict__ tiles, int b_rt, int64_t n, const T *__r
     }
     double vmax = 0.0, cs_sum = 0.0, cs_max = 0.0, bad = 0.0;
     const bool desc = tile_desc(P, Q, int((n + b - 1) / b));
-    for (int m = 0; m <= Q - P; ++m) {
+    for (int m = m0; m < m1; ++m) {
         const int J = tile_J(P, Q, m, desc);
         if (J != Q) {
             const int64_t ii = int64_t(P) * b + il, jj = int64_t(J) * b + kl;
@@ -334,13 +337,14 @@ static inline unsigned grid_of(int64_t count, int block) {
 }
 
 template <typename T>
-int launch_metric_resid(const Tile *tiles, int64_t ntiles, int b, int64_t n, const T *x,
-                        const T *y, double *partial, hipStream_t s) {
+int launch_metric_resid(const Tile *tiles, const int32_t *chunks, int64_t nchunks, int b, int64_t n,
+                        const T *x, const T *y, double *partial, hipStream_t s) {
+    const dim3 grid = dim3(unsigned(nchunks));
     switch (b) {
-        case 8: hipLaunchKernelGGL((k_metric_resid<T, 8>), dim3(ntiles), dim3(64), 0, s, tiles, b, n, x, y, partial); break;
-        case 16: hipLaunchKernelGGL((k_metric_resid<T, 16>), dim3(ntiles), dim3(256), 0, s, tiles, b, n, x, y, partial); break;
-        case 32: hipLaunchKernelGGL((k_metric_resid<T, 32>), dim3(ntiles), dim3(1024), 0, s, tiles, b, n, x, y, partial); break;
-        default: hipLaunchKernelGGL((k_metric_resid<T, 0>), dim3(ntiles), dim3(b * b), 0, s, tiles, b, n, x, y, partial); break;
+        case 8: hipLaunchKernelGGL((k_metric_resid<T, 8>), grid, dim3(64), 0, s, tiles, chunks, b, n, x, y, partial); break;
+        case 16: hipLaunchKernelGGL((k_metric_resid<T, 16>), grid, dim3(256), 0, s, tiles, chunks, b, n, x, y, partial); break;
+        case 32: hipLaunchKernelGGL((k_metric_resid<T, 32>), grid, dim3(1024), 0, s, tiles, chunks, b, n, x, y, partial); break;
+        default: hipLaunchKernelGGL((k_metric_resid<T, 0>), grid, dim3(b * b), 0, s, tiles, chunks, b, n, x, y, partial); break;
     }
     CCP_LAUNCH_CHECK("k_metric_resid");
     return CC_OK;
@@ -406,10 +410,10 @@ int launch_slots_to_lex(const Tile *tiles, int64_t ntiles, int b, int64_t n,
     return CC_OK;
 }
 
-template int launch_metric_resid<double>(const Tile *, int64_t, int, int64_t, const double *,
-                                         const double *, double *, hipStream_t);
-template int launch_metric_resid<float>(const Tile *, int64_t, int, int64_t, const float *,
-                                        const float *, double *, hipStream_t);
+template int launch_metric_resid<double>(const Tile *, const int32_t *, int64_t, int, int64_t,
+                                         const double *, const double *, double *, hipStream_t);
+template int launch_metric_resid<float>(const Tile *, const int32_t *, int64_t, int, int64_t,
+                                        const float *, const float *, double *, hipStream_t);
 template int launch_pair_resid<double>(int64_t, const double *, const double *, const double *,
                                        const double *, const uint8_t *, const double *, double,
                                        double *, hipStream_t);
