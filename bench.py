@@ -167,6 +167,78 @@ def large_sweep(config=4, b=32, prec="f32", steps=5, warmup=2):
     return out
 
 
+def cpu_baseline_rows(config=1, b=16, mlp_sample=200_000, batch=8192):
+    """CPU-baseline leg per step of the path: each step on the GPU beside the
+    oracle's own code for it, on the same FP64 instance (the headline n = 500
+    planted partition) after two sweeps.  GPU: median of 10 calls, each bracketed by device
+    synchronisation (launch and synchronisation included).  Oracle: one call
+    on the host, one core; for the network rows, the reference network on
+    `mlp_sample` random rows (features included) scaled to every row, and one
+    gradient evaluation on a batch of `batch` rows."""
+    import numpy as np
+    import torch
+    import oracle
+    from oracle import mlp_ref as M
+    from paper_1901_10084_amd import ccproj as C
+    from paper_1901_10084_amd import instances as I
+    from paper_1901_10084_amd import warmstart as W
+    inst = I.workload(config)
+    s = C.Solver.from_instance(inst, b=b, prec="f64")
+    o = oracle.State.from_instance(inst)
+    s.sweep(2)
+    o.sweep(2, b=b)
+    torch.cuda.synchronize()
+
+    def gpu(fn, reps=10):
+        ts = []
+        for _ in range(reps):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            fn()
+            torch.cuda.synchronize()
+            ts.append(time.perf_counter() - t0)
+        return sorted(ts)[len(ts) // 2] * 1e3
+
+    def cpu(fn):
+        t0 = time.perf_counter()
+        fn()
+        return (time.perf_counter() - t0) * 1e3
+
+    rows = {}
+
+    def put(name, g_ms, o_ms, note=None):
+        rows[name] = {"gpu_ms": g_ms, "oracle_ms": o_ms, "oracle_over_gpu": o_ms / g_ms}
+        if note:
+            rows[name]["note"] = note
+        log(f"cpu baseline, {name}: {rows[name]}")
+
+    put("a3+a4 sweep (metric rounds + pair pass)", gpu(lambda: s.sweep(1)), cpu(lambda: o.sweep(1, b=b)))
+    put("a4 pair pass", gpu(s.pair_pass),
+        cpu(lambda: oracle.pair_pass(o.n, o.gamma, o.w, o.d, o.x, o.f, o.y_pair)))
+    put("a5 residuals (all, FP64)", gpu(s.residuals), cpu(o.residuals))
+    put("a6 x from y", gpu(s.x_from_y), cpu(o.x_from_y))
+    net = W.load()
+    deg = W.degrees(inst)
+    yv = torch.empty_like(s.y)
+    rng = np.random.default_rng(7)
+    tri = np.sort(rng.integers(0, inst.n, size=(mlp_sample, 3)), axis=1)
+    tri = tri[(tri[:, 0] < tri[:, 1]) & (tri[:, 1] < tri[:, 2])]
+    oo = rng.integers(0, 3, size=tri.shape[0])
+    p = net.host_params().astype(np.float64)
+    rows_all = 3 * inst.n * (inst.n - 1) * (inst.n - 2) // 6
+    o_ms = cpu(lambda: M.forward(p, M.features(inst.d, inst.w, inst.deg, tri[:, 0], tri[:, 1],
+                                                tri[:, 2], oo))) * rows_all / tri.shape[0]
+    put("a8 warm-start inference (every row)", gpu(lambda: W.infer(s, net, deg, yv)), o_ms,
+        f"oracle: {tri.shape[0]} sampled rows, scaled to {rows_all}")
+    phi = torch.rand((batch, 4), device="cuda")
+    tgt = torch.rand(batch, device="cuda")
+    phi_h, tgt_h = phi.double().cpu().numpy(), tgt.double().cpu().numpy()
+    put(f"a9 training step (batch {batch})", gpu(lambda: net.train_step(phi, tgt, lr=0.0)),
+        cpu(lambda: M.loss_and_grad(p, phi_h, tgt_h)))
+    put("a2 cold init", gpu(s.init_cold), cpu(o.init_cold))
+    return {"workload": inst.name, "n": inst.n, "b": b, "prec": "f64", "rows": rows}
+
+
 def polish_report(config=2, b=16):
     """FP32 sweeps + FP64 polish against the FP64-only solve on the n = 1500
     Chung-Lu workload (exponent 2.5, mean degree 10, unit weights, gamma 5):
@@ -277,6 +349,8 @@ def main():
     ap.add_argument("--warm-report", action="store_true",
                     help="FP64 cold vs FP32 cold vs FP32 + learned warm start, each to max "
                          "violation <= 1e-4, on workload --warm-config (tile size 32)")
+    ap.add_argument("--cpu-baseline-rows", action="store_true",
+                    help="each step of the path on the GPU beside the oracle (n = 500)")
     ap.add_argument("--polish-report", action="store_true",
                     help="n = 1500 Chung-Lu: FP32 sweeps + FP64 polish vs the FP64-only solve")
     ap.add_argument("--warm-config", type=int, default=3, choices=[3, 4],
@@ -415,6 +489,9 @@ def main():
         log("n = 4000 FP32 sweep ...")
         out["large_workload"] = large_sweep()
         log(f"large: {out['large_workload']}")
+
+    if args.cpu_baseline_rows:
+        out["cpu_baseline_rows"] = cpu_baseline_rows()
 
     if args.polish_report:
         out["polish"] = polish_report()
