@@ -48,6 +48,13 @@ class Resid(ctypes.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_}
 
 
+class NResid(ctypes.Structure):
+    _fields_ = [(k, _dbl) for k in ("max_viol", "primal", "dual", "gap", "cs_max", "stat_resid")]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
 _lib = None
 
 
@@ -74,6 +81,12 @@ def lib():
         L.orc_residuals.restype = ctypes.c_int
         L.orc_dual_objective.argtypes = [_i64, _dbl, _p, _p, _p, _p]
         L.orc_dual_objective.restype = _dbl
+        L.orc_nearness_init.argtypes = [_i64, _p, _p, _p]
+        L.orc_nearness_init.restype = None
+        L.orc_nearness_sweeps.argtypes = [_i64, _i64, _p, _p, _p, _i32, _i32]
+        L.orc_nearness_sweeps.restype = ctypes.c_int
+        L.orc_nearness_residuals.argtypes = [_i64, _p, _p, _p, _p, ctypes.POINTER(NResid)]
+        L.orc_nearness_residuals.restype = ctypes.c_int
         _lib = L
     return _lib
 
@@ -205,3 +218,51 @@ def second_sweep_prefix(n, b, gamma, w, d, rounds, cap=None):
         if cnt <= cap:
             return x, f, y_pair, t[:cnt], o[:cnt], y[:cnt]
         cap = int(cnt)
+
+
+class Nearness:
+    """Oracle iterate of the l2 metric nearness problem (Sec. II-A, p = 2):
+    min (1/2) sum_p w_p (x_p - d_p)^2 over metric x, for real dissimilarities
+    d.  x per pair, y colex metric duals; Algorithm 1 from x = d, y = 0."""
+
+    def __init__(self, n, w, dv):
+        self.n = int(n)
+        self.w = _f64(w)
+        self.dv = _f64(dv)
+        npairs = num_pairs(self.n)
+        assert self.w.shape == (npairs,) and self.dv.shape == (npairs,)
+        self.x = np.zeros(npairs)
+        self.y = np.zeros(3 * num_triplets(self.n))
+        self.sweeps = 0
+        self.init()
+
+    def init(self):
+        lib().orc_nearness_init(self.n, _ptr(self.dv), _ptr(self.x), _ptr(self.y))
+        self.sweeps = 0
+
+    def sweep(self, nsweeps=1, b=8, order="schedule"):
+        rc = lib().orc_nearness_sweeps(self.n, int(b), _ptr(self.w), _ptr(self.x), _ptr(self.y),
+                                       int(nsweeps), 0 if order == "schedule" else 1)
+        if rc != 0:
+            raise ValueError("oracle sweep rejected its input")
+        self.sweeps += nsweeps
+
+    def residuals(self) -> dict:
+        out = NResid()
+        rc = lib().orc_nearness_residuals(self.n, _ptr(self.w), _ptr(self.dv), _ptr(self.x),
+                                          _ptr(self.y), ctypes.byref(out))
+        if rc != 0:
+            raise MemoryError
+        return out.as_dict()
+
+    def solve(self, tol=1e-6, b=8, max_sweeps=100000, order="schedule", gap_tol=None):
+        """Sweep until the max metric violation is at most tol and, with
+        gap_tol, the primal-dual gap is at most gap_tol * max(1, |primal|).
+        (The iterate can be feasible well before it is optimal.)"""
+        while self.sweeps < max_sweeps:
+            self.sweep(1, b=b, order=order)
+            r = self.residuals()
+            if r["max_viol"] <= tol and (gap_tol is None or
+                                         abs(r["gap"]) <= gap_tol * max(1.0, abs(r["primal"]))):
+                return r
+        return self.residuals()

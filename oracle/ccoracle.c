@@ -18,6 +18,8 @@
  *                   projection step and a dual update, visiting constraints
  *                   cyclically;
  *   visiting order: the tiled block-diagonal schedule of Sec. III-B/C.
+ * Also the l2 metric nearness problem (Sec. II-A, p = 2) on the same metric
+ * rows and schedule, at the end of this file.
  *
  * Schedule (Sec. III-B/C; the reading of its unspecified parts is stated in
  * the design notes):  indices 0..n-1 are cut into aligned blocks of size b,
@@ -430,4 +432,90 @@ double orc_dual_objective(int64_t n, double gamma, const double *w, const uint8_
     }
     free(ax); free(af);
     return -by - 0.5 * gamma * q;
+}
+
+/* ------------------------------------------------------------------------ */
+/* l2 metric nearness (Sec. II-A, the metric nearness problem with p = 2):  */
+/*   min (1/2) sum_p w_p (x_p - d_p)^2   s.t.  x_ij <= x_ik + x_jk          */
+/* for real dissimilarities d_p.  It is (qp) with v = x alone, W = diag(w), */
+/* eps = 1 and c = -W d (so c'x + (1/2) x'Wx differs from the objective by  */
+/* the constant (1/2) d'Wd), and A the metric rows only, b = 0.             */
+/* Algorithm 1 then starts from x = -(1/eps) W^{-1} c = d with y = 0, and a */
+/* sweep is the metric rounds of the schedule alone: no pair rows.          */
+/* Dual:  D(y) = d'A'y - (1/2) (A'y)' W^{-1} (A'y), stationarity            */
+/* x = d - W^{-1} A'y; both differ from (qp)'s by the same constant.        */
+/* ------------------------------------------------------------------------ */
+void orc_nearness_init(int64_t n, const double *dv, double *x, double *y)
+{
+    int64_t np = orc_num_pairs(n);
+    for (int64_t p = 0; p < np; p++) x[p] = dv[p];
+    if (y) memset(y, 0, (size_t)(3 * orc_num_triplets(n)) * sizeof(double));
+}
+
+/* nsweeps sweeps (order 0: tiled schedule with tile size b; 1: plain
+ * lexicographic order).  Returns 0, or -1 on bad input. */
+int orc_nearness_sweeps(int64_t n, int64_t b, const double *w, double *x, double *y,
+                        int32_t nsweeps, int32_t order)
+{
+    if (n < 2 || b < 1 || !y) return -1;
+    int64_t np = orc_num_pairs(n);
+    double *r = inverse_weights(np, w);
+    if (!r) return -1;
+    sweep_ctx c;
+    memset(&c, 0, sizeof(c));
+    c.n = n; c.gamma = 1.0; c.r = r; c.x = x; c.y = y;
+    for (int32_t s = 0; s < nsweeps && n >= 3; s++) {
+        if (order == 0) visit_schedule(n, b, -1, metric_visit, &c);
+        else visit_lex(n, metric_visit, &c);
+    }
+    free(r);
+    return 0;
+}
+
+typedef struct {
+    double max_viol;    /* max over metric rows of (a'x)^+                  */
+    double primal;      /* (1/2) sum_p w_p (x_p - d_p)^2                    */
+    double dual;        /* d'A'y - (1/2) (A'y)' W^{-1} (A'y)                */
+    double gap;         /* primal - dual                                    */
+    double cs_max;      /* max over rows of |y (0 - a'x)|                   */
+    double stat_resid;  /* max |x - (d - W^{-1} A'y)|                       */
+} orc_nres;
+
+int orc_nearness_residuals(int64_t n, const double *w, const double *dv, const double *x,
+                           const double *y, orc_nres *out)
+{
+    int64_t np = orc_num_pairs(n);
+    memset(out, 0, sizeof(*out));
+    double *ax = (double *)malloc((size_t)(np > 0 ? np : 1) * sizeof(double));
+    double *af = (double *)malloc((size_t)(np > 0 ? np : 1) * sizeof(double));
+    double *yp0 = (double *)calloc((size_t)(np > 0 ? 2 * np : 1), sizeof(double));
+    if (!ax || !af || !yp0) { free(ax); free(af); free(yp0); return -1; }
+    accumulate_aty(n, y, yp0, ax, af);   /* no pair rows: their duals are 0 */
+    double primal = 0.0, dual_lin = 0.0, dual_quad = 0.0, stat = 0.0;
+    for (int64_t p = 0; p < np; p++) {
+        double e = x[p] - dv[p];
+        primal += 0.5 * w[p] * e * e;
+        dual_lin += dv[p] * ax[p];
+        dual_quad += ax[p] * ax[p] / w[p];
+        stat = dmax(stat, fabs(x[p] - (dv[p] - ax[p] / w[p])));
+    }
+    double vmet = 0.0, cs = 0.0;
+    for (int64_t k = 2; k < n; k++)
+        for (int64_t j = 1; j < k; j++)
+            for (int64_t i = 0; i < j; i++) {
+                double xij = x[pidx(i, j)], xik = x[pidx(i, k)], xjk = x[pidx(j, k)];
+                double s[3] = { xik + xjk - xij, xij + xjk - xik, xij + xik - xjk };
+                for (int o = 0; o < 3; o++) {
+                    vmet = dmax(vmet, -s[o]);
+                    if (y) cs = dmax(cs, fabs(y[3 * tidx(i, j, k) + o] * s[o]));
+                }
+            }
+    out->max_viol = vmet;
+    out->primal = primal;
+    out->dual = dual_lin - 0.5 * dual_quad;
+    out->gap = out->primal - out->dual;
+    out->cs_max = cs;
+    out->stat_resid = stat;
+    free(ax); free(af); free(yp0);
+    return 0;
 }

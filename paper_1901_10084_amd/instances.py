@@ -154,6 +154,32 @@ def random_signed(n: int, seed: int = 0, gamma: float = 1.0, weighted: bool = Tr
     return Instance(f"rand_n{n}_s{seed}", n, d, w, deg, float(gamma), dict(model="random"))
 
 
+@dataclass
+class NearnessInstance:
+    """Dissimilarities for the l2 metric nearness problem, in packed pair order."""
+    name: str
+    n: int
+    dv: np.ndarray           # float64 [N_p], dissimilarity d_p
+    w: np.ndarray            # float64 [N_p], > 0
+    meta: dict = field(default_factory=dict)
+
+
+def noisy_distances(n: int, seed: int = 0, dim: int = 2, noise: float = 0.5,
+                    weighted: bool = True) -> NearnessInstance:
+    """Euclidean distances of n uniform points in the unit cube of dimension
+    `dim`, each multiplied by an independent factor U[1 - noise, 1 + noise]
+    (which breaks triangle inequalities), weights U[0.5, 1.5] or 1.
+    noise = 0 gives a metric."""
+    rng = np.random.default_rng(seed)
+    pts = rng.random((n, dim))
+    i, j = pair_coords(n)
+    base = np.sqrt(((pts[i] - pts[j]) ** 2).sum(axis=1))
+    dv = base * rng.uniform(1.0 - noise, 1.0 + noise, base.shape)
+    w = rng.uniform(0.5, 1.5, base.shape) if weighted else np.ones(base.shape)
+    return NearnessInstance(f"noisy_euclid_n{n}_d{dim}_s{seed}", n, dv, w,
+                            dict(model="noisy_euclidean", dim=dim, noise=noise, seed=seed))
+
+
 # The five benchmark workloads: sizes, models and parameters of the headline runs.
 def workload(idx: int) -> Instance:
     if idx == 0:

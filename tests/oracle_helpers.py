@@ -95,3 +95,56 @@ def halfspace_projection(v, a, beta, Wdiag):
         return v.copy()
     Winv_a = a / Wdiag
     return v - viol * Winv_a / (a @ Winv_a)
+
+
+def dense_metric_rows(n):
+    """The metric rows over x alone, in colex triplet order 3 t + o."""
+    npairs = n * (n - 1) // 2
+    rows = []
+    for k in range(n):
+        for j in range(k):
+            for i in range(j):
+                pij, pik, pjk = pidx(i, j), pidx(i, k), pidx(j, k)
+                for L, S1, S2 in ((pij, pik, pjk), (pik, pij, pjk), (pjk, pij, pik)):
+                    a = np.zeros(npairs)
+                    a[L] += 1.0
+                    a[S1] -= 1.0
+                    a[S2] -= 1.0
+                    rows.append(a)
+    return np.array(rows).reshape(-1, npairs)
+
+
+def nearness_bruteforce(n, w, dv):
+    """min (1/2) sum w (x - d)^2 s.t. every metric row <= 0, by SLSQP and an
+    exact KKT solve on the detected active set.  Returns x."""
+    from scipy.optimize import minimize
+    A = dense_metric_rows(n)
+    w = np.asarray(w, float)
+    dv = np.asarray(dv, float)
+    fun = lambda x: 0.5 * np.sum(w * (x - dv) ** 2)
+    jac = lambda x: w * (x - dv)
+    res = minimize(fun, dv.copy(), jac=jac, method="SLSQP",
+                   constraints=[dict(type="ineq", fun=lambda x: -A @ x, jac=lambda x: -A)],
+                   options=dict(ftol=1e-15, maxiter=2000))
+    x = res.x
+    act = (-A @ x) < 1e-7
+    nv = len(x)
+    for _ in range(200):
+        Aa = A[act]
+        m = Aa.shape[0]
+        K = np.zeros((nv + m, nv + m))
+        K[:nv, :nv] = np.diag(w)
+        K[:nv, nv:] = Aa.T
+        K[nv:, :nv] = Aa
+        sol = np.linalg.lstsq(K, np.concatenate([w * dv, np.zeros(m)]), rcond=None)[0]
+        xk, lam = sol[:nv], sol[nv:]
+        viol = A @ xk
+        lmin = lam.min() if m else 0.0
+        if lmin >= -1e-12 and viol.max() <= 1e-12:
+            return xk
+        idx = np.flatnonzero(act)
+        if lmin < -1e-12:
+            act[idx[np.argmin(lam)]] = False
+        else:
+            act[np.argmax(viol)] = True
+    raise RuntimeError("active-set refinement did not settle")
