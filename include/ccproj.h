@@ -208,6 +208,37 @@ int cc_dataflow_tables(int64_t n, int32_t b, int64_t *ntiles, int64_t *nsteps, i
 int cc_widen(const float *src, double *dst, int64_t count, void *stream);
 int cc_narrow(const double *src, float *dst, int64_t count, void *stream);
 
+/* ----- l2 metric nearness (Sec. II-A, the metric nearness problem, p = 2) --
+ * min (1/2) sum_p w_p (x_p - d_p)^2 over x satisfying every x_ij <= x_ik +
+ * x_jk, for real dissimilarities d (device double[N_p], packed pair order).
+ * It is (qp) with v = x alone, W = diag(w), eps = 1, c = -W d and only the
+ * metric rows, so Algorithm 1 starts at x = d with y = 0 and one sweep is
+ * cc_sweep_metric (either executor) with g = 1/w, i.e. cc_prepare with
+ * gamma = 1.  Same schedule, kernels, layouts and precisions as above;
+ * there are no f, y_pair or pair rows. */
+
+/* Residuals of the nearness problem, in FP64.  Fields a call did not
+ * request are NaN. */
+typedef struct {
+    double max_viol;     /* max over metric rows of (x_L - x_S1 - x_S2)^+     */
+    double primal;       /* (1/2) sum w (x - d)^2                             */
+    double dual;         /* d'A'y - (1/2) (A'y)' W^{-1} (A'y)   (CC_RESID_DUAL) */
+    double gap;          /* primal - dual                       (CC_RESID_DUAL) */
+    double cs_max;       /* max over rows of |y (x_S1 + x_S2 - x_L)| (CC_RESID_CS) */
+    double stat_resid;   /* max |x - (d - W^{-1} A'y)|          (CC_RESID_DUAL) */
+} cc_nresid;
+
+/* Starting point: x = d in the context's precision, every metric dual 0.
+ * Enqueues only.  Errors: CC_EINVAL (null pointer). */
+int cc_nearness_init(cc_ctx *ctx, const double *d, void *x, void *y);
+
+/* Residuals selected by `what` (CC_RESID_VIOL, CC_RESID_CS, CC_RESID_DUAL;
+ * the last runs one A'y pass).  y may be NULL for CC_RESID_VIOL alone.
+ * w, d: device double[N_p].  Returns CC_ENONFINITE (with *out filled) if x
+ * holds a NaN or Inf.  Synchronises. */
+int cc_nearness_residuals(cc_ctx *ctx, const void *x, const void *y, const double *w,
+                          const double *d, int32_t what, cc_nresid *out);
+
 /* ----- Learned warm start (a 4-32-32-1 network per metric row) ---------
  * A nonnegative dual predicted for every metric row is a valid start for
  * Algorithm 1, which is dual coordinate ascent: started from any y >= 0 at

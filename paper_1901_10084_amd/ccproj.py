@@ -43,6 +43,13 @@ class Resid(ctypes.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_}
 
 
+class NResid(ctypes.Structure):
+    _fields_ = [(k, _dbl) for k in ("max_viol", "primal", "dual", "gap", "cs_max", "stat_resid")]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
 class Info(ctypes.Structure):
     _fields_ = [("sweeps", _i32), ("sweeps_f32", _i32), ("warm_accepted", _i32),
                 ("reserved", _i32), ("wall_s", _dbl), ("resid", Resid)]
@@ -79,6 +86,8 @@ _sig("cc_widen", ctypes.c_int, _p, _p, _i64, _p)
 _sig("cc_solve_cc_lp", ctypes.c_int, _i64, _p, _p, _dbl, _dbl, _i32, _i32, _i32, _i32, _p, _p,
      _p, _p, ctypes.POINTER(Info))
 _sig("cc_narrow", ctypes.c_int, _p, _p, _i64, _p)
+_sig("cc_nearness_init", ctypes.c_int, _p, _p, _p, _p)
+_sig("cc_nearness_residuals", ctypes.c_int, _p, _p, _p, _p, _p, _i32, ctypes.POINTER(NResid))
 
 _sig("cc_mlp_num_params", _i32)
 _sig("cc_mlp_workspace_bytes", _i64, _i64)
@@ -97,7 +106,8 @@ EXPORTS = ["cc_last_error", "cc_num_metric_duals", "cc_create", "cc_destroy", "c
            "cc_num_rounds", "cc_prepare", "cc_init_cold", "cc_sweep", "cc_sweep_rounds",
            "cc_sweep_metric", "cc_status",
            "cc_pair_pass", "cc_residuals", "cc_x_from_y", "cc_duals_to_lex", "cc_slots_to_lex",
-           "cc_dataflow_tables", "cc_widen", "cc_narrow", "cc_solve_cc_lp"]
+           "cc_dataflow_tables", "cc_widen", "cc_narrow", "cc_solve_cc_lp",
+           "cc_nearness_init", "cc_nearness_residuals"]
 
 
 class CCError(RuntimeError):
@@ -350,3 +360,69 @@ class Solver:
             if max(r["max_viol_metric"], r["max_viol_pair"]) <= tol:
                 return self.residuals(), True, time.perf_counter() - t0
         return self.residuals(), False, time.perf_counter() - t0
+
+
+class NearnessSolver:
+    """Device state of an l2 metric nearness instance (Sec. II-A, p = 2):
+    min (1/2) sum w (x - d)^2 over metric x.  w, d (float64, device), g =
+    1/w, x and y (schedule order) in the chosen precision.  Algorithm 1 from
+    x = d, y = 0; a sweep is the metric rounds only."""
+
+    def __init__(self, n, w, dv, b=16, prec="f64", device="cuda", stream=None):
+        self.n, self.b, self.prec = int(n), int(b), prec
+        self.ctx = Context(self.n, self.b, prec, stream)
+        dt = torch.float64 if prec == "f64" else torch.float32
+        self.w = torch.as_tensor(np.ascontiguousarray(w, dtype=np.float64)).to(device)
+        self.dv = torch.as_tensor(np.ascontiguousarray(dv, dtype=np.float64)).to(device)
+        npairs = self.n * (self.n - 1) // 2
+        assert self.w.numel() == npairs and self.dv.numel() == npairs
+        self.g = torch.empty(npairs, dtype=dt, device=device)
+        self.x = torch.empty(npairs, dtype=dt, device=device)
+        self.y = torch.empty(self.ctx.slots, dtype=dt, device=device)
+        self.ctx.prepare(self.w, 1.0, self.g)
+        self.init()
+
+    @classmethod
+    def from_instance(cls, inst, **kw):
+        return cls(inst.n, inst.w, inst.dv, **kw)
+
+    def init(self):
+        check(_L.cc_nearness_init(self.ctx.handle, _ptr(self.dv), _ptr(self.x), _ptr(self.y)))
+        self.sweeps = 0
+
+    def sweep(self, nsweeps=1, executor=None):
+        for _ in range(nsweeps):
+            self.ctx.sweep_metric(self.x, self.y, self.g, executor)
+        self.sweeps += nsweeps
+
+    def status(self):
+        self.ctx.status()
+
+    def residuals(self, what=CC_RESID_ALL, raise_nonfinite=True):
+        out = NResid()
+        rc = _L.cc_nearness_residuals(self.ctx.handle, _ptr(self.x), _ptr(self.y), _ptr(self.w),
+                                      _ptr(self.dv), int(what), ctypes.byref(out))
+        if rc == CC_ENONFINITE and not raise_nonfinite:
+            return out.as_dict()
+        check(rc)
+        return out.as_dict()
+
+    def duals_lex(self):
+        y_lex = torch.empty(num_metric_duals(self.n), dtype=self.y.dtype, device=self.y.device)
+        self.ctx.duals_to_lex(self.y, y_lex)
+        return y_lex
+
+    def solve(self, tol=1e-6, gap_tol=None, max_sweeps=100000, check_every=None, executor=None):
+        """Sweep until the max metric violation is at most tol and, with
+        gap_tol, the relative primal-dual gap is at most gap_tol.  Returns
+        (residuals, converged)."""
+        every = check_every or (1 if self.n <= 1000 else 5)
+        what = CC_RESID_VIOL | (CC_RESID_DUAL if gap_tol is not None else 0)
+        r = self.residuals(what)
+        while self.sweeps < max_sweeps:
+            self.sweep(min(every, max_sweeps - self.sweeps), executor)
+            r = self.residuals(what)
+            if r["max_viol"] <= tol and (gap_tol is None or
+                                         abs(r["gap"]) <= gap_tol * max(1.0, abs(r["primal"]))):
+                return r, True
+        return r, False

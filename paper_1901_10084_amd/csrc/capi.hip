@@ -26,6 +26,10 @@ template <typename T> int launch_pair_pass(int64_t, T *, T *, T *, const T *, co
 template <typename T> int launch_prepare(int64_t, const double *, double, T *, int *, hipStream_t);
 template <typename T> int launch_init_cold(int64_t, int64_t, T *, T *, T *, T *, double, hipStream_t);
 template <typename S, typename D> int launch_convert(int64_t, const S *, D *, hipStream_t);
+template <typename T> int launch_nearness_init(int64_t, int64_t, const double *, T *, T *, hipStream_t);
+template <typename T>
+int launch_nearness_pair_resid(int64_t, const T *, const double *, const double *, const double *, double *,
+                               hipStream_t);
 template <typename T> int launch_metric_resid(const Tile *, const int32_t *, int64_t, int, int64_t, const T *, const T *, double *, hipStream_t);
 template <typename T> int launch_pair_resid(int64_t, const T *, const T *, const T *, const double *, const uint8_t *, const double *, double, double *, hipStream_t);
 int launch_final_reduce(const double *, int64_t, const double *, double *, hipStream_t);
@@ -358,6 +362,44 @@ int residuals_t(cc_ctx *c, const T *x, const T *f, const T *y, const T *yp, cons
     return CC_OK;
 }
 
+// l2 metric nearness: the metric rows' residuals as for (qp), the pair terms
+// from k_nearness_pair_resid in k_pair_resid's slots.
+template <typename T>
+int nearness_residuals_t(cc_ctx *c, const T *x, const T *y, const double *w, const double *dv, int what,
+                         cc_nresid *out) {
+    const bool want_cs = (what & CC_RESID_CS) && y;
+    const bool want_dual = (what & CC_RESID_DUAL) && y;
+    int rc;
+    if (want_dual && (rc = aty_t<T>(c, y))) return rc;
+    rc = launch_metric_resid<T>(c->d_tiles, c->d_chunks, c->nchunks, c->b, c->n, x, want_cs ? y : nullptr,
+                                c->d_mpart, c->stream);
+    if (rc) return rc;
+    rc = launch_nearness_pair_resid<T>(num_pairs(c->n), x, dv, w, want_dual ? c->d_ax : nullptr,
+                                       c->d_ppart, c->stream);
+    if (rc) return rc;
+    if ((rc = launch_final_reduce(c->d_mpart, c->nchunks, c->d_ppart, c->d_out, c->stream))) return rc;
+    double h[14];
+    CCP_HIP_CHECK(hipMemcpyAsync(h, c->d_out, sizeof(h), hipMemcpyDeviceToHost, c->stream));
+    CCP_HIP_CHECK(hipStreamSynchronize(c->stream));
+    if (want_dual && (rc = check_dataflow(c))) return rc;
+    const double nan = std::nan("");
+    // h: 0 metric max viol, 2 metric cs max, 3 metric bad, 6 sum w (x-d)^2,
+    //    10 sum (A'y)^2 / w, 11 d'A'y, 12 stationarity, 13 pair bad
+    out->max_viol = h[0];
+    out->primal = 0.5 * h[6];
+    out->cs_max = want_cs ? h[2] : nan;
+    if (want_dual) {
+        out->dual = h[11] - 0.5 * h[10];
+        out->gap = out->primal - out->dual;
+        out->stat_resid = h[12];
+    } else {
+        out->dual = out->gap = out->stat_resid = nan;
+    }
+    if (h[3] != 0.0 || h[13] != 0.0 || !std::isfinite(out->primal))
+        return fail(CC_ENONFINITE, "non-finite value in x");
+    return CC_OK;
+}
+
 template <typename T>
 int x_from_y_t(cc_ctx *c, const T *y, const T *yp, const double *w, double gamma, T *x, T *f) {
     int rc = aty_t<T>(c, y);
@@ -583,6 +625,30 @@ int cc_residuals(cc_ctx *c, const void *x, const void *f, const void *y, const v
                                    (const double *)yp, w, d, gamma, what, out);
     return residuals_t<float>(c, (const float *)x, (const float *)f, (const float *)y,
                               (const float *)yp, w, d, gamma, what, out);
+}
+
+int cc_nearness_init(cc_ctx *c, const double *dv, void *x, void *y) {
+    int rc;
+    if ((rc = check_ctx(c)) || (rc = need(dv, "d")) || (rc = need(x, "x")) || (rc = need(y, "y")))
+        return rc;
+    if (c->prec == CC_F64)
+        return launch_nearness_init<double>(num_pairs(c->n), c->slots, dv, (double *)x, (double *)y,
+                                            c->stream);
+    return launch_nearness_init<float>(num_pairs(c->n), c->slots, dv, (float *)x, (float *)y, c->stream);
+}
+
+int cc_nearness_residuals(cc_ctx *c, const void *x, const void *y, const double *w, const double *dv,
+                          int32_t what, cc_nresid *out) {
+    int rc;
+    if ((rc = check_ctx(c)) || (rc = need(x, "x")) || (rc = need(w, "w")) || (rc = need(dv, "d")) ||
+        (rc = need(out, "out")))
+        return rc;
+    if ((what & (CC_RESID_CS | CC_RESID_DUAL)) && !y)
+        return fail(CC_EINVAL, "y is needed for CC_RESID_CS / CC_RESID_DUAL");
+    if ((rc = check_dataflow(c))) return rc;
+    if (c->prec == CC_F64)
+        return nearness_residuals_t<double>(c, (const double *)x, (const double *)y, w, dv, what, out);
+    return nearness_residuals_t<float>(c, (const float *)x, (const float *)y, w, dv, what, out);
 }
 
 int cc_x_from_y(cc_ctx *c, const void *y, const void *yp, const double *w, double gamma,

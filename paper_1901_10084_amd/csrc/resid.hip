@@ -172,6 +172,37 @@ k_pair_resid(int64_t np, const T *__restrict__ x, const T *__restrict__ f,
         for (int e = 0; e < 10; ++e) partial[int64_t(blockIdx.x) * 10 + e] = v[e];
 }
 
+// Pair terms of the l2 metric nearness problem, in the slots of k_pair_resid
+// (so k_final_reduce serves both): 2 sum w (x - d)^2, 6 sum (A'y)^2 / w,
+// 7 d'A'y, 8 max |x - (d - A'y / w)|, 9 non-finite flag; the others 0.
+// ax (the metric A'y) may be null: then 6-8 stay 0.
+template <typename T>
+__global__ void __launch_bounds__(256)
+k_nearness_pair_resid(int64_t np, const T *__restrict__ x, const double *__restrict__ dv,
+                      const double *__restrict__ w, const double *__restrict__ ax,
+                      double *__restrict__ partial) {
+    __shared__ double red[10 * 16];
+    double sq = 0, qd = 0, dy = 0, st = 0, bad = 0;
+    for (int64_t p = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; p < np;
+         p += int64_t(gridDim.x) * blockDim.x) {
+        const double xv = double(x[p]), dp = dv[p], wv = w[p];
+        const double e = xv - dp;
+        sq += wv * (e * e);
+        if (!finite(xv)) bad = 1.0;
+        if (ax) {
+            const double a = ax[p];
+            qd += (a * a) / wv;
+            dy += dp * a;
+            st = fmax(st, fabs(xv - (dp - a / wv)));
+        }
+    }
+    double v[10] = {0, 0, sq, 0, 0, 0, qd, dy, st, bad};
+    const int op[10] = {1, 0, 0, 0, 1, 0, 0, 0, 1, 1};
+    block_reduce<10>(v, op, red);
+    if (threadIdx.x == 0)
+        for (int e = 0; e < 10; ++e) partial[int64_t(blockIdx.x) * 10 + e] = v[e];
+}
+
 // Fixed-order final reduction: out[0..3] from the metric partials, out[4..13]
 // from the pair partials.
 __global__ void __launch_bounds__(256)
@@ -351,6 +382,15 @@ int launch_metric_resid(const Tile *tiles, const int32_t *chunks, int64_t nchunk
 }
 
 template <typename T>
+int launch_nearness_pair_resid(int64_t np, const T *x, const double *dv, const double *w,
+                               const double *ax, double *partial, hipStream_t s) {
+    hipLaunchKernelGGL(k_nearness_pair_resid<T>, dim3(kPairBlocks), dim3(256), 0, s, np, x, dv, w,
+                       ax, partial);
+    CCP_LAUNCH_CHECK("k_nearness_pair_resid");
+    return CC_OK;
+}
+
+template <typename T>
 int launch_pair_resid(int64_t np, const T *x, const T *f, const T *yp, const double *w,
                       const uint8_t *d, const double *ax, double gamma, double *partial,
                       hipStream_t s) {
@@ -410,6 +450,12 @@ int launch_slots_to_lex(const Tile *tiles, int64_t ntiles, int b, int64_t n,
     return CC_OK;
 }
 
+template int launch_nearness_pair_resid<double>(int64_t, const double *, const double *,
+                                                const double *, const double *, double *,
+                                                hipStream_t);
+template int launch_nearness_pair_resid<float>(int64_t, const float *, const double *,
+                                               const double *, const double *, double *,
+                                               hipStream_t);
 template int launch_metric_resid<double>(const Tile *, const int32_t *, int64_t, int, int64_t,
                                          const double *, const double *, double *, hipStream_t);
 template int launch_metric_resid<float>(const Tile *, const int32_t *, int64_t, int, int64_t,

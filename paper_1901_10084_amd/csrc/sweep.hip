@@ -349,6 +349,17 @@ int launch_init_cold(int64_t np, int64_t slots, T *x, T *f, T *y, T *yp, double 
     return CC_OK;
 }
 
+// l2 metric nearness: Algorithm 1 starts at x = d (the dissimilarities, in
+// the context's precision) with every dual 0.
+template <typename T>
+int launch_nearness_init(int64_t np, int64_t slots, const double *dv, T *x, T *y, hipStream_t s) {
+    hipLaunchKernelGGL((k_convert<double, T>), dim3(grid_for(np, 256)), dim3(256), 0, s, np, dv, x);
+    CCP_LAUNCH_CHECK("k_convert");
+    hipLaunchKernelGGL(k_fill_zero<T>, dim3(grid_for(slots, 256)), dim3(256), 0, s, slots, y);
+    CCP_LAUNCH_CHECK("k_fill_zero");
+    return CC_OK;
+}
+
 template <typename S, typename D>
 int launch_convert(int64_t count, const S *src, D *dst, hipStream_t s) {
     if (count <= 0) return CC_OK;
@@ -376,6 +387,10 @@ template int launch_init_cold<double>(int64_t, int64_t, double *, double *, doub
                                       double, hipStream_t);
 template int launch_init_cold<float>(int64_t, int64_t, float *, float *, float *, float *,
                                      double, hipStream_t);
+template int launch_nearness_init<double>(int64_t, int64_t, const double *, double *, double *,
+                                          hipStream_t);
+template int launch_nearness_init<float>(int64_t, int64_t, const double *, float *, float *,
+                                         hipStream_t);
 template int launch_convert<float, double>(int64_t, const float *, double *, hipStream_t);
 template int launch_convert<double, float>(int64_t, const double *, float *, hipStream_t);
 
