@@ -239,6 +239,78 @@ def cpu_baseline_rows(config=1, b=16, mlp_sample=200_000, batch=8192):
     return {"workload": inst.name, "n": inst.n, "b": b, "prec": "f64", "rows": rows}
 
 
+def nearness_report(n=2000, b=16, solve_n=500, solve_tol=1e-4, oracle_sweeps=3):
+    """l2 metric nearness (Sec. II-A, p = 2) on noisy Euclidean distances (n
+    points in the unit square, each distance times U[0.5, 1.5], weights
+    U[0.5, 1.5]).  At n, per precision: the time of one sweep (metric rounds
+    only; HIP events around 5 sweeps after 2 warm-up ones), constraint
+    projections per second and the HBM roofline of the sweep kernel (2 N_c s
+    + 3 N_p s bytes per launch).  At solve_n: FP64 and FP32 solves from x = d
+    to max violation solve_tol (residuals every 10 sweeps), and the oracle's
+    nearness sweep on the same instance (one core) beside them."""
+    import torch
+    from paper_1901_10084_amd import ccproj as C
+    from paper_1901_10084_amd import instances as I
+    res = {}
+    inst = I.noisy_distances(n, seed=0, noise=0.5)
+    rows = 3 * n * (n - 1) * (n - 2) // 6
+    npairs = n * (n - 1) // 2
+    res["sweep"] = {"workload": inst.name, "n": n, "b": b, "metric_rows": rows}
+    for prec, sz in (("f64", 8), ("f32", 4)):
+        s = C.NearnessSolver.from_instance(inst, b=b, prec=prec)
+        s.sweep(2)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        s.sweep(5)
+        e1.record()
+        torch.cuda.synchronize()
+        s.status()
+        ms = e0.elapsed_time(e1) / 5
+        algo = 2 * rows * sz + 3 * npairs * sz
+        res["sweep"][prec] = {"ms_per_sweep": ms,
+                              "constraint_projections_per_s": rows / (ms * 1e-3),
+                              "roofline": {"bound": "hbm", "achieved": algo / (ms * 1e-3) / 1e9,
+                                           "peak": 8000.0, "unit": "GB/s",
+                                           "frac": algo / (ms * 1e-3) / 8e12}}
+        log(f"nearness sweep n={n} {prec}: {res['sweep'][prec]}")
+        del s
+        torch.cuda.empty_cache()
+
+    small = I.noisy_distances(solve_n, seed=0, noise=0.5)
+    srows = 3 * solve_n * (solve_n - 1) * (solve_n - 2) // 6
+    res["solve"] = {"workload": small.name, "n": solve_n, "b": b, "tol": solve_tol}
+    for prec in ("f64", "f32"):
+        s = C.NearnessSolver.from_instance(small, b=b, prec=prec)
+        s.residuals(C.CC_RESID_VIOL)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ok = False
+        while not ok and s.sweeps < 20000:
+            r, ok = s.solve(tol=solve_tol, max_sweeps=s.sweeps + 500, check_every=10)
+            log(f"nearness solve n={solve_n} {prec}: {s.sweeps} sweeps, "
+                f"max violation {r['max_viol']:.3e}")
+        sec = time.perf_counter() - t0
+        full = s.residuals()
+        res["solve"][prec] = {"seconds": sec, "sweeps": s.sweeps, "converged": ok,
+                              "max_viol": full["max_viol"], "primal": full["primal"],
+                              "rel_gap": full["gap"] / max(1.0, abs(full["primal"]))}
+        log(f"nearness solve n={solve_n} {prec}: {res['solve'][prec]}")
+        del s
+        torch.cuda.empty_cache()
+    import oracle
+    o = oracle.Nearness(small.n, small.w, small.dv)
+    t0 = time.perf_counter()
+    o.sweep(oracle_sweeps, b=b)
+    dt = time.perf_counter() - t0
+    res["cpu_baseline"] = {"value": oracle_sweeps * srows / dt, "unit": "constraint-projections/s",
+                           "cores": 1, "kind": "oracle",
+                           "sample": f"{oracle_sweeps} FP64 nearness sweeps at n = {solve_n} "
+                                     f"from x = d, {dt:.2f} s"}
+    log(f"nearness oracle: {res['cpu_baseline']}")
+    return res
+
+
 def polish_report(config=2, b=16):
     """FP32 sweeps + FP64 polish against the FP64-only solve on the n = 1500
     Chung-Lu workload (exponent 2.5, mean degree 10, unit weights, gamma 5):
@@ -351,6 +423,8 @@ def main():
                          "violation <= 1e-4, on workload --warm-config (tile size 32)")
     ap.add_argument("--cpu-baseline-rows", action="store_true",
                     help="each step of the path on the GPU beside the oracle (n = 500)")
+    ap.add_argument("--nearness-report", action="store_true",
+                    help="l2 metric nearness at n = 2000 (FP64 and FP32) beside the oracle")
     ap.add_argument("--polish-report", action="store_true",
                     help="n = 1500 Chung-Lu: FP32 sweeps + FP64 polish vs the FP64-only solve")
     ap.add_argument("--warm-config", type=int, default=3, choices=[3, 4],
@@ -492,6 +566,9 @@ def main():
 
     if args.cpu_baseline_rows:
         out["cpu_baseline_rows"] = cpu_baseline_rows()
+
+    if args.nearness_report:
+        out["nearness"] = nearness_report()
 
     if args.polish_report:
         out["polish"] = polish_report()
