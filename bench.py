@@ -61,7 +61,7 @@ def recorded_traffic(kernel, inst, b, prec):
     return rec["traffic_bytes_per_launch"]
 
 
-def warm_report(config, b, tol=1e-4):
+def warm_report(config, b, tol=1e-4, sparse=False):
     """Time to max violation <= tol: FP64 plain cold solve vs FP32 cold vs
     FP32 + learned warm start.  Workload 3: the n = 2000 planted partition
     (20 blocks, p_in 0.25, p_out 0.01, gamma 5); workload 4: the n = 4000
@@ -70,7 +70,9 @@ def warm_report(config, b, tol=1e-4):
     Chung-Lu graphs also runs if its weights exist.  Wall times include inference, the
     x-from-y pass and every residual check.  Objective errors are against an
     FP64 solve to 1e-7 (n = 4000: FP64 to 1e-6 if its 256 GB of duals can be
-    allocated, else FP32 to 1e-6, as recorded in the result)."""
+    allocated, else FP32 to 1e-6, as recorded in the result).  With sparse,
+    the runs are repeated with sparse dual access (same sweeps, same
+    results)."""
     import torch
     from paper_1901_10084_amd import ccproj as C
     from paper_1901_10084_amd import instances as I
@@ -82,13 +84,15 @@ def warm_report(config, b, tol=1e-4):
         nets["chunglu300"] = W.load(W.weights_path("chunglu300"))
     res = {"workload": inst.name, "n": inst.n, "tol": tol, "b": b}
 
-    def run(prec, warm, tol_run=tol):
+    def run(prec, warm, tol_run=tol, sp=False):
         s = C.Solver.from_instance(inst, b=b, prec=prec)
+        if sp:
+            s.ensure_mask()  # allocation outside the timed region
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         info = W.warm_start(s, nets[warm], deg) if warm else None
         t_warm = time.perf_counter() - t0
-        r, conv, _ = s.solve(tol=tol_run, max_sweeps=20000, executor=C.CC_EXEC_DATAFLOW)
+        r, conv, _ = s.solve(tol=tol_run, max_sweeps=20000, executor=C.CC_EXEC_DATAFLOW, sparse=sp)
         dt = time.perf_counter() - t0
         out = {"seconds": dt, "sweeps": s.sweeps, "converged": conv, "primal_qp": r["primal_qp"],
                "max_viol": max(r["max_viol_metric"], r["max_viol_pair"])}
@@ -105,8 +109,10 @@ def warm_report(config, b, tol=1e-4):
         runs.append(("f32_warm_chunglu300", "f32", "chunglu300"))
     if config != 4:
         runs.insert(0, ("f64_cold", "f64", None))
+    if sparse:
+        runs += [(name + "_sparse", prec, warm) for name, prec, warm in runs]
     for name, prec, warm in runs:
-        res[name] = run(prec, warm)
+        res[name] = run(prec, warm, sp=name.endswith("_sparse"))
         log(f"warm report {name}: {res[name]}")
     ref_tol = 1e-7 if config != 4 else 1e-6
     try:
@@ -237,6 +243,55 @@ def cpu_baseline_rows(config=1, b=16, mlp_sample=200_000, batch=8192):
         cpu(lambda: M.loss_and_grad(p, phi_h, tgt_h)))
     put("a2 cold init", gpu(s.init_cold), cpu(o.init_cold))
     return {"workload": inst.name, "n": inst.n, "b": b, "prec": "f64", "rows": rows}
+
+
+def sparse_report(cases=((3, 16, "f32"), (3, 16, "f64"), (4, 32, "f32")), settle=20, steps=5):
+    """Sparse dual access (Sec. III-D) against the dense sweep, per metric
+    sweep, on the state after `settle` dense sweeps from the cold start
+    (the nonzero fraction of a solve in progress): HIP events around `steps`
+    launches of each after one untimed launch, the mask build, and the
+    fraction of nonzero duals.  Sparse bytes per sweep: the mask read and
+    written (slots / 8 each), the nonzero duals read and written, x and g."""
+    import torch
+    from paper_1901_10084_amd import ccproj as C
+    from paper_1901_10084_amd import instances as I
+    out = []
+    for config, b, prec in cases:
+        inst = I.workload(config)
+        sz = 8 if prec == "f64" else 4
+        s = C.Solver.from_instance(inst, b=b, prec=prec)
+        s.sweep(settle)
+        torch.cuda.synchronize()
+        nz = sum(int(torch.count_nonzero(s.y[i:i + (1 << 28)])) for i in range(0, s.y.numel(), 1 << 28))
+        row = {"workload": inst.name, "n": inst.n, "b": b, "prec": prec, "after_sweeps": settle,
+               "nonzero_duals": nz, "nonzero_fraction": nz / (3 * inst.n * (inst.n - 1) * (inst.n - 2) // 6)}
+        for sp in (False, True):
+            s.sweep_metric(sparse=sp)
+            torch.cuda.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            for _ in range(steps):
+                s.sweep_metric(sparse=sp)
+            e1.record()
+            torch.cuda.synchronize()
+            s.status()
+            row["sparse_ms" if sp else "dense_ms"] = e0.elapsed_time(e1) / steps
+        s.invalidate_mask()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        s.ensure_mask()
+        e1.record()
+        torch.cuda.synchronize()
+        row["mask_build_ms"] = e0.elapsed_time(e1)
+        row["speedup"] = row["dense_ms"] / row["sparse_ms"]
+        npairs = inst.n * (inst.n - 1) // 2
+        row["sparse_bytes"] = 2 * s.mask.numel() + 2 * nz * sz + 3 * npairs * sz
+        row["dense_bytes"] = metric_sweep_bytes(inst, sz)
+        log(f"sparse report: {row}")
+        out.append(row)
+        del s
+        torch.cuda.empty_cache()
+    return out
 
 
 def nearness_report(n=2000, b=16, solve_n=500, solve_tol=1e-4, oracle_sweeps=3):
@@ -423,6 +478,10 @@ def main():
                          "violation <= 1e-4, on workload --warm-config (tile size 32)")
     ap.add_argument("--cpu-baseline-rows", action="store_true",
                     help="each step of the path on the GPU beside the oracle (n = 500)")
+    ap.add_argument("--sparse-report", action="store_true",
+                    help="sparse dual access against the dense sweep at n = 2000 and 4000")
+    ap.add_argument("--sparse", action="store_true",
+                    help="with --warm-report: repeat its solves with sparse dual access")
     ap.add_argument("--nearness-report", action="store_true",
                     help="l2 metric nearness at n = 2000 (FP64 and FP32) beside the oracle")
     ap.add_argument("--polish-report", action="store_true",
@@ -567,6 +626,9 @@ def main():
     if args.cpu_baseline_rows:
         out["cpu_baseline_rows"] = cpu_baseline_rows()
 
+    if args.sparse_report:
+        out["sparse"] = sparse_report()
+
     if args.nearness_report:
         out["nearness"] = nearness_report()
 
@@ -580,7 +642,8 @@ def main():
         torch.cuda.empty_cache()
         # b = 16 keeps every CU busy at n = 2000 (about 670 tiles in flight
         # against 170 at b = 32); at n = 4000 b = 32 has enough
-        out["warm_start"] = warm_report(args.warm_config, 16 if args.warm_config == 3 else 32)
+        out["warm_start"] = warm_report(args.warm_config, 16 if args.warm_config == 3 else 32,
+                                        sparse=args.sparse)
 
     props = torch.cuda.get_device_properties(0)
     out["gpu"] = torch.cuda.get_device_name(0) or getattr(props, "gcnArchName", "")

@@ -25,6 +25,7 @@ CC_OK, CC_ENOTCONV = 0, 1
 CC_EINVAL, CC_ENOMEM, CC_EHIP, CC_ENONFINITE = -1, -2, -3, -4
 CC_F64, CC_F32 = 0, 1
 CC_MODE_F64, CC_MODE_F32, CC_MODE_F32_POLISH = 0, 1, 2
+CC_MODE_SPARSE = 16  # flag or-ed into a mode: sparse dual access
 CC_WARM_NONE, CC_WARM_MLP = 0, 1
 CC_EXEC_ROUNDS, CC_EXEC_DATAFLOW = 0, 1
 CC_RESID_VIOL, CC_RESID_CS, CC_RESID_DUAL, CC_RESID_ALL = 1, 2, 4, 7
@@ -87,6 +88,10 @@ _sig("cc_solve_cc_lp", ctypes.c_int, _i64, _p, _p, _dbl, _dbl, _i32, _i32, _i32,
      _p, _p, ctypes.POINTER(Info))
 _sig("cc_narrow", ctypes.c_int, _p, _p, _i64, _p)
 _sig("cc_nearness_init", ctypes.c_int, _p, _p, _p, _p)
+_sig("cc_dual_mask_bytes", _i64, _p)
+_sig("cc_dual_mask_build", ctypes.c_int, _p, _p, _p)
+_sig("cc_sweep_sparse", ctypes.c_int, _p, _p, _p, _p, _p, _p, _p, _p, _i32)
+_sig("cc_sweep_metric_sparse", ctypes.c_int, _p, _p, _p, _p, _p)
 _sig("cc_nearness_residuals", ctypes.c_int, _p, _p, _p, _p, _p, _i32, ctypes.POINTER(NResid))
 
 _sig("cc_mlp_num_params", _i32)
@@ -107,7 +112,8 @@ EXPORTS = ["cc_last_error", "cc_num_metric_duals", "cc_create", "cc_destroy", "c
            "cc_sweep_metric", "cc_status",
            "cc_pair_pass", "cc_residuals", "cc_x_from_y", "cc_duals_to_lex", "cc_slots_to_lex",
            "cc_dataflow_tables", "cc_widen", "cc_narrow", "cc_solve_cc_lp",
-           "cc_nearness_init", "cc_nearness_residuals"]
+           "cc_nearness_init", "cc_nearness_residuals", "cc_dual_mask_bytes",
+           "cc_dual_mask_build", "cc_sweep_sparse", "cc_sweep_metric_sparse"]
 
 
 class CCError(RuntimeError):
@@ -199,6 +205,22 @@ class Context:
 
     def sweep_metric(self, x, y, g, executor=None):
         check(_L.cc_sweep_metric(self._h, _ptr(x), _ptr(y), _ptr(g), self.executor(executor)))
+
+    def mask_bytes(self) -> int:
+        nbytes = _L.cc_dual_mask_bytes(self._h)
+        if nbytes < 0:
+            raise CCError(CC_EINVAL, "sparse dual access needs b = 8, 16 or 32")
+        return nbytes
+
+    def mask_build(self, y, mask):
+        check(_L.cc_dual_mask_build(self._h, _ptr(y), _ptr(mask)))
+
+    def sweep_sparse(self, x, f, y, y_pair, g, d, mask, nsweeps=1):
+        check(_L.cc_sweep_sparse(self._h, _ptr(x), _ptr(f), _ptr(y), _ptr(y_pair), _ptr(g),
+                                 _ptr(d), _ptr(mask), int(nsweeps)))
+
+    def sweep_metric_sparse(self, x, y, g, mask):
+        check(_L.cc_sweep_metric_sparse(self._h, _ptr(x), _ptr(y), _ptr(g), _ptr(mask)))
 
     def status(self):
         check(_L.cc_status(self._h))
@@ -302,6 +324,10 @@ class Solver:
         self.y_pair = torch.empty(2 * npairs, dtype=dt, device=device)
         self.ctx.prepare(self.w, self.gamma, self.g)
         self.sweeps = 0
+        # sparse dual access (Sec. III-D): the nonzero pattern of y, valid
+        # only while no dense writer has touched y since it was built
+        self.mask = None
+        self.mask_valid = False
         if cold:
             self.init_cold()
 
@@ -309,19 +335,44 @@ class Solver:
     def from_instance(cls, inst, **kw):
         return cls(inst.n, inst.w, inst.d, inst.gamma, **kw)
 
+    def invalidate_mask(self):
+        """Call after writing y by any means other than sparse sweeps."""
+        self.mask_valid = False
+
+    def ensure_mask(self):
+        if self.mask is None:
+            self.mask = torch.empty(self.ctx.mask_bytes(), dtype=torch.uint8, device=self.y.device)
+        if not self.mask_valid:
+            self.ctx.mask_build(self.y, self.mask)
+            self.mask_valid = True
+        return self.mask
+
     def init_cold(self):
         self.ctx.init_cold(self.x, self.f, self.y, self.y_pair, self.gamma)
+        self.invalidate_mask()
         self.sweeps = 0
 
-    def sweep(self, nsweeps=1, executor=None):
-        self.ctx.sweep(self.x, self.f, self.y, self.y_pair, self.g, self.d, nsweeps, executor)
+    def sweep(self, nsweeps=1, executor=None, sparse=False):
+        """nsweeps sweeps; sparse=True reads only the duals the mask marks
+        (dataflow executor, b = 8, 16, 32; the same results bit for bit)."""
+        if sparse:
+            self.ctx.sweep_sparse(self.x, self.f, self.y, self.y_pair, self.g, self.d,
+                                  self.ensure_mask(), nsweeps)
+        else:
+            self.ctx.sweep(self.x, self.f, self.y, self.y_pair, self.g, self.d, nsweeps, executor)
+            self.invalidate_mask()
         self.sweeps += nsweeps
 
     def sweep_rounds(self, first, count):
         self.ctx.sweep_rounds(self.x, self.y, self.g, first, count)
+        self.invalidate_mask()
 
-    def sweep_metric(self, executor=None):
-        self.ctx.sweep_metric(self.x, self.y, self.g, executor)
+    def sweep_metric(self, executor=None, sparse=False):
+        if sparse:
+            self.ctx.sweep_metric_sparse(self.x, self.y, self.g, self.ensure_mask())
+        else:
+            self.ctx.sweep_metric(self.x, self.y, self.g, executor)
+            self.invalidate_mask()
 
     def status(self):
         self.ctx.status()
@@ -344,7 +395,7 @@ class Solver:
         self.ctx.duals_to_lex(self.y, y_lex)
         return y_lex
 
-    def solve(self, tol=1e-6, max_sweeps=100000, check_every=None, executor=None):
+    def solve(self, tol=1e-6, max_sweeps=100000, check_every=None, executor=None, sparse=False):
         """Sweep until both max violations are <= tol, checked every
         `check_every` sweeps (default as in cc_solve_cc_lp: every sweep up to
         n = 1000, every 5 above; a check reads every triplet).  Returns
@@ -355,7 +406,7 @@ class Solver:
         r = None
         while self.sweeps < max_sweeps:
             k = min(check_every, max_sweeps - self.sweeps)
-            self.sweep(k, executor)
+            self.sweep(k, executor, sparse)
             r = self.residuals(CC_RESID_VIOL)
             if max(r["max_viol_metric"], r["max_viol_pair"]) <= tol:
                 return self.residuals(), True, time.perf_counter() - t0
@@ -380,6 +431,7 @@ class NearnessSolver:
         self.x = torch.empty(npairs, dtype=dt, device=device)
         self.y = torch.empty(self.ctx.slots, dtype=dt, device=device)
         self.ctx.prepare(self.w, 1.0, self.g)
+        self.mask = None  # nonzero pattern of y for sparse sweeps
         self.init()
 
     @classmethod
@@ -388,11 +440,24 @@ class NearnessSolver:
 
     def init(self):
         check(_L.cc_nearness_init(self.ctx.handle, _ptr(self.dv), _ptr(self.x), _ptr(self.y)))
+        self.mask_valid = False
         self.sweeps = 0
 
-    def sweep(self, nsweeps=1, executor=None):
+    def ensure_mask(self):
+        if self.mask is None:
+            self.mask = torch.empty(self.ctx.mask_bytes(), dtype=torch.uint8, device=self.y.device)
+        if not self.mask_valid:
+            self.ctx.mask_build(self.y, self.mask)
+            self.mask_valid = True
+        return self.mask
+
+    def sweep(self, nsweeps=1, executor=None, sparse=False):
         for _ in range(nsweeps):
-            self.ctx.sweep_metric(self.x, self.y, self.g, executor)
+            if sparse:
+                self.ctx.sweep_metric_sparse(self.x, self.y, self.g, self.ensure_mask())
+            else:
+                self.ctx.sweep_metric(self.x, self.y, self.g, executor)
+                self.mask_valid = False
         self.sweeps += nsweeps
 
     def status(self):
@@ -412,7 +477,8 @@ class NearnessSolver:
         self.ctx.duals_to_lex(self.y, y_lex)
         return y_lex
 
-    def solve(self, tol=1e-6, gap_tol=None, max_sweeps=100000, check_every=None, executor=None):
+    def solve(self, tol=1e-6, gap_tol=None, max_sweeps=100000, check_every=None, executor=None,
+              sparse=False):
         """Sweep until the max metric violation is at most tol and, with
         gap_tol, the relative primal-dual gap is at most gap_tol.  Returns
         (residuals, converged)."""
@@ -420,7 +486,7 @@ class NearnessSolver:
         what = CC_RESID_VIOL | (CC_RESID_DUAL if gap_tol is not None else 0)
         r = self.residuals(what)
         while self.sweeps < max_sweeps:
-            self.sweep(min(every, max_sweeps - self.sweeps), executor)
+            self.sweep(min(every, max_sweeps - self.sweeps), executor, sparse)
             r = self.residuals(what)
             if r["max_viol"] <= tol and (gap_tol is None or
                                          abs(r["gap"]) <= gap_tol * max(1.0, abs(r["primal"]))):

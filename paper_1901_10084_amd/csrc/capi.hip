@@ -58,7 +58,8 @@ struct DataflowArgs {
 };
 void build_dataflow_tables(int64_t n, int b, std::vector<DTile> &tiles, std::vector<uint32_t> &needs,
                            std::vector<uint32_t> &K);
-template <typename T> int launch_sweep_dataflow(const DataflowArgs &, int, int, int64_t, T *, const T *, T *, hipStream_t);
+template <typename T> int launch_sweep_dataflow(const DataflowArgs &, int, int, int64_t, T *, const T *, T *, void *, hipStream_t);
+template <typename T> int launch_mask_build(int, int64_t, const T *, void *, hipStream_t);
 template <typename T> int dataflow_occupancy(int, int *);
 template <typename T> int launch_aty_dataflow(const DataflowArgs &, int, int, int64_t, const T *, double *, hipStream_t);
 template <typename T> int aty_dataflow_occupancy(int, int *);
@@ -234,15 +235,17 @@ int ensure_dataflow(cc_ctx *c) {
     return CC_OK;
 }
 
+// mask != nullptr: the sparse dataflow sweep (exec must be CC_EXEC_DATAFLOW)
 template <typename T>
-int sweep_metric_t(cc_ctx *c, T *x, T *y, const T *g, int exec, unsigned long long *prof);
+int sweep_metric_t(cc_ctx *c, T *x, T *y, const T *g, int exec, unsigned long long *prof,
+                   void *mask = nullptr);
 
 template <typename T>
 int sweep_dataflow_t(cc_ctx *c, T *x, T *f, T *y, T *yp, const T *g, const uint8_t *d,
-                     int nsweeps) {
+                     int nsweeps, void *mask = nullptr) {
     int rc;
     for (int s = 0; s < nsweeps; ++s) {
-        if ((rc = sweep_metric_t<T>(c, x, y, g, CC_EXEC_DATAFLOW, nullptr))) return rc;
+        if ((rc = sweep_metric_t<T>(c, x, y, g, CC_EXEC_DATAFLOW, nullptr, mask))) return rc;
         if ((rc = launch_pair_pass<T>(num_pairs(c->n), x, f, yp, g, d, c->stream))) return rc;
     }
     return CC_OK;
@@ -279,12 +282,13 @@ int dataflow_args(cc_ctx *c, unsigned long long *prof, DataflowArgs &a) {
 }
 
 template <typename T>
-int sweep_metric_t(cc_ctx *c, T *x, T *y, const T *g, int exec, unsigned long long *prof) {
+int sweep_metric_t(cc_ctx *c, T *x, T *y, const T *g, int exec, unsigned long long *prof,
+                   void *mask) {
     if (exec == CC_EXEC_ROUNDS) return sweep_rounds_t<T>(c, x, y, g, 0, c->nrounds);
     DataflowArgs a;
     int rc = dataflow_args(c, prof, a);
     if (rc) return rc;
-    if ((rc = launch_sweep_dataflow<T>(a, c->df_grid, c->b, c->n, x, g, y, c->stream))) return rc;
+    if ((rc = launch_sweep_dataflow<T>(a, c->df_grid, c->b, c->n, x, g, y, mask, c->stream))) return rc;
     c->epoch++;
     return CC_OK;
 }
@@ -549,6 +553,49 @@ int cc_sweep_metric(cc_ctx *c, void *x, void *y, const void *g, int32_t exec) {
     if (exec != CC_EXEC_ROUNDS && exec != CC_EXEC_DATAFLOW) return fail(CC_EINVAL, "unknown executor");
     if (c->prec == CC_F64) return sweep_metric_t<double>(c, (double *)x, (double *)y, (const double *)g, exec, nullptr);
     return sweep_metric_t<float>(c, (float *)x, (float *)y, (const float *)g, exec, nullptr);
+}
+
+int64_t cc_dual_mask_bytes(const cc_ctx *c) {
+    if (!c || !(c->b == 8 || c->b == 16 || c->b == 32)) return -1;
+    return c->slots / 8;
+}
+
+int cc_dual_mask_build(cc_ctx *c, const void *y, void *mask) {
+    int rc;
+    if ((rc = check_ctx(c)) || (rc = need(y, "y")) || (rc = need(mask, "mask"))) return rc;
+    const int64_t nsteps = c->slots / (int64_t(3) * c->b * c->b * c->b);
+    if (c->prec == CC_F64) return launch_mask_build<double>(c->b, nsteps, (const double *)y, mask, c->stream);
+    return launch_mask_build<float>(c->b, nsteps, (const float *)y, mask, c->stream);
+}
+
+int cc_sweep_sparse(cc_ctx *c, void *x, void *f, void *y, void *yp, const void *g, const uint8_t *d,
+                    void *mask, int32_t nsweeps) {
+    int rc;
+    if ((rc = check_ctx(c)) || (rc = need(x, "x")) || (rc = need(f, "f")) || (rc = need(y, "y")) ||
+        (rc = need(yp, "y_pair")) || (rc = need(g, "g")) || (rc = need(d, "d")) || (rc = need(mask, "mask")))
+        return rc;
+    if (nsweeps < 0) return fail(CC_EINVAL, "nsweeps must be >= 0");
+    if (!(c->b == 8 || c->b == 16 || c->b == 32)) return fail(CC_EINVAL, "sparse sweeps need b = 8, 16 or 32");
+    if (int64_t(c->nb) * 3 * c->b * c->b * c->b * int64_t(elem_size(c)) >= (int64_t(1) << 31))
+        return fail(CC_EINVAL, "sparse sweeps address a tile's duals with 31-bit offsets: n too large for b");
+    if (c->prec == CC_F64)
+        return sweep_dataflow_t<double>(c, (double *)x, (double *)f, (double *)y, (double *)yp,
+                                        (const double *)g, d, nsweeps, mask);
+    return sweep_dataflow_t<float>(c, (float *)x, (float *)f, (float *)y, (float *)yp, (const float *)g,
+                                   d, nsweeps, mask);
+}
+
+int cc_sweep_metric_sparse(cc_ctx *c, void *x, void *y, const void *g, void *mask) {
+    int rc;
+    if ((rc = check_ctx(c)) || (rc = need(x, "x")) || (rc = need(y, "y")) || (rc = need(g, "g")) ||
+        (rc = need(mask, "mask")))
+        return rc;
+    if (!(c->b == 8 || c->b == 16 || c->b == 32)) return fail(CC_EINVAL, "sparse sweeps need b = 8, 16 or 32");
+    if (int64_t(c->nb) * 3 * c->b * c->b * c->b * int64_t(elem_size(c)) >= (int64_t(1) << 31))
+        return fail(CC_EINVAL, "sparse sweeps address a tile's duals with 31-bit offsets: n too large for b");
+    if (c->prec == CC_F64)
+        return sweep_metric_t<double>(c, (double *)x, (double *)y, (const double *)g, CC_EXEC_DATAFLOW, nullptr, mask);
+    return sweep_metric_t<float>(c, (float *)x, (float *)y, (const float *)g, CC_EXEC_DATAFLOW, nullptr, mask);
 }
 
 int cc_dataflow_breakdown(cc_ctx *c, void *x, void *y, const void *g, double *out) {
@@ -911,16 +958,25 @@ struct CtxGuard {
 };
 
 // Sweeps until both max violations are <= tol or max_sweeps is reached;
-// returns CC_OK or CC_ENOTCONV, *done = sweeps run.
+// returns CC_OK or CC_ENOTCONV, *done = sweeps run.  sparse: sparse dual
+// access, with a mask built from y here (nothing else writes y meanwhile).
 int sweep_to_tol(cc_ctx *c, void *x, void *f, void *y, void *yp, void *g, const uint8_t *d,
                  const double *w, double gamma, double tol, int max_sweeps, int *done,
-                 cc_resid *r) {
+                 cc_resid *r, bool sparse) {
     const int every = c->n <= 1000 ? 1 : 5;
     const int exec = (c->b == 8 || c->b == 16 || c->b == 32) ? CC_EXEC_DATAFLOW : CC_EXEC_ROUNDS;
+    DevBuf mask;
+    if (sparse) {
+        int rc;
+        if ((rc = mask.alloc(size_t(cc_dual_mask_bytes(c)), "dual mask")) ||
+            (rc = cc_dual_mask_build(c, y, mask.p)))
+            return rc;
+    }
     *done = 0;
     while (*done < max_sweeps) {
         const int k = std::min(every, max_sweeps - *done);
-        int rc = cc_sweep(c, x, f, y, yp, g, d, k, exec);
+        int rc = sparse ? cc_sweep_sparse(c, x, f, y, yp, g, d, mask.p, k)
+                        : cc_sweep(c, x, f, y, yp, g, d, k, exec);
         if (rc) return rc;
         *done += k;
         rc = cc_residuals(c, x, f, nullptr, nullptr, w, d, gamma, CC_RESID_VIOL, r);
@@ -943,8 +999,12 @@ extern "C" int cc_solve_cc_lp(int64_t n, const double *w_host, const uint8_t *d_
     if (!(gamma > 0.0) || !std::isfinite(gamma)) return fail(CC_EINVAL, "gamma must be > 0");
     if (!(tol > 0.0)) return fail(CC_EINVAL, "tol must be > 0");
     if (max_sweeps < 1) return fail(CC_EINVAL, "max_sweeps must be >= 1");
+    const bool sparse = (mode & CC_MODE_SPARSE) != 0;
+    mode &= ~CC_MODE_SPARSE;
     if (mode != CC_MODE_F64 && mode != CC_MODE_F32 && mode != CC_MODE_F32_POLISH)
         return fail(CC_EINVAL, "unknown mode");
+    if (sparse && !(b == 8 || b == 16 || b == 32))
+        return fail(CC_EINVAL, "CC_MODE_SPARSE needs b = 8, 16 or 32");
     if (warm != CC_WARM_NONE && warm != CC_WARM_MLP) return fail(CC_EINVAL, "unknown warm start");
     if (warm == CC_WARM_MLP && (!mlp_weights_host || !deg_host))
         return fail(CC_EINVAL, "warm start needs network weights and degrees");
@@ -994,7 +1054,7 @@ extern "C" int cc_solve_cc_lp(int64_t n, const double *w_host, const uint8_t *d_
         }
         const double tol32 = (mode == CC_MODE_F32_POLISH) ? std::fmax(tol, 1e-4) : tol;
         status = sweep_to_tol(c32.c, x32.p, f32b.p, y32.p, yp32.p, g32.p, d, w, gamma, tol32,
-                              max_sweeps, &done, &r);
+                              max_sweeps, &done, &r, sparse);
         if (status < 0) return status;
         info->sweeps = info->sweeps_f32 = done;
     }
@@ -1033,7 +1093,7 @@ extern "C" int cc_solve_cc_lp(int64_t n, const double *w_host, const uint8_t *d_
         const int left = max_sweeps - info->sweeps;
         if (left > 0) {
             status = sweep_to_tol(c64.c, x64.p, f64b.p, y64.p, yp64.p, g64.p, d, w, gamma, tol,
-                                  left, &done, &r);
+                                  left, &done, &r, sparse);
             if (status < 0) return status;
             info->sweeps += done;
         } else {

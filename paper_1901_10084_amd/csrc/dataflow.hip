@@ -22,12 +22,53 @@
 // counters; a waiting tile polls the counters (agent-scope loads) before it
 // loads the blocks.  No L2 write-back is needed: the dual stream, which is
 // private to its tile, stays out of the release.
+//
+// Sparse dual access (Sec. III-D keeps only the nonzero duals, in visit
+// order, per processor).  Here the dense schedule-ordered dual array stays
+// the storage every other kernel reads, and a bit mask with one bit per dual
+// slot marks the slots that may hold a nonzero dual.  The sparse sweep loads
+// only marked duals (an unmarked one is 0), stores a dual only where its
+// value changed, and rewrites the mask from the new duals; its results equal
+// the dense sweep's bit for bit.  Mask layout: tile step c (schedule order)
+// holds 3 b^2 words of b bits, word [c][o][lane] with bit t for sub-step t.
 #include <vector>
 
 #include "common.hpp"
 #include "project.hpp"
 
 namespace ccp {
+
+template <int B> struct MaskWord;
+template <> struct MaskWord<8> { using type = uint8_t; };
+template <> struct MaskWord<16> { using type = uint16_t; };
+template <> struct MaskWord<32> { using type = uint32_t; };
+
+// Bit pattern of a dual: the mask marks every slot whose bits are not those
+// of +0.0 (a -0.0 counts as nonzero), so an unmarked slot reads back exactly.
+__device__ __forceinline__ uint64_t dual_bits(double v) { return __builtin_bit_cast(uint64_t, v); }
+__device__ __forceinline__ uint64_t dual_bits(float v) { return __builtin_bit_cast(uint32_t, v); }
+
+// Masked dual accesses go through a buffer resource over the tile's dual
+// segment: an offset at or beyond its size (kOffNone) reads 0 and writes
+// nothing, without a memory access, so a masked lane needs no branch (and
+// the prefetch ring keeps exact memory-counter waits).  Cache policy 2 is
+// the non-temporal hint of the dense accesses.
+constexpr uint32_t kOffNone = 0x80000000u;
+constexpr int kBufNT = 2;
+constexpr int kBufFlags = 0x00020000;  // gfx9 raw buffer, 32-bit data format
+__device__ __forceinline__ double buf_load(__amdgpu_buffer_rsrc_t r, uint32_t off, double) {
+    return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, int(off), 0, kBufNT));
+}
+__device__ __forceinline__ float buf_load(__amdgpu_buffer_rsrc_t r, uint32_t off, float) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, int(off), 0, kBufNT));
+}
+__device__ __forceinline__ void buf_store(double v, __amdgpu_buffer_rsrc_t r, uint32_t off) {
+    using V2 = decltype(__builtin_amdgcn_raw_buffer_load_b64(r, 0, 0, 0));
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(V2, v), r, int(off), 0, kBufNT);
+}
+__device__ __forceinline__ void buf_store(float v, __amdgpu_buffer_rsrc_t r, uint32_t off) {
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, v), r, int(off), 0, kBufNT);
+}
 
 struct DTile {
     int32_t P, Q;
@@ -129,10 +170,11 @@ __device__ __forceinline__ bool wait_counts(const uint32_t *c0, uint32_t n0, con
     return res;
 }
 
-template <typename T, int B, int D>
+template <typename T, int B, int D, bool SP>
 __global__ void __launch_bounds__(B * B)
 k_sweep_dataflow(DataflowArgs a, int64_t n, T *__restrict__ x, const T *__restrict__ g,
-                 T *__restrict__ y) {
+                 T *__restrict__ y, typename MaskWord<B>::type *__restrict__ mask) {
+    using MW = typename MaskWord<B>::type;
     // the first and last groups of D sub-steps are peeled: refills of the
     // other groups stay inside the step
     static_assert(B % D == 0 && B >= 2 * D, "ring depth must divide b, twice at least");
@@ -252,17 +294,54 @@ k_sweep_dataflow(DataflowArgs a, int64_t n, T *__restrict__ x, const T *__restri
         const int64_t ystep = int64_t(3) * bb;
         const unsigned lane = unsigned(tid);
         T yq[D][3];
+        // Sparse access: mw holds the mask words of the current step, mwn
+        // those of the next step (loaded one step ahead), nm the new words.
+        uint32_t mw[3] = {0u, 0u, 0u}, mwn[3] = {0u, 0u, 0u}, nm[3] = {0u, 0u, 0u};
+        auto mask_row = [&](int m) { return mask + (int64_t(tl.jsbase) + m) * 3 * bb; };
+        auto load_mask = [&](int m) {
+            const MW *r = mask_row(m);
+            mwn[0] = r[lane];
+            mwn[1] = r[lane + bb];
+            mwn[2] = r[lane + 2 * bb];
+        };
+        // The tile's dual segment as a buffer (sparse access only; its size
+        // stays below kOffNone, at most nb 3 b^3 elements).
+        // (inputs made wave-uniform: a descriptor in vector registers would
+        // cost a loop over the distinct values at every access)
+        const uint64_t ya = reinterpret_cast<uint64_t>(ytile);
+        const uint64_t yau = (uint64_t(__builtin_amdgcn_readfirstlane(uint32_t(ya >> 32))) << 32) |
+                             uint32_t(__builtin_amdgcn_readfirstlane(uint32_t(ya)));
+        const __amdgpu_buffer_rsrc_t yr = __builtin_amdgcn_make_buffer_rsrc(
+            reinterpret_cast<void *>(yau), 0,
+            __builtin_amdgcn_readfirstlane(int(int64_t(Q - P + 1) * b * ystep * int64_t(sizeof(T)))), kBufFlags);
+        // byte offset of dual (u, o) of this lane, kOffNone where mask bit t is clear
+        auto boff = [&](int u, int t, int o) {
+            const uint32_t off = uint32_t((int64_t(u) * ystep + o * bb + int(lane)) * int64_t(sizeof(T)));
+            return ((mw[o] >> t) & 1u) ? off : kOffNone;
+        };
+        // dual o of sub-step t of step m (flat sub-step u = m b + t)
+        auto ld = [&](const T *p, int u, int t, int o) {
+            if constexpr (SP)
+                return buf_load(yr, boff(u, t, o), T(0));
+            else
+                return __builtin_nontemporal_load(p);
+        };
+        // Ring slot d <- the duals of sub-step t of the step (flat sub-step
+        // u).  Sparse access issues every load (unmarked lanes read 0 out of
+        // range): a load under a branch would leave the compiler unable to
+        // count the loads in flight, and it would then wait for all of them.
+        auto ring_load = [&](int d, const T *src, int u, int t) {
+            yq[d][0] = ld(&src[lane], u, t, 0);
+            yq[d][1] = ld(&src[lane + bb], u, t, 1);
+            yq[d][2] = ld(&src[lane + 2 * bb], u, t, 2);
+        };
         // ring: the first D sub-steps of step m (all inside the step, D | b)
         auto fill_ring = [&](int m) {
 #pragma unroll
-            for (int d = 0; d < D; ++d) {
-                const T *src = ytile + int64_t(m * b + d) * ystep;
-                yq[d][0] = __builtin_nontemporal_load(&src[lane]);
-                yq[d][1] = __builtin_nontemporal_load(&src[lane + bb]);
-                yq[d][2] = __builtin_nontemporal_load(&src[lane + 2 * bb]);
-            }
+            for (int d = 0; d < D; ++d) ring_load(d, ytile + int64_t(m * b + d) * ystep, m * b + d, d);
         };
 
+        if constexpr (SP) load_mask(0);
         // Block (P,Q) and the first step's blocks: wait, then hold (P,Q).
         if (tid == 0) {
             if (a.prof) s_pt[5] = wall_clock64();
@@ -295,6 +374,14 @@ k_sweep_dataflow(DataflowArgs a, int64_t n, T *__restrict__ x, const T *__restri
             T vax, vag, vbx, vbg;
             blk_load(P, J, vax, vag);
             blk_load(J, Q, vbx, vbg);
+            if constexpr (SP) {
+#pragma unroll
+                for (int o = 0; o < 3; ++o) {
+                    mw[o] = mwn[o];
+                    nm[o] = 0u;
+                }
+                if (m < Q - P) load_mask(m + 1);
+            }
             fill_ring(m);
             blk_store(P, J, vax, vag, Ax0, Ag0);
             blk_store(J, Q, vbx, vbg, Bx0, Bg0);
@@ -353,17 +440,31 @@ k_sweep_dataflow(DataflowArgs a, int64_t n, T *__restrict__ x, const T *__restri
                         }
                     }
                     T *dst = ytile + int64_t(__builtin_amdgcn_readfirstlane(u)) * ystep;
-                    __builtin_nontemporal_store(y0, &dst[lane]);
-                    __builtin_nontemporal_store(y1, &dst[lane + bb]);
-                    __builtin_nontemporal_store(y2, &dst[lane + 2 * bb]);
+                    if constexpr (SP) {
+                        // store only changed duals; mark the nonzero ones
+                        const uint64_t b0 = dual_bits(y0), b1 = dual_bits(y1), b2 = dual_bits(y2);
+                        const uint32_t ou = uint32_t(int64_t(u) * ystep * int64_t(sizeof(T)));
+                        constexpr uint32_t os = uint32_t(bb * sizeof(T));
+                        const uint32_t l = uint32_t(lane * sizeof(T));
+                        // (under a branch: a wave with nothing to store skips
+                        // the instruction, which would otherwise queue ahead
+                        // of the ring's loads)
+                        if (b0 != dual_bits(yq[d][0])) buf_store(y0, yr, ou + l);
+                        if (b1 != dual_bits(yq[d][1])) buf_store(y1, yr, ou + os + l);
+                        if (b2 != dual_bits(yq[d][2])) buf_store(y2, yr, ou + 2 * os + l);
+                        nm[0] |= uint32_t(b0 != 0) << t;
+                        nm[1] |= uint32_t(b1 != 0) << t;
+                        nm[2] |= uint32_t(b2 != 0) << t;
+                    } else {
+                        __builtin_nontemporal_store(y0, &dst[lane]);
+                        __builtin_nontemporal_store(y1, &dst[lane + bb]);
+                        __builtin_nontemporal_store(y2, &dst[lane + 2 * bb]);
+                    }
                     if (refill) {
                         // Refill slot d after its duals are consumed, so the
                         // old and new values never live at once (no register
                         // copies of loads in flight).
-                        const T *src = ytile + int64_t(__builtin_amdgcn_readfirstlane(u + D)) * ystep;
-                        yq[d][0] = __builtin_nontemporal_load(&src[lane]);
-                        yq[d][1] = __builtin_nontemporal_load(&src[lane + bb]);
-                        yq[d][2] = __builtin_nontemporal_load(&src[lane + 2 * bb]);
+                        ring_load(d, ytile + int64_t(__builtin_amdgcn_readfirstlane(u + D)) * ystep, u + D, t + D);
                     }
                     lds_barrier();
                 }
@@ -372,6 +473,12 @@ k_sweep_dataflow(DataflowArgs a, int64_t n, T *__restrict__ x, const T *__restri
 #pragma nounroll
             for (int t0 = D; t0 < b - D; t0 += D) group(t0, true);
             group(b - D, false);
+            if constexpr (SP) {
+                MW *r = mask_row(m);
+                if (nm[0] != mw[0]) r[lane] = MW(nm[0]);
+                if (nm[1] != mw[1]) r[lane + bb] = MW(nm[1]);
+                if (nm[2] != mw[2]) r[lane + 2 * bb] = MW(nm[2]);
+            }
             if (tid == 0 && a.prof) mark(2);
 
             // Publish this step's (P,J) and (J,Q) blocks (and (P,Q) after the
@@ -594,6 +701,51 @@ __global__ void k_fill_u32(int64_t count, uint32_t *a) {
         a[e] = 0u;
 }
 
+// The mask of a dual array: bit t of word [c][o][lane] is set where slot
+// (t, o, lane) of tile step c holds a dual whose bits are not +0.0.
+template <typename T, int B>
+__global__ void __launch_bounds__(B * B)
+k_mask_build(int64_t nsteps, const T *__restrict__ y, typename MaskWord<B>::type *__restrict__ mask) {
+    using MW = typename MaskWord<B>::type;
+    constexpr int bb = B * B;
+    const int lane = threadIdx.x;
+    for (int64_t c = blockIdx.x; c < nsteps; c += gridDim.x) {
+        const T *yc = y + c * 3 * B * bb;
+        uint32_t w0 = 0u, w1 = 0u, w2 = 0u;
+#pragma unroll 4
+        for (int t = 0; t < B; ++t) {
+            const T *r = yc + int64_t(t) * 3 * bb;
+            w0 |= uint32_t(dual_bits(__builtin_nontemporal_load(&r[lane])) != 0) << t;
+            w1 |= uint32_t(dual_bits(__builtin_nontemporal_load(&r[lane + bb])) != 0) << t;
+            w2 |= uint32_t(dual_bits(__builtin_nontemporal_load(&r[lane + 2 * bb])) != 0) << t;
+        }
+        MW *m = mask + c * 3 * bb;
+        m[lane] = MW(w0);
+        m[lane + bb] = MW(w1);
+        m[lane + 2 * bb] = MW(w2);
+    }
+}
+
+template <typename T, int B>
+static int launch_mask_build_t(int64_t nsteps, const T *y, void *mask, hipStream_t s) {
+    if (nsteps <= 0) return CC_OK;
+    const int64_t grid = nsteps < (int64_t(1) << 20) ? nsteps : (int64_t(1) << 20);
+    hipLaunchKernelGGL((k_mask_build<T, B>), dim3(unsigned(grid)), dim3(B * B), 0, s, nsteps, y,
+                       static_cast<typename MaskWord<B>::type *>(mask));
+    CCP_LAUNCH_CHECK("k_mask_build");
+    return CC_OK;
+}
+
+template <typename T>
+int launch_mask_build(int b, int64_t nsteps, const T *y, void *mask, hipStream_t s) {
+    switch (b) {
+        case 8: return launch_mask_build_t<T, 8>(nsteps, y, mask, s);
+        case 16: return launch_mask_build_t<T, 16>(nsteps, y, mask, s);
+        case 32: return launch_mask_build_t<T, 32>(nsteps, y, mask, s);
+        default: return fail(CC_EINVAL, "sparse dual access supports b = 8, 16, 32");
+    }
+}
+
 template <typename T>
 size_t dataflow_lds_bytes(int b) {
     return size_t(6) * b * b * sizeof(T);
@@ -601,22 +753,29 @@ size_t dataflow_lds_bytes(int b) {
 
 template <typename T, int B, int D>
 static int launch_df_t(const DataflowArgs &a, int grid, int64_t n, T *x, const T *g, T *y,
-                       hipStream_t s) {
+                       void *mask, hipStream_t s) {
+    using MW = typename MaskWord<B>::type;
     const size_t lds = dataflow_lds_bytes<T>(B);
     hipLaunchKernelGGL(k_dataflow_reset, dim3(1), dim3(64), 0, s, a.ctl);
     CCP_LAUNCH_CHECK("k_dataflow_reset");
-    hipLaunchKernelGGL((k_sweep_dataflow<T, B, D>), dim3(grid), dim3(B * B), lds, s, a, n, x, g, y);
+    if (mask)
+        hipLaunchKernelGGL((k_sweep_dataflow<T, B, D, true>), dim3(grid), dim3(B * B), lds, s, a, n, x, g, y,
+                           static_cast<MW *>(mask));
+    else
+        hipLaunchKernelGGL((k_sweep_dataflow<T, B, D, false>), dim3(grid), dim3(B * B), lds, s, a, n, x, g, y,
+                           static_cast<MW *>(nullptr));
     CCP_LAUNCH_CHECK("k_sweep_dataflow");
     return CC_OK;
 }
 
+// mask == nullptr: the dense sweep; otherwise the sparse one with this mask.
 template <typename T>
 int launch_sweep_dataflow(const DataflowArgs &a, int grid, int b, int64_t n, T *x, const T *g,
-                          T *y, hipStream_t s) {
+                          T *y, void *mask, hipStream_t s) {
     switch (b) {
-        case 8: return launch_df_t<T, 8, 4>(a, grid, n, x, g, y, s);
-        case 16: return launch_df_t<T, 16, 8>(a, grid, n, x, g, y, s);
-        case 32: return launch_df_t<T, 32, 4>(a, grid, n, x, g, y, s);
+        case 8: return launch_df_t<T, 8, 4>(a, grid, n, x, g, y, mask, s);
+        case 16: return launch_df_t<T, 16, 8>(a, grid, n, x, g, y, mask, s);
+        case 32: return launch_df_t<T, 32, 4>(a, grid, n, x, g, y, mask, s);
         default: return fail(CC_EINVAL, "the dataflow executor supports b = 8, 16, 32");
     }
 }
@@ -627,16 +786,19 @@ int dataflow_occupancy(int b, int *blocks_per_cu) {
     const int lds = int(dataflow_lds_bytes<T>(b));
     switch (b) {
         case 8:
-            e = hipFuncSetAttribute((const void *)k_sweep_dataflow<T, 8, 4>, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
-            if (e == hipSuccess) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, k_sweep_dataflow<T, 8, 4>, 64, lds);
+            e = hipFuncSetAttribute((const void *)k_sweep_dataflow<T, 8, 4, false>, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+            if (e == hipSuccess) e = hipFuncSetAttribute((const void *)k_sweep_dataflow<T, 8, 4, true>, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+            if (e == hipSuccess) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, k_sweep_dataflow<T, 8, 4, false>, 64, lds);
             break;
         case 16:
-            e = hipFuncSetAttribute((const void *)k_sweep_dataflow<T, 16, 8>, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
-            if (e == hipSuccess) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, k_sweep_dataflow<T, 16, 8>, 256, lds);
+            e = hipFuncSetAttribute((const void *)k_sweep_dataflow<T, 16, 8, false>, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+            if (e == hipSuccess) e = hipFuncSetAttribute((const void *)k_sweep_dataflow<T, 16, 8, true>, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+            if (e == hipSuccess) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, k_sweep_dataflow<T, 16, 8, false>, 256, lds);
             break;
         case 32:
-            e = hipFuncSetAttribute((const void *)k_sweep_dataflow<T, 32, 4>, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
-            if (e == hipSuccess) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, k_sweep_dataflow<T, 32, 4>, 1024, lds);
+            e = hipFuncSetAttribute((const void *)k_sweep_dataflow<T, 32, 4, false>, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+            if (e == hipSuccess) e = hipFuncSetAttribute((const void *)k_sweep_dataflow<T, 32, 4, true>, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+            if (e == hipSuccess) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, k_sweep_dataflow<T, 32, 4, false>, 1024, lds);
             break;
         default:
             *blocks_per_cu = 0;
@@ -690,9 +852,11 @@ int launch_fill_u32(int64_t count, uint32_t *a, hipStream_t s) {
 }
 
 template int launch_sweep_dataflow<double>(const DataflowArgs &, int, int, int64_t, double *,
-                                           const double *, double *, hipStream_t);
+                                           const double *, double *, void *, hipStream_t);
 template int launch_sweep_dataflow<float>(const DataflowArgs &, int, int, int64_t, float *,
-                                          const float *, float *, hipStream_t);
+                                          const float *, float *, void *, hipStream_t);
+template int launch_mask_build<double>(int, int64_t, const double *, void *, hipStream_t);
+template int launch_mask_build<float>(int, int64_t, const float *, void *, hipStream_t);
 template int launch_aty_dataflow<double>(const DataflowArgs &, int, int, int64_t, const double *, double *, hipStream_t);
 template int launch_aty_dataflow<float>(const DataflowArgs &, int, int, int64_t, const float *, double *, hipStream_t);
 template int aty_dataflow_occupancy<double>(int, int *);

@@ -114,6 +114,7 @@ def warm_start(solver, net: Network, deg) -> dict:
                                    solver.x.data_ptr(), solver.f.data_ptr(), solver.y.data_ptr(),
                                    solver.y_pair.data_ptr(), solver.g.data_ptr(),
                                    ctypes.byref(acc), ctypes.byref(dw), ctypes.byref(dc)))
+    solver.invalidate_mask()
     solver.sweeps = 0
     return {"accepted": bool(acc.value), "dual_warm": dw.value, "dual_cold": dc.value}
 
