@@ -322,8 +322,17 @@ def nearness_report(n=2000, b=16, solve_n=500, solve_tol=1e-4, oracle_sweeps=3):
         torch.cuda.synchronize()
         s.status()
         ms = e0.elapsed_time(e1) / 5
+        s.sweep(1, sparse=True)
+        e0.record()
+        s.sweep(5, sparse=True)
+        e1.record()
+        torch.cuda.synchronize()
+        s.status()
+        ms_sparse = e0.elapsed_time(e1) / 5
         algo = 2 * rows * sz + 3 * npairs * sz
-        res["sweep"][prec] = {"ms_per_sweep": ms,
+        nz = sum(int(torch.count_nonzero(s.y[i:i + (1 << 28)])) for i in range(0, s.y.numel(), 1 << 28))
+        res["sweep"][prec] = {"ms_per_sweep": ms, "ms_per_sweep_sparse": ms_sparse,
+                              "sweeps_before_sparse_timing": 8, "nonzero_fraction": nz / rows,
                               "constraint_projections_per_s": rows / (ms * 1e-3),
                               "roofline": {"bound": "hbm", "achieved": algo / (ms * 1e-3) / 1e9,
                                            "peak": 8000.0, "unit": "GB/s",
@@ -335,22 +344,25 @@ def nearness_report(n=2000, b=16, solve_n=500, solve_tol=1e-4, oracle_sweeps=3):
     small = I.noisy_distances(solve_n, seed=0, noise=0.5)
     srows = 3 * solve_n * (solve_n - 1) * (solve_n - 2) // 6
     res["solve"] = {"workload": small.name, "n": solve_n, "b": b, "tol": solve_tol}
-    for prec in ("f64", "f32"):
+    for prec, sp in (("f64", False), ("f32", False), ("f64", True), ("f32", True)):
         s = C.NearnessSolver.from_instance(small, b=b, prec=prec)
         s.residuals(C.CC_RESID_VIOL)
+        if sp:
+            s.ensure_mask()
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         ok = False
         while not ok and s.sweeps < 20000:
-            r, ok = s.solve(tol=solve_tol, max_sweeps=s.sweeps + 500, check_every=10)
-            log(f"nearness solve n={solve_n} {prec}: {s.sweeps} sweeps, "
+            r, ok = s.solve(tol=solve_tol, max_sweeps=s.sweeps + 500, check_every=10, sparse=sp)
+            log(f"nearness solve n={solve_n} {prec}{' sparse' if sp else ''}: {s.sweeps} sweeps, "
                 f"max violation {r['max_viol']:.3e}")
         sec = time.perf_counter() - t0
         full = s.residuals()
-        res["solve"][prec] = {"seconds": sec, "sweeps": s.sweeps, "converged": ok,
+        key = prec + ("_sparse" if sp else "")
+        res["solve"][key] = {"seconds": sec, "sweeps": s.sweeps, "converged": ok,
                               "max_viol": full["max_viol"], "primal": full["primal"],
                               "rel_gap": full["gap"] / max(1.0, abs(full["primal"]))}
-        log(f"nearness solve n={solve_n} {prec}: {res['solve'][prec]}")
+        log(f"nearness solve n={solve_n} {key}: {res['solve'][key]}")
         del s
         torch.cuda.empty_cache()
     import oracle
@@ -371,9 +383,11 @@ def polish_report(config=2, b=16):
     Chung-Lu workload (exponent 2.5, mean degree 10, unit weights, gamma 5):
     one-shot solves to max violation 1e-6 (cc_solve_cc_lp, host arrays in and
     out), the FP32 phase alone to 1e-4, and the per-sweep time of each
-    precision.  Errors are against the FP64-only solution.  An untimed
-    one-sweep solve comes first: the first large device allocation after
-    torch has released its cache costs seconds once per process."""
+    precision.  Errors are against the FP64-only solution.  Each solve runs
+    with dense and with sparse dual access (CC_MODE_SPARSE; the same sweeps
+    and results).  An untimed one-sweep solve comes first: the first large
+    device allocation after torch has released its cache costs seconds once
+    per process."""
     import numpy as np
     import torch
     from paper_1901_10084_amd import ccproj as C
@@ -393,8 +407,10 @@ def polish_report(config=2, b=16):
     C.solve_cc_lp(inst.n, inst.w, inst.d, inst.gamma, tol=1e-6, b=b, mode=C.CC_MODE_F32_POLISH,
                   max_sweeps=1)
     runs = {}
-    for name, mode, tol in (("f64", C.CC_MODE_F64, 1e-6), ("f32_polish", C.CC_MODE_F32_POLISH, 1e-6),
-                            ("f32_only", C.CC_MODE_F32, 1e-4)):
+    modes = (("f64", C.CC_MODE_F64, 1e-6), ("f32_polish", C.CC_MODE_F32_POLISH, 1e-6),
+             ("f32_only", C.CC_MODE_F32, 1e-4))
+    modes += tuple((name + "_sparse", mode | C.CC_MODE_SPARSE, tol) for name, mode, tol in modes)
+    for name, mode, tol in modes:
         t0 = time.perf_counter()
         rc, x, _, info = C.solve_cc_lp(inst.n, inst.w, inst.d, inst.gamma, tol=tol, b=b, mode=mode)
         wall = time.perf_counter() - t0
