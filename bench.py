@@ -294,6 +294,51 @@ def sparse_report(cases=((3, 16, "f32"), (3, 16, "f64"), (4, 32, "f32")), settle
     return out
 
 
+def schedule_report(cases=((1, 16, "f64"), (3, 16, "f32")), tol=1e-4):
+    """Visiting orders (Sec. IV-E: the order changes the sweeps needed, not
+    the limit).  On the GPU: the paper's tiled schedule (dataflow executor)
+    against the sum-mod-n colouring (one launch per colour), per sweep (HIP
+    events around 5 sweeps after 2) and to max violation `tol` from the cold
+    start.  On the CPU: the oracle's sweeps to 1e-6 on the n = 60 workload in
+    the schedule, lexicographic and colour orders."""
+    import torch
+    import oracle
+    from paper_1901_10084_amd import ccproj as C
+    from paper_1901_10084_amd import instances as I
+    out = {"tol": tol, "gpu": []}
+    for config, b, prec in cases:
+        inst = I.workload(config)
+        row = {"workload": inst.name, "n": inst.n, "b": b, "prec": prec}
+        for name, make in (("schedule", lambda: C.Solver.from_instance(inst, b=b, prec=prec)),
+                           ("colour", lambda: C.ColourSolver.from_instance(inst, prec=prec))):
+            s = make()
+            s.sweep(2)
+            torch.cuda.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            s.sweep(5)
+            e1.record()
+            torch.cuda.synchronize()
+            ms = e0.elapsed_time(e1) / 5
+            s.init_cold()
+            torch.cuda.synchronize()
+            r, ok, sec = s.solve(tol=tol, max_sweeps=5000)
+            row[name] = {"ms_per_sweep": ms, "sweeps_to_tol": s.sweeps, "seconds_to_tol": sec,
+                         "converged": ok, "primal_qp": r["primal_qp"]}
+            log(f"schedule report n={inst.n} {prec} {name}: {row[name]}")
+            del s
+            torch.cuda.empty_cache()
+        out["gpu"].append(row)
+    inst = I.workload(0)
+    out["oracle_sweeps_to_1e-6_n60"] = {}
+    for order in ("schedule", "lex", "colour"):
+        o = oracle.State.from_instance(inst)
+        o.solve(tol=1e-6, b=8, max_sweeps=5000, order=order)
+        out["oracle_sweeps_to_1e-6_n60"][order] = o.sweeps
+    log(f"schedule report oracle n=60: {out['oracle_sweeps_to_1e-6_n60']}")
+    return out
+
+
 def nearness_report(n=2000, b=16, solve_n=500, solve_tol=1e-4, oracle_sweeps=3):
     """l2 metric nearness (Sec. II-A, p = 2) on noisy Euclidean distances (n
     points in the unit square, each distance times U[0.5, 1.5], weights
@@ -494,6 +539,8 @@ def main():
                          "violation <= 1e-4, on workload --warm-config (tile size 32)")
     ap.add_argument("--cpu-baseline-rows", action="store_true",
                     help="each step of the path on the GPU beside the oracle (n = 500)")
+    ap.add_argument("--schedule-report", action="store_true",
+                    help="the tiled schedule against the sum-mod-n colouring order")
     ap.add_argument("--sparse-report", action="store_true",
                     help="sparse dual access against the dense sweep at n = 2000 and 4000")
     ap.add_argument("--sparse", action="store_true",
@@ -644,6 +691,9 @@ def main():
 
     if args.sparse_report:
         out["sparse"] = sparse_report()
+
+    if args.schedule_report:
+        out["orders"] = schedule_report()
 
     if args.nearness_report:
         out["nearness"] = nearness_report()

@@ -182,6 +182,24 @@ int cc_sweep_sparse(cc_ctx *ctx, void *x, void *f, void *y, void *y_pair, const 
 /* One sparse sweep's metric rounds only (no pair pass). */
 int cc_sweep_metric_sparse(cc_ctx *ctx, void *x, void *y, const void *g, void *mask);
 
+/* Another visiting order: the sum-mod-n colouring.  Triplets that share a
+ * pair conflict (the colouring view of the related-work section); colour t
+ * holds every triplet i<j<k with i + j + k = t (mod n), and a pair fixes
+ * the third index of its colour, so a colour's triplets share no pair.  A
+ * sweep visits colours t = 0..n-1 in turn (one launch each; within a colour
+ * the order cannot matter), the three orientations of each triplet as in
+ * the schedule, then the pair pass.  Sec. IV-E: the order changes the
+ * iterates and the number of sweeps to a tolerance, not the limit.  Duals
+ * are in colex order (the layout of cc_duals_to_lex), y_lex:
+ * cc_num_metric_duals(n) elements in the context's precision; the context's
+ * b is not used.  g, d as for cc_sweep.  Enqueues only. */
+int cc_sweep_colour(cc_ctx *ctx, void *x, void *f, void *y_lex, void *y_pair, const void *g,
+                    const uint8_t *d, int32_t nsweeps);
+
+/* Cold start for cc_sweep_colour: as cc_init_cold, with the metric duals
+ * in colex order (cc_num_metric_duals(n) zeros). */
+int cc_init_cold_lex(cc_ctx *ctx, void *x, void *f, void *y_lex, void *y_pair, double gamma);
+
 /* Diagnostic: one dataflow metric sweep (b = 8, 16, 32) with a time
  * breakdown summed over all workgroups, in microseconds: out[0] waiting for
  * the blocks a tile step needs, out[1] loading them into LDS, out[2] the

@@ -67,6 +67,10 @@ def lib():
         L = ctypes.CDLL(_LIB)
         L.orc_schedule.argtypes = [_i64, _i64, _p, _i64]
         L.orc_schedule.restype = _i64
+        L.orc_colour_order.argtypes = [_i64, _p, _i64]
+        L.orc_colour_order.restype = _i64
+        L.orc_sweeps_list.argtypes = [_i64, _dbl, _p, _p, _p, _p, _p, _p, _i32, _p, _i64]
+        L.orc_sweeps_list.restype = ctypes.c_int
         L.orc_init_cold.argtypes = [_i64, _dbl, _p, _p, _p, _p, _p]
         L.orc_init_cold.restype = None
         L.orc_sweeps.argtypes = [_i64, _i64, _dbl, _p, _p, _p, _p, _p, _p, _i32, _i32]
@@ -93,6 +97,17 @@ def lib():
 
 def _ptr(a):
     return None if a is None else a.ctypes.data
+
+
+# visiting orders of the metric rows: the tiled schedule (Sec. III-B/C),
+# plain lexicographic order, the sum-mod-n colouring
+ORDERS = {"schedule": 0, "lex": 1, "colour": 2}
+
+
+def _order(order):
+    if order not in ORDERS:
+        raise ValueError(f"unknown order {order!r}")
+    return ORDERS[order]
 
 
 def _f64(a):
@@ -138,7 +153,17 @@ class State:
         assert self.y is not None
         rc = lib().orc_sweeps(self.n, int(b), self.gamma, _ptr(self.w), _ptr(self.d),
                               _ptr(self.x), _ptr(self.f), _ptr(self.y), _ptr(self.y_pair),
-                              int(nsweeps), 0 if order == "schedule" else 1)
+                              int(nsweeps), _order(order))
+        if rc != 0:
+            raise ValueError("oracle sweep rejected its input")
+        self.sweeps += nsweeps
+
+    def sweep_list(self, triplets, nsweeps=1):
+        """Sweeps that visit the given (i, j, k) rows in the given order."""
+        tr = np.ascontiguousarray(triplets, dtype=np.int64).reshape(-1, 3)
+        rc = lib().orc_sweeps_list(self.n, self.gamma, _ptr(self.w), _ptr(self.d), _ptr(self.x),
+                                   _ptr(self.f), _ptr(self.y), _ptr(self.y_pair), int(nsweeps),
+                                   _ptr(tr), tr.shape[0])
         if rc != 0:
             raise ValueError("oracle sweep rejected its input")
         self.sweeps += nsweeps
@@ -180,6 +205,15 @@ def schedule(n: int, b: int) -> np.ndarray:
     got = lib().orc_schedule(n, b, _ptr(out), cnt)
     assert got == cnt, (got, cnt)
     return out[:cnt]
+
+
+def colour_order(n: int) -> np.ndarray:
+    """The sum-mod-n colouring's visiting order as rows (i, j, k, colour)."""
+    cnt = num_triplets(n)
+    out = np.zeros((max(cnt, 1), 7), dtype=np.int64)
+    got = lib().orc_colour_order(n, _ptr(out), cnt)
+    assert got == cnt, (got, cnt)
+    return out[:cnt, :4]
 
 
 def pair_pass(n, gamma, w, d, x, f, y_pair):
@@ -242,7 +276,7 @@ class Nearness:
 
     def sweep(self, nsweeps=1, b=8, order="schedule"):
         rc = lib().orc_nearness_sweeps(self.n, int(b), _ptr(self.w), _ptr(self.x), _ptr(self.y),
-                                       int(nsweeps), 0 if order == "schedule" else 1)
+                                       int(nsweeps), _order(order))
         if rc != 0:
             raise ValueError("oracle sweep rejected its input")
         self.sweeps += nsweeps

@@ -18,6 +18,12 @@
  *                   projection step and a dual update, visiting constraints
  *                   cyclically;
  *   visiting order: the tiled block-diagonal schedule of Sec. III-B/C.
+ * Other visiting orders (Sec. IV-E: the order changes the iteration count,
+ * not the limit): plain lexicographic order, and the sum-mod-n colouring
+ * (the colouring view of the related-work section: triplets that share a
+ * pair conflict; colour t = every triplet with i + j + k = t (mod n), in
+ * which a pair fixes the third index, so no two triplets of a colour share
+ * a pair), colours t = 0..n-1 in turn.
  * Also the l2 metric nearness problem (Sec. II-A, p = 2) on the same metric
  * rows and schedule, at the end of this file.
  *
@@ -106,6 +112,21 @@ static void visit_lex(int64_t n, visit_fn fn, void *ctx)
                 fn(ctx, i, j, k, 0, 0, 0, 0);
 }
 
+/* Sum-mod-n colouring: colours t = 0, 1, ..., n-1 in turn; inside a colour
+ * the triplets go by (i, j) lexicographically, the third index being
+ * k = (t - i - j) mod n, taken when k > j (so each triplet is visited once,
+ * from its two smallest indices).  The triplets of a colour share no pair,
+ * so their order inside the colour cannot change the result. */
+static void visit_colour(int64_t n, visit_fn fn, void *ctx)
+{
+    for (int64_t t = 0; t < n; t++)
+        for (int64_t i = 0; i < n; i++)
+            for (int64_t j = i + 1; j < n; j++) {
+                int64_t k = ((t - i - j) % n + n) % n;
+                if (k > j) fn(ctx, i, j, k, t, 0, 0, 0);
+            }
+}
+
 /* Enumerate the schedule into arrays (small n only, for schedule tests).
  * Each output row: i, j, k, round, P, J, t.  Returns the number of rows. */
 int64_t orc_schedule(int64_t n, int64_t b, int64_t *out, int64_t cap);
@@ -126,6 +147,14 @@ int64_t orc_schedule(int64_t n, int64_t b, int64_t *out, int64_t cap)
 {
     struct enum_ctx e = { out, cap, 0 };
     visit_schedule(n, b, -1, enum_visit, &e);
+    return e.cnt;
+}
+
+/* The colour order into arrays, rows (i, j, k, colour, 0, 0, 0). */
+int64_t orc_colour_order(int64_t n, int64_t *out, int64_t cap)
+{
+    struct enum_ctx e = { out, cap, 0 };
+    visit_colour(n, enum_visit, &e);
     return e.cnt;
 }
 
@@ -249,7 +278,8 @@ void orc_init_cold(int64_t n, double gamma, const double *w, double *x, double *
 }
 
 /* nsweeps full sweeps.  order 0: the tiled schedule with tile size b;
- * order 1: plain lexicographic order.  Returns 0, or -1 on bad input. */
+ * order 1: plain lexicographic order; order 2: the sum-mod-n colouring.
+ * Returns 0, or -1 on bad input. */
 int orc_sweeps(int64_t n, int64_t b, double gamma, const double *w, const uint8_t *d,
                double *x, double *f, double *y, double *y_pair, int32_t nsweeps,
                int32_t order)
@@ -264,8 +294,36 @@ int orc_sweeps(int64_t n, int64_t b, double gamma, const double *w, const uint8_
     for (int32_t s = 0; s < nsweeps; s++) {
         if (n >= 3) {
             if (order == 0) visit_schedule(n, b, -1, metric_visit, &c);
-            else visit_lex(n, metric_visit, &c);
+            else if (order == 1) visit_lex(n, metric_visit, &c);
+            else visit_colour(n, metric_visit, &c);
         }
+        pair_pass(np, gamma, r, d, x, f, y_pair);
+    }
+    free(r);
+    return 0;
+}
+
+/* nsweeps sweeps that visit the given triplets (count rows i, j, k with
+ * i < j < k < n) in the given order, then the pair pass.  For checks that
+ * the result depends only on the order of conflicting triplets. */
+int orc_sweeps_list(int64_t n, double gamma, const double *w, const uint8_t *d, double *x,
+                    double *f, double *y, double *y_pair, int32_t nsweeps,
+                    const int64_t *trip, int64_t count)
+{
+    if (n < 2 || !(gamma > 0.0)) return -1;
+    for (int64_t e = 0; e < count; e++)
+        if (!(0 <= trip[3 * e] && trip[3 * e] < trip[3 * e + 1] &&
+              trip[3 * e + 1] < trip[3 * e + 2] && trip[3 * e + 2] < n))
+            return -1;
+    int64_t np = orc_num_pairs(n);
+    double *r = inverse_weights(np, w);
+    if (!r) return -1;
+    sweep_ctx c;
+    memset(&c, 0, sizeof(c));
+    c.n = n; c.gamma = gamma; c.r = r; c.x = x; c.y = y;
+    for (int32_t s = 0; s < nsweeps; s++) {
+        for (int64_t e = 0; e < count; e++)
+            metric_visit(&c, trip[3 * e], trip[3 * e + 1], trip[3 * e + 2], 0, 0, 0, 0);
         pair_pass(np, gamma, r, d, x, f, y_pair);
     }
     free(r);
@@ -453,7 +511,8 @@ void orc_nearness_init(int64_t n, const double *dv, double *x, double *y)
 }
 
 /* nsweeps sweeps (order 0: tiled schedule with tile size b; 1: plain
- * lexicographic order).  Returns 0, or -1 on bad input. */
+ * lexicographic order; 2: the sum-mod-n colouring).  Returns 0, or -1 on
+ * bad input. */
 int orc_nearness_sweeps(int64_t n, int64_t b, const double *w, double *x, double *y,
                         int32_t nsweeps, int32_t order)
 {
@@ -466,7 +525,8 @@ int orc_nearness_sweeps(int64_t n, int64_t b, const double *w, double *x, double
     c.n = n; c.gamma = 1.0; c.r = r; c.x = x; c.y = y;
     for (int32_t s = 0; s < nsweeps && n >= 3; s++) {
         if (order == 0) visit_schedule(n, b, -1, metric_visit, &c);
-        else visit_lex(n, metric_visit, &c);
+        else if (order == 1) visit_lex(n, metric_visit, &c);
+        else visit_colour(n, metric_visit, &c);
     }
     free(r);
     return 0;

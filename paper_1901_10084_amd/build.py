@@ -7,7 +7,7 @@ import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
-SOURCES = ["sweep.hip", "resid.hip", "dataflow.hip", "mlp.hip", "capi.hip"]
+SOURCES = ["sweep.hip", "resid.hip", "dataflow.hip", "colour.hip", "mlp.hip", "capi.hip"]
 LIB = os.path.join(HERE, "libccproj.so")
 
 HIPCC_FLAGS = [

@@ -92,6 +92,8 @@ _sig("cc_dual_mask_bytes", _i64, _p)
 _sig("cc_dual_mask_build", ctypes.c_int, _p, _p, _p)
 _sig("cc_sweep_sparse", ctypes.c_int, _p, _p, _p, _p, _p, _p, _p, _p, _i32)
 _sig("cc_sweep_metric_sparse", ctypes.c_int, _p, _p, _p, _p, _p)
+_sig("cc_sweep_colour", ctypes.c_int, _p, _p, _p, _p, _p, _p, _p, _i32)
+_sig("cc_init_cold_lex", ctypes.c_int, _p, _p, _p, _p, _p, _dbl)
 _sig("cc_nearness_residuals", ctypes.c_int, _p, _p, _p, _p, _p, _i32, ctypes.POINTER(NResid))
 
 _sig("cc_mlp_num_params", _i32)
@@ -113,7 +115,8 @@ EXPORTS = ["cc_last_error", "cc_num_metric_duals", "cc_create", "cc_destroy", "c
            "cc_pair_pass", "cc_residuals", "cc_x_from_y", "cc_duals_to_lex", "cc_slots_to_lex",
            "cc_dataflow_tables", "cc_widen", "cc_narrow", "cc_solve_cc_lp",
            "cc_nearness_init", "cc_nearness_residuals", "cc_dual_mask_bytes",
-           "cc_dual_mask_build", "cc_sweep_sparse", "cc_sweep_metric_sparse"]
+           "cc_dual_mask_build", "cc_sweep_sparse", "cc_sweep_metric_sparse", "cc_sweep_colour",
+           "cc_init_cold_lex"]
 
 
 class CCError(RuntimeError):
@@ -411,6 +414,60 @@ class Solver:
             if max(r["max_viol_metric"], r["max_viol_pair"]) <= tol:
                 return self.residuals(), True, time.perf_counter() - t0
         return self.residuals(), False, time.perf_counter() - t0
+
+
+class ColourSolver:
+    """Device state for the sum-mod-n colouring order (cc_sweep_colour): w,
+    d, g, x, f, y_pair as in Solver, the metric duals y in colex order."""
+
+    def __init__(self, n, w, d, gamma, prec="f64", device="cuda", stream=None):
+        if not torch.cuda.is_available():
+            raise RuntimeError("ccproj needs a ROCm GPU; none is visible")
+        self.n, self.gamma, self.prec = int(n), float(gamma), prec
+        self.ctx = Context(self.n, 16, prec, stream)
+        dt = self.ctx.dtype
+        npairs = self.n * (self.n - 1) // 2
+        self.w = torch.as_tensor(np.ascontiguousarray(w, dtype=np.float64)).to(device)
+        self.d = torch.as_tensor(np.ascontiguousarray(d, dtype=np.uint8)).to(device)
+        self.g = torch.empty(npairs, dtype=dt, device=device)
+        self.x = torch.empty(npairs, dtype=dt, device=device)
+        self.f = torch.empty(npairs, dtype=dt, device=device)
+        self.y = torch.empty(num_metric_duals(self.n), dtype=dt, device=device)
+        self.y_pair = torch.empty(2 * npairs, dtype=dt, device=device)
+        self.ctx.prepare(self.w, self.gamma, self.g)
+        self.init_cold()
+
+    @classmethod
+    def from_instance(cls, inst, **kw):
+        return cls(inst.n, inst.w, inst.d, inst.gamma, **kw)
+
+    def init_cold(self):
+        check(_L.cc_init_cold_lex(self.ctx.handle, _ptr(self.x), _ptr(self.f), _ptr(self.y),
+                                  _ptr(self.y_pair), self.gamma))
+        self.sweeps = 0
+
+    def sweep(self, nsweeps=1):
+        check(_L.cc_sweep_colour(self.ctx.handle, _ptr(self.x), _ptr(self.f), _ptr(self.y),
+                                 _ptr(self.y_pair), _ptr(self.g), _ptr(self.d), int(nsweeps)))
+        self.sweeps += nsweeps
+
+    def residuals(self):
+        """Max violations and the primal objective (the dual terms need the
+        schedule-ordered duals and are not offered here)."""
+        return self.ctx.residuals(self.x, self.f, None, None, self.w, self.d, self.gamma,
+                                  CC_RESID_VIOL)
+
+    def solve(self, tol=1e-6, max_sweeps=100000, check_every=None):
+        if check_every is None:
+            check_every = 1 if self.n <= 1000 else 5
+        t0 = time.perf_counter()
+        r = None
+        while self.sweeps < max_sweeps:
+            self.sweep(min(check_every, max_sweeps - self.sweeps))
+            r = self.residuals()
+            if max(r["max_viol_metric"], r["max_viol_pair"]) <= tol:
+                return r, True, time.perf_counter() - t0
+        return r, False, time.perf_counter() - t0
 
 
 class NearnessSolver:

@@ -60,6 +60,7 @@ void build_dataflow_tables(int64_t n, int b, std::vector<DTile> &tiles, std::vec
                            std::vector<uint32_t> &K);
 template <typename T> int launch_sweep_dataflow(const DataflowArgs &, int, int, int64_t, T *, const T *, T *, void *, hipStream_t);
 template <typename T> int launch_mask_build(int, int64_t, const T *, void *, hipStream_t);
+template <typename T> int launch_sweep_colour(int64_t, T *, const T *, T *, hipStream_t);
 template <typename T> int dataflow_occupancy(int, int *);
 template <typename T> int launch_aty_dataflow(const DataflowArgs &, int, int, int64_t, const T *, double *, hipStream_t);
 template <typename T> int aty_dataflow_occupancy(int, int *);
@@ -596,6 +597,43 @@ int cc_sweep_metric_sparse(cc_ctx *c, void *x, void *y, const void *g, void *mas
     if (c->prec == CC_F64)
         return sweep_metric_t<double>(c, (double *)x, (double *)y, (const double *)g, CC_EXEC_DATAFLOW, nullptr, mask);
     return sweep_metric_t<float>(c, (float *)x, (float *)y, (const float *)g, CC_EXEC_DATAFLOW, nullptr, mask);
+}
+
+int cc_init_cold_lex(cc_ctx *c, void *x, void *f, void *y_lex, void *yp, double gamma) {
+    int rc;
+    if ((rc = check_ctx(c)) || (rc = need(x, "x")) || (rc = need(f, "f")) || (rc = need(y_lex, "y_lex")) ||
+        (rc = need(yp, "y_pair")))
+        return rc;
+    if (!(gamma > 0.0) || !std::isfinite(gamma)) return fail(CC_EINVAL, "gamma must be finite and > 0");
+    const int64_t np = num_pairs(c->n), nm = cc_num_metric_duals(c->n);
+    if (c->prec == CC_F64)
+        return launch_init_cold<double>(np, nm, (double *)x, (double *)f, (double *)y_lex, (double *)yp, gamma,
+                                        c->stream);
+    return launch_init_cold<float>(np, nm, (float *)x, (float *)f, (float *)y_lex, (float *)yp, gamma, c->stream);
+}
+
+int cc_sweep_colour(cc_ctx *c, void *x, void *f, void *y_lex, void *yp, const void *g, const uint8_t *d,
+                    int32_t nsweeps) {
+    int rc;
+    if ((rc = check_ctx(c)) || (rc = need(x, "x")) || (rc = need(f, "f")) || (rc = need(y_lex, "y_lex")) ||
+        (rc = need(yp, "y_pair")) || (rc = need(g, "g")) || (rc = need(d, "d")))
+        return rc;
+    if (nsweeps < 0) return fail(CC_EINVAL, "nsweeps must be >= 0");
+    const int64_t np = num_pairs(c->n);
+    for (int s = 0; s < nsweeps; ++s) {
+        if (c->prec == CC_F64) {
+            if ((rc = launch_sweep_colour<double>(c->n, (double *)x, (const double *)g, (double *)y_lex, c->stream)) ||
+                (rc = launch_pair_pass<double>(np, (double *)x, (double *)f, (double *)yp, (const double *)g, d,
+                                               c->stream)))
+                return rc;
+        } else {
+            if ((rc = launch_sweep_colour<float>(c->n, (float *)x, (const float *)g, (float *)y_lex, c->stream)) ||
+                (rc = launch_pair_pass<float>(np, (float *)x, (float *)f, (float *)yp, (const float *)g, d,
+                                              c->stream)))
+                return rc;
+        }
+    }
+    return CC_OK;
 }
 
 int cc_dataflow_breakdown(cc_ctx *c, void *x, void *y, const void *g, double *out) {
