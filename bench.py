@@ -241,6 +241,21 @@ def cpu_baseline_rows(config=1, b=16, mlp_sample=200_000, batch=8192):
     phi_h, tgt_h = phi.double().cpu().numpy(), tgt.double().cpu().numpy()
     put(f"a9 training step (batch {batch})", gpu(lambda: net.train_step(phi, tgt, lr=0.0)),
         cpu(lambda: M.loss_and_grad(p, phi_h, tgt_h)))
+    # the NEXT rows on the same instance: the sparse sweep gives the dense
+    # sweep's bits, so its oracle is the oracle's sweep; the colour order
+    # against the oracle's colour order
+    sp = C.Solver.from_instance(inst, b=b, prec="f64")
+    sp.sweep(2)
+    sp.sweep(1, sparse=True)
+    put("NEXT-1 sparse sweep (Sec. III-D)", gpu(lambda: sp.sweep(1, sparse=True)),
+        cpu(lambda: o.sweep(1, b=b)), "oracle: its sweep (the sparse sweep's results are the dense sweep's)")
+    del sp
+    cs = C.ColourSolver.from_instance(inst, prec="f64")
+    oc = oracle.State.from_instance(inst)
+    cs.sweep(2)
+    oc.sweep(2, order="colour")
+    put("NEXT-2 colour-order sweep", gpu(lambda: cs.sweep(1)), cpu(lambda: oc.sweep(1, order="colour")))
+    del cs
     put("a2 cold init", gpu(s.init_cold), cpu(o.init_cold))
     return {"workload": inst.name, "n": inst.n, "b": b, "prec": "f64", "rows": rows}
 
