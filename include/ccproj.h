@@ -360,7 +360,11 @@ int cc_warm_start_mlp(cc_ctx *ctx, const float *params, const float *deg, const 
 
 /* One-shot solve from host arrays (allocates its own device buffers).
  * w_host: double[N_p] > 0; d_host: uint8[N_p]; tol: stop when both max
- * violations are <= tol; mode: CC_MODE_F64, CC_MODE_F32 (FP32 sweeps to tol)
+ * violations are <= tol and, if gap_tol > 0, also the duality gap (Sec.
+ * IV-D stops on constraint satisfaction and the gap) |primal - dual| <=
+ * gap_tol max(1, |primal|) (evaluated in FP64, with A'y, only once the
+ * violations are below tol; gap_tol <= 0: violations only); mode:
+ * CC_MODE_F64, CC_MODE_F32 (FP32 sweeps to tol)
  * or CC_MODE_F32_POLISH (FP32 sweeps to max(tol, 1e-4), then duals widened,
  * x recomputed from them in FP64 and FP64 sweeps to tol), or-ed with
  * CC_MODE_SPARSE for sparse dual access (b = 8, 16, 32; same results, the
@@ -371,7 +375,8 @@ int cc_warm_start_mlp(cc_ctx *ctx, const float *params, const float *deg, const 
  * y_lex_out_host: double[3 C(n,3)] or NULL.  Returns CC_OK, CC_ENOTCONV
  * (info filled, outputs written), or an error. */
 int cc_solve_cc_lp(int64_t n, const double *w_host, const uint8_t *d_host, double gamma,
-                   double tol, int32_t max_sweeps, int32_t b, int32_t mode, int32_t warm,
+                   double tol, double gap_tol, int32_t max_sweeps, int32_t b, int32_t mode,
+                   int32_t warm,
                    const float *mlp_weights_host, const float *deg_host,
                    double *x_out_host, double *y_lex_out_host, cc_info *info);
 

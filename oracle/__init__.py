@@ -188,12 +188,16 @@ class State:
                            _ptr(self.y_pair), _ptr(x), _ptr(f))
         return x, f
 
-    def solve(self, tol=1e-6, b=8, max_sweeps=100000, check_every=1, order="schedule"):
-        """Sweep until the max constraint violation is at most tol."""
+    def solve(self, tol=1e-6, b=8, max_sweeps=100000, check_every=1, order="schedule",
+              gap_tol=None):
+        """Sweep until the max constraint violation is at most tol and, with
+        gap_tol, the duality gap is at most gap_tol * max(1, |primal|)
+        (Sec. IV-D stops on constraint satisfaction and the gap)."""
         while self.sweeps < max_sweeps:
             self.sweep(check_every, b=b, order=order)
             r = self.residuals()
-            if max(r["max_viol_metric"], r["max_viol_pair"]) <= tol:
+            if max(r["max_viol_metric"], r["max_viol_pair"]) <= tol and (
+                    gap_tol is None or abs(r["gap"]) <= gap_tol * max(1.0, abs(r["primal_qp"]))):
                 return r
         return self.residuals()
 

@@ -84,7 +84,7 @@ _sig("cc_duals_to_lex", ctypes.c_int, _p, _p, _p)
 _sig("cc_slots_to_lex", ctypes.c_int, _p, _p, _i64, _p)
 _sig("cc_dataflow_tables", ctypes.c_int, _i64, _i32, _p, _p, _p, _p, _p, _p, _p, _p)
 _sig("cc_widen", ctypes.c_int, _p, _p, _i64, _p)
-_sig("cc_solve_cc_lp", ctypes.c_int, _i64, _p, _p, _dbl, _dbl, _i32, _i32, _i32, _i32, _p, _p,
+_sig("cc_solve_cc_lp", ctypes.c_int, _i64, _p, _p, _dbl, _dbl, _dbl, _i32, _i32, _i32, _i32, _p, _p,
      _p, _p, ctypes.POINTER(Info))
 _sig("cc_narrow", ctypes.c_int, _p, _p, _i64, _p)
 _sig("cc_nearness_init", ctypes.c_int, _p, _p, _p, _p)
@@ -276,7 +276,7 @@ def dataflow_tables(n: int, b: int) -> dict:
 
 
 def solve_cc_lp(n, w, d, gamma, tol=1e-6, max_sweeps=100000, b=16, mode=CC_MODE_F64,
-                mlp_weights=None, deg=None, want_duals=False):
+                mlp_weights=None, deg=None, want_duals=False, gap_tol=0.0):
     """One-shot solve from host arrays (cc_solve_cc_lp).  Returns
     (status, x, y_lex or None, info dict)."""
     w = np.ascontiguousarray(w, dtype=np.float64)
@@ -288,7 +288,7 @@ def solve_cc_lp(n, w, d, gamma, tol=1e-6, max_sweeps=100000, b=16, mode=CC_MODE_
     dg = None if deg is None else np.ascontiguousarray(deg, dtype=np.float32)
     info = Info()
     rc = _L.cc_solve_cc_lp(int(n), w.ctypes.data, d.ctypes.data, float(gamma), float(tol),
-                           int(max_sweeps), int(b), int(mode), int(warm),
+                           float(gap_tol), int(max_sweeps), int(b), int(mode), int(warm),
                            None if mw is None else mw.ctypes.data,
                            None if dg is None else dg.ctypes.data, x.ctypes.data,
                            None if ylex is None else ylex.ctypes.data, ctypes.byref(info))
@@ -398,11 +398,13 @@ class Solver:
         self.ctx.duals_to_lex(self.y, y_lex)
         return y_lex
 
-    def solve(self, tol=1e-6, max_sweeps=100000, check_every=None, executor=None, sparse=False):
-        """Sweep until both max violations are <= tol, checked every
-        `check_every` sweeps (default as in cc_solve_cc_lp: every sweep up to
-        n = 1000, every 5 above; a check reads every triplet).  Returns
-        (residuals, converged, seconds)."""
+    def solve(self, tol=1e-6, max_sweeps=100000, check_every=None, executor=None, sparse=False,
+              gap_tol=None):
+        """Sweep until both max violations are <= tol (and, with gap_tol,
+        the relative duality gap is <= gap_tol), checked every `check_every`
+        sweeps (default as in cc_solve_cc_lp: every sweep up to n = 1000,
+        every 5 above; a check reads every triplet).  Returns (residuals,
+        converged, seconds)."""
         if check_every is None:
             check_every = 1 if self.n <= 1000 else 5
         t0 = time.perf_counter()
@@ -412,7 +414,9 @@ class Solver:
             self.sweep(k, executor, sparse)
             r = self.residuals(CC_RESID_VIOL)
             if max(r["max_viol_metric"], r["max_viol_pair"]) <= tol:
-                return self.residuals(), True, time.perf_counter() - t0
+                full = self.residuals()
+                if gap_tol is None or abs(full["gap"]) <= gap_tol * max(1.0, abs(full["primal_qp"])):
+                    return full, True, time.perf_counter() - t0
         return self.residuals(), False, time.perf_counter() - t0
 
 

@@ -995,12 +995,15 @@ struct CtxGuard {
     ~CtxGuard() { cc_destroy(c); }
 };
 
-// Sweeps until both max violations are <= tol or max_sweeps is reached;
-// returns CC_OK or CC_ENOTCONV, *done = sweeps run.  sparse: sparse dual
-// access, with a mask built from y here (nothing else writes y meanwhile).
+// Sweeps until both max violations are <= tol (and, with gap_tol > 0, the
+// relative duality gap is <= gap_tol) or max_sweeps is reached; returns
+// CC_OK or CC_ENOTCONV, *done = sweeps run.  The gap needs A'y, so it is
+// evaluated only at checks whose violations already pass.  sparse: sparse
+// dual access, with a mask built from y here (nothing else writes y
+// meanwhile).
 int sweep_to_tol(cc_ctx *c, void *x, void *f, void *y, void *yp, void *g, const uint8_t *d,
-                 const double *w, double gamma, double tol, int max_sweeps, int *done,
-                 cc_resid *r, bool sparse) {
+                 const double *w, double gamma, double tol, double gap_tol, int max_sweeps,
+                 int *done, cc_resid *r, bool sparse) {
     const int every = c->n <= 1000 ? 1 : 5;
     const int exec = (c->b == 8 || c->b == 16 || c->b == 32) ? CC_EXEC_DATAFLOW : CC_EXEC_ROUNDS;
     DevBuf mask;
@@ -1019,7 +1022,12 @@ int sweep_to_tol(cc_ctx *c, void *x, void *f, void *y, void *yp, void *g, const 
         *done += k;
         rc = cc_residuals(c, x, f, nullptr, nullptr, w, d, gamma, CC_RESID_VIOL, r);
         if (rc) return rc;
-        if (std::fmax(r->max_viol_metric, r->max_viol_pair) <= tol) return CC_OK;
+        if (std::fmax(r->max_viol_metric, r->max_viol_pair) <= tol) {
+            if (!(gap_tol > 0.0)) return CC_OK;
+            rc = cc_residuals(c, x, f, y, yp, w, d, gamma, CC_RESID_VIOL | CC_RESID_DUAL, r);
+            if (rc) return rc;
+            if (std::fabs(r->gap) <= gap_tol * std::fmax(1.0, std::fabs(r->primal_qp))) return CC_OK;
+        }
     }
     return CC_ENOTCONV;
 }
@@ -1027,8 +1035,8 @@ int sweep_to_tol(cc_ctx *c, void *x, void *f, void *y, void *yp, void *g, const 
 }  // namespace
 
 extern "C" int cc_solve_cc_lp(int64_t n, const double *w_host, const uint8_t *d_host,
-                              double gamma, double tol, int32_t max_sweeps, int32_t b,
-                              int32_t mode, int32_t warm, const float *mlp_weights_host,
+                              double gamma, double tol, double gap_tol, int32_t max_sweeps,
+                              int32_t b, int32_t mode, int32_t warm, const float *mlp_weights_host,
                               const float *deg_host, double *x_out_host,
                               double *y_lex_out_host, cc_info *info) {
     const auto t0 = std::chrono::steady_clock::now();
@@ -1036,6 +1044,7 @@ extern "C" int cc_solve_cc_lp(int64_t n, const double *w_host, const uint8_t *d_
     if (n < 3) return fail(CC_EINVAL, "n must be at least 3");
     if (!(gamma > 0.0) || !std::isfinite(gamma)) return fail(CC_EINVAL, "gamma must be > 0");
     if (!(tol > 0.0)) return fail(CC_EINVAL, "tol must be > 0");
+    if (std::isnan(gap_tol)) return fail(CC_EINVAL, "gap_tol must not be NaN");
     if (max_sweeps < 1) return fail(CC_EINVAL, "max_sweeps must be >= 1");
     const bool sparse = (mode & CC_MODE_SPARSE) != 0;
     mode &= ~CC_MODE_SPARSE;
@@ -1091,7 +1100,10 @@ extern "C" int cc_solve_cc_lp(int64_t n, const double *w_host, const uint8_t *d_
             info->warm_accepted = acc;
         }
         const double tol32 = (mode == CC_MODE_F32_POLISH) ? std::fmax(tol, 1e-4) : tol;
-        status = sweep_to_tol(c32.c, x32.p, f32b.p, y32.p, yp32.p, g32.p, d, w, gamma, tol32,
+        // the FP32 phase of the polish stops on the violations alone; the
+        // FP64 phase applies the gap test
+        const double gap32 = (mode == CC_MODE_F32_POLISH) ? 0.0 : gap_tol;
+        status = sweep_to_tol(c32.c, x32.p, f32b.p, y32.p, yp32.p, g32.p, d, w, gamma, tol32, gap32,
                               max_sweeps, &done, &r, sparse);
         if (status < 0) return status;
         info->sweeps = info->sweeps_f32 = done;
@@ -1131,7 +1143,7 @@ extern "C" int cc_solve_cc_lp(int64_t n, const double *w_host, const uint8_t *d_
         const int left = max_sweeps - info->sweeps;
         if (left > 0) {
             status = sweep_to_tol(c64.c, x64.p, f64b.p, y64.p, yp64.p, g64.p, d, w, gamma, tol,
-                                  left, &done, &r, sparse);
+                                  gap_tol, left, &done, &r, sparse);
             if (status < 0) return status;
             info->sweeps += done;
         } else {

@@ -308,6 +308,27 @@ def test_solve_modes():
           ip["sweeps"], flush=True)
 
 
+def test_solve_gap_tolerance():
+    """Stop on max violation and the relative duality gap: the one-shot solve
+    and the Solver take the oracle's sweep count under the same test, and
+    the gap they stop at meets the bound."""
+    inst = I.workload(0)
+    o = oracle.State.from_instance(inst)
+    ro = o.solve(tol=1e-6, b=8, max_sweeps=5000, gap_tol=1e-10)
+    _, _, _, iv = C.solve_cc_lp(inst.n, inst.w, inst.d, inst.gamma, tol=1e-6, b=8)
+    rc, x, _, ig = C.solve_cc_lp(inst.n, inst.w, inst.d, inst.gamma, tol=1e-6, b=8, gap_tol=1e-10)
+    assert rc == C.CC_OK and ig["sweeps"] == o.sweeps >= iv["sweeps"]
+    r = ig["resid"]
+    assert abs(r["gap"]) <= 1e-10 * max(1.0, abs(r["primal_qp"]))
+    assert rel_err(x, o.x) <= TOL64
+    g = C.Solver.from_instance(inst, b=8)
+    rg, ok, _ = g.solve(tol=1e-6, gap_tol=1e-10, max_sweeps=5000)
+    assert ok and g.sweeps == o.sweeps
+    with pytest.raises(C.CCError):
+        C.solve_cc_lp(inst.n, inst.w, inst.d, inst.gamma, tol=1e-6, b=8, gap_tol=float("nan"))
+    print("sweeps: violation only", iv["sweeps"], "with the gap", ig["sweeps"], flush=True)
+
+
 def test_solve_not_converged_reports():
     inst = I.workload(0)
     rc, x, _, info = C.solve_cc_lp(inst.n, inst.w, inst.d, inst.gamma, tol=1e-12, b=8,
