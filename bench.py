@@ -557,7 +557,9 @@ def main():
     ap.add_argument("--schedule-report", action="store_true",
                     help="the tiled schedule against the sum-mod-n colouring order")
     ap.add_argument("--sparse-report", action="store_true",
-                    help="sparse dual access against the dense sweep at n = 2000 and 4000")
+                    help="sparse dual access against the dense sweep at n = 2000 and 4000 "
+                         "(runs by default unless --no-solve or --no-sparse)")
+    ap.add_argument("--no-sparse", action="store_true", help="skip the sparse dual access report")
     ap.add_argument("--sparse", action="store_true",
                     help="with --warm-report: repeat its solves with sparse dual access")
     ap.add_argument("--nearness-report", action="store_true",
@@ -704,8 +706,11 @@ def main():
     if args.cpu_baseline_rows:
         out["cpu_baseline_rows"] = cpu_baseline_rows()
 
-    if args.sparse_report:
-        out["sparse"] = sparse_report()
+    # sparse dual access against the dense sweep (part of the default line;
+    # its n = 4000 case is skipped with --no-large)
+    if args.sparse_report or not (args.no_solve or args.no_sparse):
+        out["sparse"] = sparse_report(cases=((3, 16, "f32"), (3, 16, "f64")) +
+                                      (() if args.no_large else ((4, 32, "f32"),)))
 
     if args.schedule_report:
         out["orders"] = schedule_report()
