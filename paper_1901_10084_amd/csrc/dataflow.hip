@@ -47,6 +47,14 @@ template <> struct MaskWord<32> { using type = uint32_t; };
 // of +0.0 (a -0.0 counts as nonzero), so an unmarked slot reads back exactly.
 __device__ __forceinline__ uint64_t dual_bits(double v) { return __builtin_bit_cast(uint64_t, v); }
 __device__ __forceinline__ uint64_t dual_bits(float v) { return __builtin_bit_cast(uint32_t, v); }
+// 1 if a dual's bits are not +0.0's, else 0 (no compare: a min of its words)
+__device__ __forceinline__ uint32_t nonzero01(double v) {
+    const uint64_t u = __builtin_bit_cast(uint64_t, v);
+    return __builtin_elementwise_min(uint32_t(u) | uint32_t(u >> 32), 1u);
+}
+__device__ __forceinline__ uint32_t nonzero01(float v) {
+    return __builtin_elementwise_min(__builtin_bit_cast(uint32_t, v), 1u);
+}
 
 // Masked dual accesses go through a buffer resource over the tile's dual
 // segment: an offset at or beyond its size (kOffNone) reads 0 and writes
@@ -296,13 +304,21 @@ k_sweep_dataflow(DataflowArgs a, int64_t n, T *__restrict__ x, const T *__restri
         T yq[D][3];
         // Sparse access: mw holds the mask words of the current step, mwn
         // those of the next step (loaded one step ahead), nm the new words.
+        // Two formulations of the mask arithmetic, chosen per tile size by
+        // measurement (b = 32: 8% faster with the lean one; b = 16: 2-4%
+        // slower with it): lean keeps the words complemented, pushes an
+        // offset out of range by shifting the complemented bit into bit 31,
+        // and forms a new bit as min(bits, 1); the other selects the offset
+        // and compares the bits with zero.
+        constexpr bool lean = (B == 32);
         uint32_t mw[3] = {0u, 0u, 0u}, mwn[3] = {0u, 0u, 0u}, nm[3] = {0u, 0u, 0u};
         auto mask_row = [&](int m) { return mask + (int64_t(tl.jsbase) + m) * 3 * bb; };
         auto load_mask = [&](int m) {
             const MW *r = mask_row(m);
-            mwn[0] = r[lane];
-            mwn[1] = r[lane + bb];
-            mwn[2] = r[lane + 2 * bb];
+            const uint32_t flip = lean ? ~0u : 0u;
+            mwn[0] = uint32_t(r[lane]) ^ flip;
+            mwn[1] = uint32_t(r[lane + bb]) ^ flip;
+            mwn[2] = uint32_t(r[lane + 2 * bb]) ^ flip;
         };
         // The tile's dual segment as a buffer (sparse access only; its size
         // stays below kOffNone, at most nb 3 b^3 elements).
@@ -314,10 +330,17 @@ k_sweep_dataflow(DataflowArgs a, int64_t n, T *__restrict__ x, const T *__restri
         const __amdgpu_buffer_rsrc_t yr = __builtin_amdgcn_make_buffer_rsrc(
             reinterpret_cast<void *>(yau), 0,
             __builtin_amdgcn_readfirstlane(int(int64_t(Q - P + 1) * b * ystep * int64_t(sizeof(T)))), kBufFlags);
-        // byte offset of dual (u, o) of this lane, kOffNone where mask bit t is clear
+        // byte offset of dual (u, o) of this lane, out of range (bit 31 set,
+        // above any tile's size) where mask bit t is clear
         auto boff = [&](int u, int t, int o) {
-            const uint32_t off = uint32_t((int64_t(u) * ystep + o * bb + int(lane)) * int64_t(sizeof(T)));
-            return ((mw[o] >> t) & 1u) ? off : kOffNone;
+            if constexpr (lean) {
+                const uint32_t off = uint32_t(int64_t(u) * ystep * int64_t(sizeof(T))) +
+                                     uint32_t((o * bb + int(lane)) * int(sizeof(T)));
+                return off | ((mw[o] << (31 - t)) & kOffNone);
+            } else {
+                const uint32_t off = uint32_t((int64_t(u) * ystep + o * bb + int(lane)) * int64_t(sizeof(T)));
+                return ((mw[o] >> t) & 1u) ? off : kOffNone;
+            }
         };
         // dual o of sub-step t of step m (flat sub-step u = m b + t)
         auto ld = [&](const T *p, int u, int t, int o) {
@@ -452,9 +475,15 @@ k_sweep_dataflow(DataflowArgs a, int64_t n, T *__restrict__ x, const T *__restri
                         if (b0 != dual_bits(yq[d][0])) buf_store(y0, yr, ou + l);
                         if (b1 != dual_bits(yq[d][1])) buf_store(y1, yr, ou + os + l);
                         if (b2 != dual_bits(yq[d][2])) buf_store(y2, yr, ou + 2 * os + l);
-                        nm[0] |= uint32_t(b0 != 0) << t;
-                        nm[1] |= uint32_t(b1 != 0) << t;
-                        nm[2] |= uint32_t(b2 != 0) << t;
+                        if constexpr (lean) {
+                            nm[0] |= nonzero01(y0) << t;
+                            nm[1] |= nonzero01(y1) << t;
+                            nm[2] |= nonzero01(y2) << t;
+                        } else {
+                            nm[0] |= uint32_t(b0 != 0) << t;
+                            nm[1] |= uint32_t(b1 != 0) << t;
+                            nm[2] |= uint32_t(b2 != 0) << t;
+                        }
                     } else {
                         __builtin_nontemporal_store(y0, &dst[lane]);
                         __builtin_nontemporal_store(y1, &dst[lane + bb]);
@@ -475,9 +504,10 @@ k_sweep_dataflow(DataflowArgs a, int64_t n, T *__restrict__ x, const T *__restri
             group(b - D, false);
             if constexpr (SP) {
                 MW *r = mask_row(m);
-                if (nm[0] != mw[0]) r[lane] = MW(nm[0]);
-                if (nm[1] != mw[1]) r[lane + bb] = MW(nm[1]);
-                if (nm[2] != mw[2]) r[lane + 2 * bb] = MW(nm[2]);
+                const uint32_t flip = lean ? ~0u : 0u;
+                if (MW(nm[0]) != MW(mw[0] ^ flip)) r[lane] = MW(nm[0]);
+                if (MW(nm[1]) != MW(mw[1] ^ flip)) r[lane + bb] = MW(nm[1]);
+                if (MW(nm[2]) != MW(mw[2] ^ flip)) r[lane + 2 * bb] = MW(nm[2]);
             }
             if (tid == 0 && a.prof) mark(2);
 
