@@ -83,6 +83,10 @@ def lib():
         L.orc_x_from_y.restype = ctypes.c_int
         L.orc_residuals.argtypes = [_i64, _dbl, _p, _p, _p, _p, _p, _p, ctypes.POINTER(Resid)]
         L.orc_residuals.restype = ctypes.c_int
+        L.orc_l1_sweeps.argtypes = [_i64, _i64, _dbl, _p, _p, _p, _p, _p, _p, _i32, _i32]
+        L.orc_l1_sweeps.restype = ctypes.c_int
+        L.orc_l1_residuals.argtypes = [_i64, _dbl, _p, _p, _p, _p, _p, _p, ctypes.POINTER(Resid)]
+        L.orc_l1_residuals.restype = ctypes.c_int
         L.orc_dual_objective.argtypes = [_i64, _dbl, _p, _p, _p, _p]
         L.orc_dual_objective.restype = _dbl
         L.orc_nearness_init.argtypes = [_i64, _p, _p, _p]
@@ -209,6 +213,41 @@ def schedule(n: int, b: int) -> np.ndarray:
     got = lib().orc_schedule(n, b, _ptr(out), cnt)
     assert got == cnt, (got, cnt)
     return out[:cnt]
+
+
+class L1Nearness(State):
+    """Oracle iterate of the l1 metric nearness problem: (mn1) with real
+    dissimilarities dv (Sec. II-A: min sum w |x - d| over metric x), solved
+    as (qp) by Algorithm 1 exactly as correlation clustering, whose d is
+    0/1.  x, f per pair; y colex metric duals; y_pair per pair row."""
+
+    def __init__(self, n, gamma, w, dv):
+        self.dv = _f64(dv)
+        super().__init__(n, gamma, w, np.zeros(num_pairs(int(n)), dtype=np.uint8))
+        assert self.dv.shape == self.w.shape
+
+    def sweep(self, nsweeps=1, b=8, order="schedule"):
+        rc = lib().orc_l1_sweeps(self.n, int(b), self.gamma, _ptr(self.w), _ptr(self.dv),
+                                 _ptr(self.x), _ptr(self.f), _ptr(self.y), _ptr(self.y_pair),
+                                 int(nsweeps), _order(order))
+        if rc != 0:
+            raise ValueError("oracle sweep rejected its input")
+        self.sweeps += nsweeps
+
+    def residuals(self) -> dict:
+        out = Resid()
+        rc = lib().orc_l1_residuals(self.n, self.gamma, _ptr(self.w), _ptr(self.dv), _ptr(self.x),
+                                    _ptr(self.f), _ptr(self.y), _ptr(self.y_pair),
+                                    ctypes.byref(out))
+        if rc != 0:
+            raise MemoryError
+        return out.as_dict()
+
+    def sweep_list(self, triplets, nsweeps=1):
+        raise NotImplementedError("explicit visit lists are offered for 0/1 d only")
+
+    def dual_objective(self) -> float:
+        return self.residuals()["dual_qp"]
 
 
 def colour_order(n: int) -> np.ndarray:

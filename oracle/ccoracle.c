@@ -25,7 +25,9 @@
  * which a pair fixes the third index, so no two triplets of a colour share
  * a pair), colours t = 0..n-1 in turn.
  * Also the l2 metric nearness problem (Sec. II-A, p = 2) on the same metric
- * rows and schedule, at the end of this file.
+ * rows and schedule, at the end of this file, and the l1 metric nearness
+ * problem, which is (mn1) itself with real dissimilarities d in place of
+ * the 0/1 ones of correlation clustering (orc_l1_*).
  *
  * Schedule (Sec. III-B/C; the reading of its unspecified parts is stated in
  * the design notes):  indices 0..n-1 are cut into aligned blocks of size b,
@@ -254,6 +256,20 @@ static void pair_pass(int64_t np, double gamma, const double *r, const uint8_t *
     }
 }
 
+/* The same pair rows for real d (l1 metric nearness). */
+static void pair_pass_real(int64_t np, double gamma, const double *r, const double *dd,
+                           double *x, double *f, double *y_pair)
+{
+    for (int64_t p = 0; p < np; p++) {
+        double *v[2] = { &x[p], &f[p] };
+        double rinv[2] = { r[p], r[p] };
+        const double c1[2] = { 1.0, -1.0 };
+        const double c2[2] = { -1.0, -1.0 };
+        dykstra_step(v, c1, rinv, 2, dd[p], &y_pair[2 * p], gamma);
+        dykstra_step(v, c2, rinv, 2, -dd[p], &y_pair[2 * p + 1], gamma);
+    }
+}
+
 static double *inverse_weights(int64_t np, const double *w)
 {
     double *r = (double *)malloc((size_t)(np > 0 ? np : 1) * sizeof(double));
@@ -422,9 +438,9 @@ typedef struct {
 
 static double dmax(double a, double b) { return a > b ? a : b; }
 
-int orc_residuals(int64_t n, double gamma, const double *w, const uint8_t *d,
-                  const double *x, const double *f, const double *y,
-                  const double *y_pair, orc_resid *out)
+static int residuals_real(int64_t n, double gamma, const double *w, const double *dd,
+                          const double *x, const double *f, const double *y,
+                          const double *y_pair, orc_resid *out)
 {
     int64_t np = orc_num_pairs(n);
     memset(out, 0, sizeof(*out));
@@ -436,7 +452,7 @@ int orc_residuals(int64_t n, double gamma, const double *w, const uint8_t *d,
     double primal = 0.0, lp = 0.0, quad_dual = 0.0, by = 0.0;
     double vpair = 0.0, cs = 0.0, stat = 0.0;
     for (int64_t p = 0; p < np; p++) {
-        double dp = (double)d[p];
+        double dp = dd[p];
         primal += w[p] * f[p] + (w[p] * (x[p] * x[p] + f[p] * f[p])) / (2.0 * gamma);
         lp += w[p] * fabs(x[p] - dp);
         double s1 = dp - (x[p] - f[p]);      /* slack of  x - f <= d  */
@@ -470,6 +486,54 @@ int orc_residuals(int64_t n, double gamma, const double *w, const uint8_t *d,
     out->stat_resid = stat;
     free(ax); free(af);
     return 0;
+}
+
+/* Residuals of (mn1)/(qp) for 0/1 d (correlation clustering): d as doubles
+ * (exact), then the same evaluation. */
+int orc_residuals(int64_t n, double gamma, const double *w, const uint8_t *d,
+                  const double *x, const double *f, const double *y,
+                  const double *y_pair, orc_resid *out)
+{
+    int64_t np = orc_num_pairs(n);
+    double *dd = (double *)malloc((size_t)(np > 0 ? np : 1) * sizeof(double));
+    if (!dd) return -1;
+    for (int64_t p = 0; p < np; p++) dd[p] = (double)d[p];
+    int rc = residuals_real(n, gamma, w, dd, x, f, y, y_pair, out);
+    free(dd);
+    return rc;
+}
+
+/* l1 metric nearness: nsweeps sweeps of (qp) with real d (orders as in
+ * orc_sweeps), and its residuals; the starting point is orc_init_cold's,
+ * and x(y) is orc_x_from_y's (neither depends on d). */
+int orc_l1_sweeps(int64_t n, int64_t b, double gamma, const double *w, const double *dd,
+                  double *x, double *f, double *y, double *y_pair, int32_t nsweeps,
+                  int32_t order)
+{
+    if (n < 2 || b < 1 || !(gamma > 0.0)) return -1;
+    int64_t np = orc_num_pairs(n);
+    double *r = inverse_weights(np, w);
+    if (!r) return -1;
+    sweep_ctx c;
+    memset(&c, 0, sizeof(c));
+    c.n = n; c.gamma = gamma; c.r = r; c.x = x; c.y = y;
+    for (int32_t s = 0; s < nsweeps; s++) {
+        if (n >= 3) {
+            if (order == 0) visit_schedule(n, b, -1, metric_visit, &c);
+            else if (order == 1) visit_lex(n, metric_visit, &c);
+            else visit_colour(n, metric_visit, &c);
+        }
+        pair_pass_real(np, gamma, r, dd, x, f, y_pair);
+    }
+    free(r);
+    return 0;
+}
+
+int orc_l1_residuals(int64_t n, double gamma, const double *w, const double *dd,
+                     const double *x, const double *f, const double *y,
+                     const double *y_pair, orc_resid *out)
+{
+    return residuals_real(n, gamma, w, dd, x, f, y, y_pair, out);
 }
 
 /* Dual objective D(y) alone (used for the monotonicity check). */
