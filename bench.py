@@ -354,6 +354,78 @@ def schedule_report(cases=((1, 16, "f64"), (3, 16, "f32")), tol=1e-4):
     return out
 
 
+def l1_report(n=2000, b=16, solve_n=500, gamma=1.0, solve_tol=1e-3, oracle_sweeps=3):
+    """l1 metric nearness ((mn1) with real d; Sec. II-A) on noisy Euclidean
+    distances, gamma = 1 (the oracle needs about 830 sweeps to 1e-3 at
+    n = 60 and 120 with it, 2600-4700 with gamma = 5, and several thousand
+    to 1e-4): at n, per precision, one sweep dense and sparse
+    (HIP events around 5 sweeps after 2) with the HBM roofline of the
+    dense sweep; at solve_n, solves from the cold start to max violation
+    solve_tol (dense FP64, FP32 and sparse FP32); the oracle's l1 sweep on
+    the solve_n instance beside them (one core)."""
+    import torch
+    import oracle
+    from paper_1901_10084_amd import ccproj as C
+    from paper_1901_10084_amd import instances as I
+    inst = I.noisy_distances(n, seed=0, noise=0.5)
+    rows = 3 * n * (n - 1) * (n - 2) // 6
+    res = {"gamma": gamma, "sweep": {"workload": inst.name, "n": n, "b": b}}
+    for prec, sz in (("f64", 8), ("f32", 4)):
+        s = C.L1Solver(inst.n, inst.w, inst.dv, gamma, b=b, prec=prec)
+        row = {}
+        for sp in (False, True):
+            s.sweep(2, sparse=sp)
+            torch.cuda.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            s.sweep(5, sparse=sp)
+            e1.record()
+            torch.cuda.synchronize()
+            s.status()
+            row["ms_per_sweep_sparse" if sp else "ms_per_sweep"] = e0.elapsed_time(e1) / 5
+        ms = row["ms_per_sweep"]
+        algo = metric_sweep_bytes(inst_like(n, rows), sz)
+        row["roofline"] = {"bound": "hbm", "achieved": algo / (ms * 1e-3) / 1e9, "peak": 8000.0,
+                           "unit": "GB/s", "frac": algo / (ms * 1e-3) / 8e12}
+        res["sweep"][prec] = row
+        log(f"l1 sweep n={n} {prec}: {row}")
+        del s
+        torch.cuda.empty_cache()
+    small = I.noisy_distances(solve_n, seed=0, noise=0.5)
+    res["solve"] = {"workload": small.name, "n": solve_n, "tol": solve_tol}
+    for name, prec, sp in (("f64", "f64", False), ("f32", "f32", False), ("f32_sparse", "f32", True)):
+        s = C.L1Solver(small.n, small.w, small.dv, gamma, b=b, prec=prec)
+        if sp:
+            s.ensure_mask()
+        torch.cuda.synchronize()
+        r, ok, sec = s.solve(tol=solve_tol, max_sweeps=20000, sparse=sp)
+        res["solve"][name] = {"seconds": sec, "sweeps": s.sweeps, "converged": ok,
+                              "lp_cost": r["lp_cost"], "primal_qp": r["primal_qp"],
+                              "max_viol": max(r["max_viol_metric"], r["max_viol_pair"])}
+        log(f"l1 solve n={solve_n} {name}: {res['solve'][name]}")
+        del s
+        torch.cuda.empty_cache()
+    o = oracle.L1Nearness(small.n, gamma, small.w, small.dv)
+    t0 = time.perf_counter()
+    o.sweep(oracle_sweeps, b=b)
+    dt = time.perf_counter() - t0
+    srows = 3 * solve_n * (solve_n - 1) * (solve_n - 2) // 6
+    res["cpu_baseline"] = {"value": oracle_sweeps * srows / dt, "unit": "constraint-projections/s",
+                           "cores": 1, "kind": "oracle",
+                           "sample": f"{oracle_sweeps} FP64 l1 sweeps at n = {solve_n} from the cold start, "
+                                     f"{dt:.2f} s"}
+    log(f"l1 oracle: {res['cpu_baseline']}")
+    return res
+
+
+def inst_like(n, rows):
+    """The two sizes metric_sweep_bytes reads, for an instance built elsewhere."""
+    class _S:
+        num_constraints = rows
+        num_pairs = n * (n - 1) // 2
+    return _S
+
+
 def nearness_report(n=2000, b=16, solve_n=500, solve_tol=1e-4, oracle_sweeps=3):
     """l2 metric nearness (Sec. II-A, p = 2) on noisy Euclidean distances (n
     points in the unit square, each distance times U[0.5, 1.5], weights
@@ -562,6 +634,8 @@ def main():
     ap.add_argument("--no-sparse", action="store_true", help="skip the sparse dual access report")
     ap.add_argument("--sparse", action="store_true",
                     help="with --warm-report: repeat its solves with sparse dual access")
+    ap.add_argument("--l1-report", action="store_true",
+                    help="l1 metric nearness ((mn1) with real d) at n = 2000 and 500")
     ap.add_argument("--nearness-report", action="store_true",
                     help="l2 metric nearness at n = 2000 (FP64 and FP32) beside the oracle")
     ap.add_argument("--polish-report", action="store_true",
@@ -714,6 +788,9 @@ def main():
 
     if args.schedule_report:
         out["orders"] = schedule_report()
+
+    if args.l1_report:
+        out["l1_nearness"] = l1_report()
 
     if args.nearness_report:
         out["nearness"] = nearness_report()

@@ -182,6 +182,25 @@ int cc_sweep_sparse(cc_ctx *ctx, void *x, void *f, void *y, void *y_pair, const 
 /* One sparse sweep's metric rounds only (no pair pass). */
 int cc_sweep_metric_sparse(cc_ctx *ctx, void *x, void *y, const void *g, void *mask);
 
+/* l1 metric nearness (Sec. II-A): min sum_p w_p |x_p - d_p| over metric x,
+ * for real dissimilarities d.  It is (mn1) with real d in place of the 0/1
+ * d of correlation clustering, so it is solved exactly like the CC LP: the
+ * same (qp), cold start (cc_init_cold), metric sweeps, x(y) (cc_x_from_y)
+ * and stop tests; only the pair rows |x_p - d_p| <= f_p read a real d.
+ * dv: device double[N_p].
+ *
+ * nsweeps full sweeps (metric rounds, then the pair pass with real d): the
+ * dataflow executor for b = 8, 16, 32 (with mask: sparse dual access, see
+ * cc_sweep_sparse), else the round executor (mask must be NULL).
+ * Enqueues only. */
+int cc_l1_sweep(cc_ctx *ctx, void *x, void *f, void *y, void *y_pair, const void *g,
+                const double *dv, void *mask, int32_t nsweeps);
+
+/* Residuals as cc_residuals, with real d in the pair terms (lp_cost is the
+ * l1 nearness objective sum w |x - d|).  Synchronises. */
+int cc_l1_residuals(cc_ctx *ctx, const void *x, const void *f, const void *y, const void *y_pair,
+                    const double *w, const double *dv, double gamma, int32_t what, cc_resid *out);
+
 /* Another visiting order: the sum-mod-n colouring.  Triplets that share a
  * pair conflict (the colouring view of the related-work section); colour t
  * holds every triplet i<j<k with i + j + k = t (mod n), and a pair fixes

@@ -93,6 +93,8 @@ _sig("cc_dual_mask_build", ctypes.c_int, _p, _p, _p)
 _sig("cc_sweep_sparse", ctypes.c_int, _p, _p, _p, _p, _p, _p, _p, _p, _i32)
 _sig("cc_sweep_metric_sparse", ctypes.c_int, _p, _p, _p, _p, _p)
 _sig("cc_sweep_colour", ctypes.c_int, _p, _p, _p, _p, _p, _p, _p, _i32)
+_sig("cc_l1_sweep", ctypes.c_int, _p, _p, _p, _p, _p, _p, _p, _p, _i32)
+_sig("cc_l1_residuals", ctypes.c_int, _p, _p, _p, _p, _p, _p, _p, _dbl, _i32, ctypes.POINTER(Resid))
 _sig("cc_init_cold_lex", ctypes.c_int, _p, _p, _p, _p, _p, _dbl)
 _sig("cc_nearness_residuals", ctypes.c_int, _p, _p, _p, _p, _p, _i32, ctypes.POINTER(NResid))
 
@@ -116,7 +118,7 @@ EXPORTS = ["cc_last_error", "cc_num_metric_duals", "cc_create", "cc_destroy", "c
            "cc_dataflow_tables", "cc_widen", "cc_narrow", "cc_solve_cc_lp",
            "cc_nearness_init", "cc_nearness_residuals", "cc_dual_mask_bytes",
            "cc_dual_mask_build", "cc_sweep_sparse", "cc_sweep_metric_sparse", "cc_sweep_colour",
-           "cc_init_cold_lex"]
+           "cc_init_cold_lex", "cc_l1_sweep", "cc_l1_residuals"]
 
 
 class CCError(RuntimeError):
@@ -418,6 +420,48 @@ class Solver:
                 if gap_tol is None or abs(full["gap"]) <= gap_tol * max(1.0, abs(full["primal_qp"])):
                     return full, True, time.perf_counter() - t0
         return self.residuals(), False, time.perf_counter() - t0
+
+
+class L1Solver(Solver):
+    """l1 metric nearness (Sec. II-A): min sum w |x - d| over metric x for
+    real dissimilarities dv, i.e. (mn1) with real d, on the same device
+    state and kernels as Solver; only the pair rows read dv."""
+
+    def __init__(self, n, w, dv, gamma, b=16, prec="f64", device="cuda", stream=None):
+        npairs = int(n) * (int(n) - 1) // 2
+        super().__init__(n, w, np.zeros(npairs, dtype=np.uint8), gamma, b=b, prec=prec,
+                         device=device, stream=stream)
+        self.dv = torch.as_tensor(np.ascontiguousarray(dv, dtype=np.float64)).to(device)
+        assert self.dv.numel() == npairs
+
+    @classmethod
+    def from_instance(cls, inst, gamma=None, **kw):
+        return cls(inst.n, inst.w, inst.dv, inst.meta.get("gamma", 1.0) if gamma is None else gamma,
+                   **kw)
+
+    def sweep(self, nsweeps=1, executor=None, sparse=False):
+        mask = self.ensure_mask() if sparse else None
+        check(_L.cc_l1_sweep(self.ctx.handle, _ptr(self.x), _ptr(self.f), _ptr(self.y),
+                             _ptr(self.y_pair), _ptr(self.g), _ptr(self.dv), _ptr(mask),
+                             int(nsweeps)))
+        if not sparse:
+            self.invalidate_mask()
+        self.sweeps += nsweeps
+
+    def pair_pass(self):
+        raise NotImplementedError("the l1 pair rows run inside cc_l1_sweep")
+
+    def residuals(self, what=CC_RESID_ALL, raise_nonfinite=True):
+        out = Resid()
+        rc = _L.cc_l1_residuals(self.ctx.handle, _ptr(self.x), _ptr(self.f), _ptr(self.y),
+                                _ptr(self.y_pair), _ptr(self.w), _ptr(self.dv), self.gamma,
+                                int(what), ctypes.byref(out))
+        if rc == CC_ENONFINITE and not raise_nonfinite:
+            r = out.as_dict()
+            r["nonfinite"] = True
+            return r
+        check(rc)
+        return out.as_dict()
 
 
 class ColourSolver:

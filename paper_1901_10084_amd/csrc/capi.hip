@@ -22,7 +22,7 @@ int fail(int code, const std::string &msg) {
 // ----- kernels (sweep.hip, resid.hip) --------------------------------------
 template <typename T> int launch_sweep_round(const Tile *, int, int, int64_t, T *, const T *, T *, hipStream_t);
 template <typename T> int set_sweep_lds_limits(int);
-template <typename T> int launch_pair_pass(int64_t, T *, T *, T *, const T *, const uint8_t *, hipStream_t);
+template <typename T, typename DT> int launch_pair_pass(int64_t, T *, T *, T *, const T *, const DT *, hipStream_t);
 template <typename T> int launch_prepare(int64_t, const double *, double, T *, int *, hipStream_t);
 template <typename T> int launch_init_cold(int64_t, int64_t, T *, T *, T *, T *, double, hipStream_t);
 template <typename S, typename D> int launch_convert(int64_t, const S *, D *, hipStream_t);
@@ -31,7 +31,7 @@ template <typename T>
 int launch_nearness_pair_resid(int64_t, const T *, const double *, const double *, const double *, double *,
                                hipStream_t);
 template <typename T> int launch_metric_resid(const Tile *, const int32_t *, int64_t, int, int64_t, const T *, const T *, double *, hipStream_t);
-template <typename T> int launch_pair_resid(int64_t, const T *, const T *, const T *, const double *, const uint8_t *, const double *, double, double *, hipStream_t);
+template <typename T, typename DT> int launch_pair_resid(int64_t, const T *, const T *, const T *, const double *, const DT *, const double *, double, double *, hipStream_t);
 int launch_final_reduce(const double *, int64_t, const double *, double *, hipStream_t);
 int pair_partial_blocks();
 template <typename T> int launch_aty_round(const Tile *, int, int, int64_t, const T *, double *, hipStream_t);
@@ -178,8 +178,8 @@ int sweep_rounds_t(cc_ctx *c, T *x, T *y, const T *g, int first, int count) {
     return CC_OK;
 }
 
-template <typename T>
-int sweep_t(cc_ctx *c, T *x, T *f, T *y, T *yp, const T *g, const uint8_t *d, int nsweeps) {
+template <typename T, typename DT>
+int sweep_t(cc_ctx *c, T *x, T *f, T *y, T *yp, const T *g, const DT *d, int nsweeps) {
     for (int s = 0; s < nsweeps; ++s) {
         int rc = sweep_rounds_t<T>(c, x, y, g, 0, c->nrounds);
         if (rc) return rc;
@@ -241,8 +241,8 @@ template <typename T>
 int sweep_metric_t(cc_ctx *c, T *x, T *y, const T *g, int exec, unsigned long long *prof,
                    void *mask = nullptr);
 
-template <typename T>
-int sweep_dataflow_t(cc_ctx *c, T *x, T *f, T *y, T *yp, const T *g, const uint8_t *d,
+template <typename T, typename DT>
+int sweep_dataflow_t(cc_ctx *c, T *x, T *f, T *y, T *yp, const T *g, const DT *d,
                      int nsweeps, void *mask = nullptr) {
     int rc;
     for (int s = 0; s < nsweeps; ++s) {
@@ -324,9 +324,9 @@ int aty_t(cc_ctx *c, const T *y) {
     return CC_OK;
 }
 
-template <typename T>
+template <typename T, typename DT>
 int residuals_t(cc_ctx *c, const T *x, const T *f, const T *y, const T *yp, const double *w,
-                const uint8_t *d, double gamma, int what, cc_resid *out) {
+                const DT *d, double gamma, int what, cc_resid *out) {
     const bool want_cs = (what & CC_RESID_CS) && y;
     const bool want_dual = (what & CC_RESID_DUAL) && y && yp;
     int rc;
@@ -597,6 +597,44 @@ int cc_sweep_metric_sparse(cc_ctx *c, void *x, void *y, const void *g, void *mas
     if (c->prec == CC_F64)
         return sweep_metric_t<double>(c, (double *)x, (double *)y, (const double *)g, CC_EXEC_DATAFLOW, nullptr, mask);
     return sweep_metric_t<float>(c, (float *)x, (float *)y, (const float *)g, CC_EXEC_DATAFLOW, nullptr, mask);
+}
+
+int cc_l1_sweep(cc_ctx *c, void *x, void *f, void *y, void *yp, const void *g, const double *dv,
+                void *mask, int32_t nsweeps) {
+    int rc;
+    if ((rc = check_ctx(c)) || (rc = need(x, "x")) || (rc = need(f, "f")) || (rc = need(y, "y")) ||
+        (rc = need(yp, "y_pair")) || (rc = need(g, "g")) || (rc = need(dv, "d")))
+        return rc;
+    if (nsweeps < 0) return fail(CC_EINVAL, "nsweeps must be >= 0");
+    const bool df = (c->b == 8 || c->b == 16 || c->b == 32);
+    if (mask && !df) return fail(CC_EINVAL, "sparse sweeps need b = 8, 16 or 32");
+    if (mask && int64_t(c->nb) * 3 * c->b * c->b * c->b * int64_t(elem_size(c)) >= (int64_t(1) << 31))
+        return fail(CC_EINVAL, "sparse sweeps address a tile's duals with 31-bit offsets: n too large for b");
+    if (c->prec == CC_F64) {
+        if (df)
+            return sweep_dataflow_t<double>(c, (double *)x, (double *)f, (double *)y, (double *)yp,
+                                            (const double *)g, dv, nsweeps, mask);
+        return sweep_t<double>(c, (double *)x, (double *)f, (double *)y, (double *)yp, (const double *)g, dv,
+                               nsweeps);
+    }
+    if (df)
+        return sweep_dataflow_t<float>(c, (float *)x, (float *)f, (float *)y, (float *)yp, (const float *)g, dv,
+                                       nsweeps, mask);
+    return sweep_t<float>(c, (float *)x, (float *)f, (float *)y, (float *)yp, (const float *)g, dv, nsweeps);
+}
+
+int cc_l1_residuals(cc_ctx *c, const void *x, const void *f, const void *y, const void *yp, const double *w,
+                    const double *dv, double gamma, int32_t what, cc_resid *out) {
+    int rc;
+    if ((rc = check_ctx(c)) || (rc = need(x, "x")) || (rc = need(f, "f")) || (rc = need(w, "w")) ||
+        (rc = need(dv, "d")) || (rc = need(out, "out")))
+        return rc;
+    if (!(gamma > 0.0)) return fail(CC_EINVAL, "gamma must be > 0");
+    if (c->prec == CC_F64)
+        return residuals_t<double>(c, (const double *)x, (const double *)f, (const double *)y,
+                                   (const double *)yp, w, dv, gamma, what, out);
+    return residuals_t<float>(c, (const float *)x, (const float *)f, (const float *)y, (const float *)yp, w,
+                              dv, gamma, what, out);
 }
 
 int cc_init_cold_lex(cc_ctx *c, void *x, void *f, void *y_lex, void *yp, double gamma) {

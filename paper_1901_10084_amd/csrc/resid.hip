@@ -133,11 +133,12 @@ k_metric_resid(const Tile *__restrict__ tiles, const int32_t *__restrict__ chunk
 // ---------------------------------------------------------------------------
 constexpr int kPairBlocks = 1024;
 
-template <typename T>
+// d: uint8 0/1 for correlation clustering, double for l1 metric nearness
+template <typename T, typename DT>
 __global__ void __launch_bounds__(256)
 k_pair_resid(int64_t np, const T *__restrict__ x, const T *__restrict__ f,
              const T *__restrict__ yp, const double *__restrict__ w,
-             const uint8_t *__restrict__ d, const double *__restrict__ ax, double gamma,
+             const DT *__restrict__ d, const double *__restrict__ ax, double gamma,
              double *__restrict__ partial) {
     __shared__ double red[10 * 16];
     double vp = 0, swf = 0, swq = 0, lp = 0, csm = 0, css = 0, qd = 0, by = 0, st = 0, bad = 0;
@@ -390,11 +391,11 @@ int launch_nearness_pair_resid(int64_t np, const T *x, const double *dv, const d
     return CC_OK;
 }
 
-template <typename T>
+template <typename T, typename DT>
 int launch_pair_resid(int64_t np, const T *x, const T *f, const T *yp, const double *w,
-                      const uint8_t *d, const double *ax, double gamma, double *partial,
+                      const DT *d, const double *ax, double gamma, double *partial,
                       hipStream_t s) {
-    hipLaunchKernelGGL(k_pair_resid<T>, dim3(kPairBlocks), dim3(256), 0, s, np, x, f, yp, w, d,
+    hipLaunchKernelGGL((k_pair_resid<T, DT>), dim3(kPairBlocks), dim3(256), 0, s, np, x, f, yp, w, d,
                        ax, gamma, partial);
     CCP_LAUNCH_CHECK("k_pair_resid");
     return CC_OK;
@@ -460,12 +461,18 @@ template int launch_metric_resid<double>(const Tile *, const int32_t *, int64_t,
                                          const double *, const double *, double *, hipStream_t);
 template int launch_metric_resid<float>(const Tile *, const int32_t *, int64_t, int, int64_t,
                                         const float *, const float *, double *, hipStream_t);
-template int launch_pair_resid<double>(int64_t, const double *, const double *, const double *,
-                                       const double *, const uint8_t *, const double *, double,
-                                       double *, hipStream_t);
-template int launch_pair_resid<float>(int64_t, const float *, const float *, const float *,
-                                      const double *, const uint8_t *, const double *, double,
-                                      double *, hipStream_t);
+template int launch_pair_resid<double, uint8_t>(int64_t, const double *, const double *, const double *,
+                                                const double *, const uint8_t *, const double *, double,
+                                                double *, hipStream_t);
+template int launch_pair_resid<float, uint8_t>(int64_t, const float *, const float *, const float *,
+                                               const double *, const uint8_t *, const double *, double,
+                                               double *, hipStream_t);
+template int launch_pair_resid<double, double>(int64_t, const double *, const double *, const double *,
+                                               const double *, const double *, const double *, double,
+                                               double *, hipStream_t);
+template int launch_pair_resid<float, double>(int64_t, const float *, const float *, const float *,
+                                              const double *, const double *, const double *, double,
+                                              double *, hipStream_t);
 template int launch_aty_round<double>(const Tile *, int, int, int64_t, const double *, double *,
                                       hipStream_t);
 template int launch_aty_round<float>(const Tile *, int, int, int64_t, const float *, double *,

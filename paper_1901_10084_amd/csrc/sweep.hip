@@ -190,10 +190,11 @@ k_sweep_round(const Tile *__restrict__ tiles, int b_rt, int64_t n, T *__restrict
 }
 
 // Pair pass: rows x - f <= d and -x - f <= -d of every pair, in that order.
-template <typename T>
+// d: uint8 0/1 for correlation clustering, double for l1 metric nearness
+template <typename T, typename DT>
 __global__ void __launch_bounds__(256)
 k_pair_pass(int64_t np, T *__restrict__ x, T *__restrict__ f, T *__restrict__ yp,
-            const T *__restrict__ g, const uint8_t *__restrict__ d) {
+            const T *__restrict__ g, const DT *__restrict__ d) {
     for (int64_t p = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; p < np;
          p += int64_t(gridDim.x) * blockDim.x) {
         T xv = x[p], fv = f[p];
@@ -318,10 +319,10 @@ int set_sweep_lds_limits(int b) {
     return CC_OK;
 }
 
-template <typename T>
-int launch_pair_pass(int64_t np, T *x, T *f, T *yp, const T *g, const uint8_t *d,
+template <typename T, typename DT>
+int launch_pair_pass(int64_t np, T *x, T *f, T *yp, const T *g, const DT *d,
                      hipStream_t s) {
-    hipLaunchKernelGGL(k_pair_pass<T>, dim3(grid_for(np, 256)), dim3(256), 0, s, np, x, f, yp,
+    hipLaunchKernelGGL((k_pair_pass<T, DT>), dim3(grid_for(np, 256)), dim3(256), 0, s, np, x, f, yp,
                        g, d);
     CCP_LAUNCH_CHECK("k_pair_pass");
     return CC_OK;
@@ -375,10 +376,14 @@ template int launch_sweep_round<float>(const Tile *, int, int, int64_t, float *,
                                        float *, hipStream_t);
 template int set_sweep_lds_limits<double>(int);
 template int set_sweep_lds_limits<float>(int);
-template int launch_pair_pass<double>(int64_t, double *, double *, double *, const double *,
-                                      const uint8_t *, hipStream_t);
-template int launch_pair_pass<float>(int64_t, float *, float *, float *, const float *,
-                                     const uint8_t *, hipStream_t);
+template int launch_pair_pass<double, uint8_t>(int64_t, double *, double *, double *, const double *,
+                                               const uint8_t *, hipStream_t);
+template int launch_pair_pass<float, uint8_t>(int64_t, float *, float *, float *, const float *,
+                                              const uint8_t *, hipStream_t);
+template int launch_pair_pass<double, double>(int64_t, double *, double *, double *, const double *,
+                                              const double *, hipStream_t);
+template int launch_pair_pass<float, double>(int64_t, float *, float *, float *, const float *,
+                                             const double *, hipStream_t);
 template int launch_prepare<double>(int64_t, const double *, double, double *, int *,
                                     hipStream_t);
 template int launch_prepare<float>(int64_t, const double *, double, float *, int *,
