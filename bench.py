@@ -354,6 +354,44 @@ def schedule_report(cases=((1, 16, "f64"), (3, 16, "f32")), tol=1e-4):
     return out
 
 
+def tile_report(cases=((1, "f64", (8, 16, 32)), (2, "f32", (8, 16, 32)), (2, "f64", (8, 16, 32)),
+                       (3, "f32", (8, 16, 32)), (4, "f32", (16, 32))), steps=5):
+    """The GPU counterpart of the paper's tile-size and core-count curves
+    (Figs. 5-6): one metric sweep (dense, and with sparse dual access after
+    20 sweeps into a solve) per tile size b on each workload, HIP events
+    around `steps` launches after 2, with the number of tiles that can run
+    at once on average, about (nb+1)(nb+2)/24 for nb = ceil(n/b), against
+    the chip's 256 compute units."""
+    import torch
+    from paper_1901_10084_amd import ccproj as C
+    from paper_1901_10084_amd import instances as I
+    out = []
+    for config, prec, bs in cases:
+        inst = I.workload(config)
+        for b in bs:
+            s = C.Solver.from_instance(inst, b=b, prec=prec)
+            row = {"workload": inst.name, "n": inst.n, "prec": prec, "b": b,
+                   "tiles_in_flight": (-(-inst.n // b) + 1) * (-(-inst.n // b) + 2) / 24}
+            s.sweep(20)
+            for sp in (False, True):
+                s.sweep_metric(sparse=sp)
+                s.sweep_metric(sparse=sp)
+                torch.cuda.synchronize()
+                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                e0.record()
+                for _ in range(steps):
+                    s.sweep_metric(sparse=sp)
+                e1.record()
+                torch.cuda.synchronize()
+                s.status()
+                row["sparse_ms" if sp else "dense_ms"] = e0.elapsed_time(e1) / steps
+            log(f"tile report: {row}")
+            out.append(row)
+            del s
+            torch.cuda.empty_cache()
+    return out
+
+
 def l1_report(n=2000, b=16, solve_n=500, gamma=1.0, solve_tol=1e-3, oracle_sweeps=3):
     """l1 metric nearness ((mn1) with real d; Sec. II-A) on noisy Euclidean
     distances, gamma = 1 (the oracle needs about 830 sweeps to 1e-3 at
@@ -634,6 +672,8 @@ def main():
     ap.add_argument("--no-sparse", action="store_true", help="skip the sparse dual access report")
     ap.add_argument("--sparse", action="store_true",
                     help="with --warm-report: repeat its solves with sparse dual access")
+    ap.add_argument("--tile-report", action="store_true",
+                    help="sweep time against the tile size b on each workload (dense and sparse)")
     ap.add_argument("--l1-report", action="store_true",
                     help="l1 metric nearness ((mn1) with real d) at n = 2000 and 500")
     ap.add_argument("--nearness-report", action="store_true",
@@ -788,6 +828,9 @@ def main():
 
     if args.schedule_report:
         out["orders"] = schedule_report()
+
+    if args.tile_report:
+        out["tiles"] = tile_report()
 
     if args.l1_report:
         out["l1_nearness"] = l1_report()
