@@ -182,6 +182,46 @@ int cc_sweep_sparse(cc_ctx *ctx, void *x, void *f, void *y, void *y_pair, const 
 /* One sparse sweep's metric rounds only (no pair pass). */
 int cc_sweep_metric_sparse(cc_ctx *ctx, void *x, void *y, const void *g, void *mask);
 
+/* Compacted dual lists: the memory form of Sec. III-D, which keeps only
+ * the nonzero duals, per processor, in visit order.  Here each tile step of
+ * the schedule keeps a list of (slot, dual) pairs for its nonzero metric
+ * duals, in a pool the context owns; there is no dense dual array, so n is
+ * no longer bounded by 3 C(n,3) duals fitting in memory.  b must be 8 or 16
+ * (CC_EINVAL otherwise).  A sweep expands each step's list in LDS, runs the
+ * step, and writes the new nonzeros to a second pool; when they do not fit,
+ * the sweep is repeated from a saved x into a pool grown to fit
+ * (CC_ENOMEM if memory runs out).  Results equal cc_sweep's bit for bit.
+ *
+ * cc_compact_init: (re)allocates both pools with room for `capacity`
+ * entries each (they grow on demand) plus per-step tables (12 bytes a step
+ * per pool) and a copy of x, and sets every list empty: the duals of the
+ * cold start.  Synchronises. */
+int cc_compact_init(cc_ctx *ctx, int64_t capacity);
+
+/* nsweeps full sweeps with compacted lists (dataflow executor): metric
+ * rounds, then the pair pass.  x, f, y_pair, g, d as for cc_sweep, from
+ * cc_init_cold with y = NULL.  Synchronises once per sweep (overflow
+ * check). */
+int cc_sweep_compact(cc_ctx *ctx, void *x, void *f, void *y_pair, const void *g,
+                     const uint8_t *d, int32_t nsweeps);
+
+/* The current lists as a dense schedule-ordered y (device,
+ * cc_dual_slots elements), zeros elsewhere.  Enqueues only. */
+int cc_compact_to_slots(cc_ctx *ctx, void *y);
+
+/* *count = entries in the current lists; if lex and val (device, room for
+ * `capacity` entries) are given and capacity >= *count, they receive each
+ * entry's colex row index 3 tidx(i,j,k) + o and its dual (in the context's
+ * precision), in pool order.  Synchronises. */
+int cc_compact_export(cc_ctx *ctx, int64_t *lex, void *val, int64_t capacity, int64_t *count);
+
+/* Entries after the last sweep, device bytes the lists and their tables
+ * hold, and sweeps repeated to grow a pool (any pointer may be NULL). */
+int cc_compact_info(cc_ctx *ctx, int64_t *nnz, int64_t *bytes, int32_t *regrows);
+
+/* Frees the lists (cc_destroy also does). */
+int cc_compact_release(cc_ctx *ctx);
+
 /* l1 metric nearness (Sec. II-A): min sum_p w_p |x_p - d_p| over metric x,
  * for real dissimilarities d.  It is (mn1) with real d in place of the 0/1
  * d of correlation clustering, so it is solved exactly like the CC LP: the

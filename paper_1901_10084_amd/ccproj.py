@@ -94,6 +94,12 @@ _sig("cc_sweep_sparse", ctypes.c_int, _p, _p, _p, _p, _p, _p, _p, _p, _i32)
 _sig("cc_sweep_metric_sparse", ctypes.c_int, _p, _p, _p, _p, _p)
 _sig("cc_sweep_colour", ctypes.c_int, _p, _p, _p, _p, _p, _p, _p, _i32)
 _sig("cc_l1_sweep", ctypes.c_int, _p, _p, _p, _p, _p, _p, _p, _p, _i32)
+_sig("cc_compact_init", ctypes.c_int, _p, _i64)
+_sig("cc_sweep_compact", ctypes.c_int, _p, _p, _p, _p, _p, _p, _i32)
+_sig("cc_compact_to_slots", ctypes.c_int, _p, _p)
+_sig("cc_compact_export", ctypes.c_int, _p, _p, _p, _i64, ctypes.POINTER(_i64))
+_sig("cc_compact_info", ctypes.c_int, _p, ctypes.POINTER(_i64), ctypes.POINTER(_i64), ctypes.POINTER(_i32))
+_sig("cc_compact_release", ctypes.c_int, _p)
 _sig("cc_l1_residuals", ctypes.c_int, _p, _p, _p, _p, _p, _p, _p, _dbl, _i32, ctypes.POINTER(Resid))
 _sig("cc_init_cold_lex", ctypes.c_int, _p, _p, _p, _p, _p, _dbl)
 _sig("cc_nearness_residuals", ctypes.c_int, _p, _p, _p, _p, _p, _i32, ctypes.POINTER(NResid))
@@ -118,7 +124,9 @@ EXPORTS = ["cc_last_error", "cc_num_metric_duals", "cc_create", "cc_destroy", "c
            "cc_dataflow_tables", "cc_widen", "cc_narrow", "cc_solve_cc_lp",
            "cc_nearness_init", "cc_nearness_residuals", "cc_dual_mask_bytes",
            "cc_dual_mask_build", "cc_sweep_sparse", "cc_sweep_metric_sparse", "cc_sweep_colour",
-           "cc_init_cold_lex", "cc_l1_sweep", "cc_l1_residuals"]
+           "cc_init_cold_lex", "cc_l1_sweep", "cc_l1_residuals", "cc_compact_init",
+           "cc_sweep_compact", "cc_compact_to_slots", "cc_compact_export", "cc_compact_info",
+           "cc_compact_release"]
 
 
 class CCError(RuntimeError):
@@ -420,6 +428,84 @@ class Solver:
                 if gap_tol is None or abs(full["gap"]) <= gap_tol * max(1.0, abs(full["primal_qp"])):
                     return full, True, time.perf_counter() - t0
         return self.residuals(), False, time.perf_counter() - t0
+
+
+class CompactSolver:
+    """Correlation-clustering state with compacted dual lists (the memory
+    form of Sec. III-D): w, d, g, x, f, y_pair on the device, and only the
+    nonzero metric duals, in per-tile-step lists the context owns.  b = 8 or
+    16.  No dense dual array is allocated."""
+
+    def __init__(self, n, w, d, gamma, b=16, prec="f64", capacity=1 << 20, device="cuda",
+                 stream=None):
+        if not torch.cuda.is_available():
+            raise RuntimeError("ccproj needs a ROCm GPU; none is visible")
+        self.n, self.gamma, self.b, self.prec = int(n), float(gamma), int(b), prec
+        self.ctx = Context(self.n, self.b, prec, stream)
+        dt = self.ctx.dtype
+        npairs = self.n * (self.n - 1) // 2
+        self.w = torch.as_tensor(np.ascontiguousarray(w, dtype=np.float64)).to(device)
+        self.d = torch.as_tensor(np.ascontiguousarray(d, dtype=np.uint8)).to(device)
+        self.g = torch.empty(npairs, dtype=dt, device=device)
+        self.x = torch.empty(npairs, dtype=dt, device=device)
+        self.f = torch.empty(npairs, dtype=dt, device=device)
+        self.y_pair = torch.empty(2 * npairs, dtype=dt, device=device)
+        self.capacity = int(capacity)
+        self.ctx.prepare(self.w, self.gamma, self.g)
+        self.init_cold()
+
+    @classmethod
+    def from_instance(cls, inst, **kw):
+        return cls(inst.n, inst.w, inst.d, inst.gamma, **kw)
+
+    def init_cold(self):
+        self.ctx.init_cold(self.x, self.f, None, self.y_pair, self.gamma)
+        check(_L.cc_compact_init(self.ctx.handle, self.capacity))
+        self.sweeps = 0
+
+    def sweep(self, nsweeps=1):
+        check(_L.cc_sweep_compact(self.ctx.handle, _ptr(self.x), _ptr(self.f), _ptr(self.y_pair),
+                                  _ptr(self.g), _ptr(self.d), int(nsweeps)))
+        self.sweeps += nsweeps
+
+    def info(self) -> dict:
+        nnz, by, rg = _i64(), _i64(), _i32()
+        check(_L.cc_compact_info(self.ctx.handle, ctypes.byref(nnz), ctypes.byref(by),
+                                 ctypes.byref(rg)))
+        return {"nnz": nnz.value, "bytes": by.value, "regrows": rg.value}
+
+    def to_slots(self):
+        """The current duals as a dense schedule-ordered array (tests)."""
+        y = torch.empty(self.ctx.slots, dtype=self.x.dtype, device=self.x.device)
+        check(_L.cc_compact_to_slots(self.ctx.handle, _ptr(y)))
+        return y
+
+    def export(self):
+        """(colex row indices, duals) of the nonzero duals, on the device."""
+        cnt = _i64()
+        check(_L.cc_compact_export(self.ctx.handle, None, None, 0, ctypes.byref(cnt)))
+        lex = torch.empty(max(cnt.value, 1), dtype=torch.int64, device=self.x.device)
+        val = torch.empty(max(cnt.value, 1), dtype=self.x.dtype, device=self.x.device)
+        check(_L.cc_compact_export(self.ctx.handle, _ptr(lex), _ptr(val), lex.numel(),
+                                   ctypes.byref(cnt)))
+        return lex[:cnt.value], val[:cnt.value]
+
+    def residuals(self):
+        """Max violations and the primal objective (x and f only)."""
+        return self.ctx.residuals(self.x, self.f, None, None, self.w, self.d, self.gamma,
+                                  CC_RESID_VIOL)
+
+    def solve(self, tol=1e-6, max_sweeps=100000, check_every=None):
+        if check_every is None:
+            check_every = 1 if self.n <= 1000 else 5
+        t0 = time.perf_counter()
+        r = None
+        while self.sweeps < max_sweeps:
+            self.sweep(min(check_every, max_sweeps - self.sweeps))
+            r = self.residuals()
+            if max(r["max_viol_metric"], r["max_viol_pair"]) <= tol:
+                return r, True, time.perf_counter() - t0
+        return r, False, time.perf_counter() - t0
 
 
 class L1Solver(Solver):

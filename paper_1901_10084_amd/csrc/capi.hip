@@ -58,7 +58,9 @@ struct DataflowArgs {
 };
 void build_dataflow_tables(int64_t n, int b, std::vector<DTile> &tiles, std::vector<uint32_t> &needs,
                            std::vector<uint32_t> &K);
-template <typename T> int launch_sweep_dataflow(const DataflowArgs &, int, int, int64_t, T *, const T *, T *, void *, hipStream_t);
+template <typename T> int launch_sweep_dataflow(const DataflowArgs &, int, int, int64_t, T *, const T *, T *, void *, const CompactArgs<T> *, hipStream_t);
+template <typename T> int launch_compact_to_slots(int, int64_t, const uint16_t *, const T *, const int64_t *, const uint32_t *, T *, hipStream_t);
+template <typename T> int launch_compact_export(int, int64_t, int, const DTile *, const int32_t *, const uint16_t *, const T *, const int64_t *, const uint32_t *, int64_t *, T *, hipStream_t);
 template <typename T> int launch_mask_build(int, int64_t, const T *, void *, hipStream_t);
 template <typename T> int launch_sweep_colour(int64_t, T *, const T *, T *, hipStream_t);
 template <typename T> int dataflow_occupancy(int, int *);
@@ -114,6 +116,19 @@ struct cc_ctx {
     float *d_mean_deg = nullptr;  // warm-start features
     int32_t *d_chunks = nullptr;  // (tile, first step) per chunk of kChunkSteps tile steps
     int64_t nchunks = 0;
+    // compacted dual lists (allocated by cc_compact_init)
+    uint16_t *cp_idx[2] = {nullptr, nullptr};
+    void *cp_val[2] = {nullptr, nullptr};
+    int64_t cp_cap[2] = {0, 0};
+    int64_t *cp_off[2] = {nullptr, nullptr};
+    uint32_t *cp_cnt[2] = {nullptr, nullptr};
+    int cp_cur = 0;                      // the pool holding the current lists
+    unsigned long long *cp_alloc = nullptr;
+    uint32_t *cp_flag = nullptr;
+    void *cp_xsnap = nullptr;            // x before the sweep, for a repeat
+    int32_t *cp_step_tile = nullptr;     // tile of each tile step (export)
+    int64_t cp_nnz = 0;                  // entries after the last sweep
+    int cp_regrows = 0;                  // sweeps repeated with a larger pool
 };
 
 namespace {
@@ -289,7 +304,7 @@ int sweep_metric_t(cc_ctx *c, T *x, T *y, const T *g, int exec, unsigned long lo
     DataflowArgs a;
     int rc = dataflow_args(c, prof, a);
     if (rc) return rc;
-    if ((rc = launch_sweep_dataflow<T>(a, c->df_grid, c->b, c->n, x, g, y, mask, c->stream))) return rc;
+    if ((rc = launch_sweep_dataflow<T>(a, c->df_grid, c->b, c->n, x, g, y, mask, nullptr, c->stream))) return rc;
     c->epoch++;
     return CC_OK;
 }
@@ -473,8 +488,33 @@ int cc_create(cc_ctx **out, int64_t n, int32_t b, int32_t prec, void *stream) {
     return CC_OK;
 }
 
+static void compact_free(cc_ctx *c) {
+    for (int e = 0; e < 2; ++e) {
+        (void)hipFree(c->cp_idx[e]);
+        (void)hipFree(c->cp_val[e]);
+        (void)hipFree(c->cp_off[e]);
+        (void)hipFree(c->cp_cnt[e]);
+        c->cp_idx[e] = nullptr;
+        c->cp_val[e] = nullptr;
+        c->cp_off[e] = nullptr;
+        c->cp_cnt[e] = nullptr;
+        c->cp_cap[e] = 0;
+    }
+    (void)hipFree(c->cp_alloc);
+    (void)hipFree(c->cp_flag);
+    (void)hipFree(c->cp_xsnap);
+    (void)hipFree(c->cp_step_tile);
+    c->cp_alloc = nullptr;
+    c->cp_flag = nullptr;
+    c->cp_xsnap = nullptr;
+    c->cp_step_tile = nullptr;
+    c->cp_nnz = 0;
+    c->cp_regrows = 0;
+}
+
 int cc_destroy(cc_ctx *c) {
     if (!c) return CC_OK;
+    compact_free(c);
     (void)hipFree(c->d_tiles);
     (void)hipFree(c->d_mpart);
     (void)hipFree(c->d_ppart);
@@ -635,6 +675,182 @@ int cc_l1_residuals(cc_ctx *c, const void *x, const void *f, const void *y, cons
                                    (const double *)yp, w, dv, gamma, what, out);
     return residuals_t<float>(c, (const float *)x, (const float *)f, (const float *)y, (const float *)yp, w,
                               dv, gamma, what, out);
+}
+
+}  // extern "C"
+
+namespace {
+
+// (Re)allocates pool e with room for cap entries.
+int compact_pool(cc_ctx *c, int e, int64_t cap) {
+    (void)hipFree(c->cp_idx[e]);
+    (void)hipFree(c->cp_val[e]);
+    c->cp_idx[e] = nullptr;
+    c->cp_val[e] = nullptr;
+    c->cp_cap[e] = 0;
+    if (hipMalloc(&c->cp_idx[e], size_t(cap) * sizeof(uint16_t)) != hipSuccess ||
+        hipMalloc(&c->cp_val[e], size_t(cap) * elem_size(c)) != hipSuccess)
+        return fail(CC_ENOMEM, "hipMalloc of a compacted dual pool failed");
+    c->cp_cap[e] = cap;
+    return CC_OK;
+}
+
+int64_t num_steps(const cc_ctx *c) { return c->slots / (int64_t(3) * c->b * c->b * c->b); }
+
+template <typename T>
+int sweep_compact_t(cc_ctx *c, T *x, T *f, T *yp, const T *g, const uint8_t *d, int nsweeps) {
+    int rc;
+    const int64_t np = num_pairs(c->n);
+    for (int s = 0; s < nsweeps; ++s) {
+        for (int attempt = 0;; ++attempt) {
+            const int in = c->cp_cur, out = 1 - c->cp_cur;
+            CCP_HIP_CHECK(hipMemcpyAsync(c->cp_xsnap, x, size_t(np) * sizeof(T), hipMemcpyDeviceToDevice, c->stream));
+            CCP_HIP_CHECK(hipMemsetAsync(c->cp_alloc, 0, sizeof(unsigned long long), c->stream));
+            CCP_HIP_CHECK(hipMemsetAsync(c->cp_flag, 0, sizeof(uint32_t), c->stream));
+            DataflowArgs a;
+            if ((rc = dataflow_args(c, nullptr, a))) return rc;
+            const CompactArgs<T> ca{c->cp_idx[in], static_cast<const T *>(c->cp_val[in]), c->cp_off[in],
+                                    c->cp_cnt[in], c->cp_idx[out], static_cast<T *>(c->cp_val[out]),
+                                    c->cp_off[out], c->cp_cnt[out], c->cp_alloc, c->cp_cap[out], c->cp_flag};
+            if ((rc = launch_sweep_dataflow<T>(a, c->df_grid, c->b, c->n, x, g, nullptr, nullptr, &ca, c->stream)))
+                return rc;
+            c->epoch++;
+            if ((rc = check_dataflow(c))) return rc;
+            unsigned long long used = 0;
+            uint32_t flag = 0;
+            CCP_HIP_CHECK(hipMemcpyAsync(&used, c->cp_alloc, sizeof(used), hipMemcpyDeviceToHost, c->stream));
+            CCP_HIP_CHECK(hipMemcpyAsync(&flag, c->cp_flag, sizeof(flag), hipMemcpyDeviceToHost, c->stream));
+            CCP_HIP_CHECK(hipStreamSynchronize(c->stream));
+            if (!flag) {
+                c->cp_nnz = int64_t(used);
+                c->cp_cur = out;
+                break;
+            }
+            // the new lists did not fit: the input lists are intact, so
+            // restore x and repeat the sweep into a larger pool
+            if (attempt >= 4) return fail(CC_ENOMEM, "compacted dual pool kept overflowing");
+            CCP_HIP_CHECK(hipMemcpyAsync(x, c->cp_xsnap, size_t(np) * sizeof(T), hipMemcpyDeviceToDevice, c->stream));
+            const int64_t want = int64_t(used) + int64_t(used) / 4 + 4096;
+            if ((rc = compact_pool(c, out, std::max<int64_t>(want, 2 * c->cp_cap[out])))) return rc;
+            c->cp_regrows++;
+        }
+        if ((rc = launch_pair_pass<T>(np, x, f, yp, g, d, c->stream))) return rc;
+    }
+    return CC_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int cc_compact_init(cc_ctx *c, int64_t capacity) {
+    int rc;
+    if ((rc = check_ctx(c))) return rc;
+    if (!(c->b == 8 || c->b == 16)) return fail(CC_EINVAL, "compacted dual lists need b = 8 or 16");
+    if (capacity < 1) return fail(CC_EINVAL, "capacity must be >= 1");
+    if ((rc = ensure_dataflow(c))) return rc;
+    compact_free(c);
+    const int64_t ns = num_steps(c);
+    for (int e = 0; e < 2; ++e) {
+        if (hipMalloc(&c->cp_off[e], size_t(ns) * sizeof(int64_t)) != hipSuccess ||
+            hipMalloc(&c->cp_cnt[e], size_t(ns) * sizeof(uint32_t)) != hipSuccess) {
+            compact_free(c);
+            return fail(CC_ENOMEM, "hipMalloc of compacted list tables failed");
+        }
+        if ((rc = compact_pool(c, e, capacity))) {
+            compact_free(c);
+            return rc;
+        }
+    }
+    if (hipMalloc(&c->cp_alloc, sizeof(unsigned long long)) != hipSuccess ||
+        hipMalloc(&c->cp_flag, sizeof(uint32_t)) != hipSuccess ||
+        hipMalloc(&c->cp_xsnap, size_t(num_pairs(c->n)) * elem_size(c)) != hipSuccess ||
+        hipMalloc(&c->cp_step_tile, size_t(ns) * sizeof(int32_t)) != hipSuccess) {
+        compact_free(c);
+        return fail(CC_ENOMEM, "hipMalloc for compacted lists failed");
+    }
+    // tile of every step, for export
+    std::vector<DTile> tiles;
+    std::vector<uint32_t> needs, K;
+    build_dataflow_tables(c->n, c->b, tiles, needs, K);
+    std::vector<int32_t> st(size_t(ns), 0);
+    for (size_t t = 0; t < tiles.size(); ++t)
+        for (int m = 0; m <= tiles[t].Q - tiles[t].P; ++m) st[size_t(tiles[t].jsbase) + m] = int32_t(t);
+    CCP_HIP_CHECK(hipMemcpy(c->cp_step_tile, st.data(), st.size() * sizeof(int32_t), hipMemcpyHostToDevice));
+    // the cold start: every list empty
+    CCP_HIP_CHECK(hipMemsetAsync(c->cp_cnt[0], 0, size_t(ns) * sizeof(uint32_t), c->stream));
+    CCP_HIP_CHECK(hipMemsetAsync(c->cp_off[0], 0, size_t(ns) * sizeof(int64_t), c->stream));
+    CCP_HIP_CHECK(hipStreamSynchronize(c->stream));
+    c->cp_cur = 0;
+    c->cp_nnz = 0;
+    return CC_OK;
+}
+
+int cc_sweep_compact(cc_ctx *c, void *x, void *f, void *yp, const void *g, const uint8_t *d, int32_t nsweeps) {
+    int rc;
+    if ((rc = check_ctx(c)) || (rc = need(x, "x")) || (rc = need(f, "f")) || (rc = need(yp, "y_pair")) ||
+        (rc = need(g, "g")) || (rc = need(d, "d")))
+        return rc;
+    if (!c->cp_cnt[0]) return fail(CC_EINVAL, "call cc_compact_init first");
+    if (nsweeps < 0) return fail(CC_EINVAL, "nsweeps must be >= 0");
+    if (c->prec == CC_F64)
+        return sweep_compact_t<double>(c, (double *)x, (double *)f, (double *)yp, (const double *)g, d, nsweeps);
+    return sweep_compact_t<float>(c, (float *)x, (float *)f, (float *)yp, (const float *)g, d, nsweeps);
+}
+
+int cc_compact_to_slots(cc_ctx *c, void *y) {
+    int rc;
+    if ((rc = check_ctx(c)) || (rc = need(y, "y"))) return rc;
+    if (!c->cp_cnt[0]) return fail(CC_EINVAL, "call cc_compact_init first");
+    const int in = c->cp_cur;
+    CCP_HIP_CHECK(hipMemsetAsync(y, 0, size_t(c->slots) * elem_size(c), c->stream));
+    if (c->prec == CC_F64)
+        return launch_compact_to_slots<double>(c->b, num_steps(c), c->cp_idx[in], (const double *)c->cp_val[in],
+                                               c->cp_off[in], c->cp_cnt[in], (double *)y, c->stream);
+    return launch_compact_to_slots<float>(c->b, num_steps(c), c->cp_idx[in], (const float *)c->cp_val[in],
+                                          c->cp_off[in], c->cp_cnt[in], (float *)y, c->stream);
+}
+
+int cc_compact_export(cc_ctx *c, int64_t *lex, void *val, int64_t capacity, int64_t *count) {
+    int rc;
+    if ((rc = check_ctx(c)) || (rc = need(count, "count"))) return rc;
+    if (!c->cp_cnt[0]) return fail(CC_EINVAL, "call cc_compact_init first");
+    *count = c->cp_nnz;
+    if (!lex || !val || capacity < c->cp_nnz) return CC_OK;
+    const int in = c->cp_cur;
+    if (c->prec == CC_F64)
+        rc = launch_compact_export<double>(c->b, num_steps(c), c->nb, c->d_dtiles, c->cp_step_tile, c->cp_idx[in],
+                                           (const double *)c->cp_val[in], c->cp_off[in], c->cp_cnt[in], lex,
+                                           (double *)val, c->stream);
+    else
+        rc = launch_compact_export<float>(c->b, num_steps(c), c->nb, c->d_dtiles, c->cp_step_tile, c->cp_idx[in],
+                                          (const float *)c->cp_val[in], c->cp_off[in], c->cp_cnt[in], lex,
+                                          (float *)val, c->stream);
+    if (rc) return rc;
+    CCP_HIP_CHECK(hipStreamSynchronize(c->stream));
+    return CC_OK;
+}
+
+int cc_compact_info(cc_ctx *c, int64_t *nnz, int64_t *bytes, int32_t *regrows) {
+    int rc;
+    if ((rc = check_ctx(c))) return rc;
+    int64_t by = 0;
+    if (c->cp_cnt[0]) {
+        by = (c->cp_cap[0] + c->cp_cap[1]) * int64_t(sizeof(uint16_t) + elem_size(c)) +
+             2 * num_steps(c) * int64_t(sizeof(int64_t) + sizeof(uint32_t)) + num_steps(c) * int64_t(sizeof(int32_t)) +
+             num_pairs(c->n) * int64_t(elem_size(c));
+    }
+    if (nnz) *nnz = c->cp_nnz;
+    if (bytes) *bytes = by;
+    if (regrows) *regrows = c->cp_regrows;
+    return CC_OK;
+}
+
+int cc_compact_release(cc_ctx *c) {
+    int rc;
+    if ((rc = check_ctx(c))) return rc;
+    compact_free(c);
+    return CC_OK;
 }
 
 int cc_init_cold_lex(cc_ctx *c, void *x, void *f, void *y_lex, void *yp, double gamma) {

@@ -42,6 +42,24 @@ struct GraphView {
     int64_t nchunks;
 };
 
+// Compacted dual lists (sweeps without a dense dual array): tile step c's
+// cnt[c] entries (slot within the step, dual) start at off[c] in a pool; a
+// sweep reads the _in pool and writes the _out pool.
+template <typename T>
+struct CompactArgs {
+    const uint16_t *idx_in;
+    const T *val_in;
+    const int64_t *off_in;
+    const uint32_t *cnt_in;
+    uint16_t *idx_out;
+    T *val_out;
+    int64_t *off_out;
+    uint32_t *cnt_out;
+    unsigned long long *alloc;  // entries taken from the output pool
+    int64_t cap;                // output pool capacity, entries
+    uint32_t *overflow;         // raised when a step's list does not fit
+};
+
 // Packed column-major upper-triangular pair index, i < j.
 __host__ __device__ __forceinline__ int64_t pidx(int64_t i, int64_t j) {
     return j * (j - 1) / 2 + i;

@@ -31,6 +31,14 @@
 // value changed, and rewrites the mask from the new duals; its results equal
 // the dense sweep's bit for bit.  Mask layout: tile step c (schedule order)
 // holds 3 b^2 words of b bits, word [c][o][lane] with bit t for sub-step t.
+//
+// Compacted dual lists (the memory form of Sec. III-D, for b = 8 and 16):
+// no dense dual array at all.  Tile step c keeps a list of (slot, dual)
+// pairs for its nonzero duals in a pool; a sweep expands a step's list into
+// an LDS copy of the step's duals, runs the sub-steps on it, and writes the
+// step's new nonzeros to the other pool through a bump allocator.  A list
+// that does not fit raises a flag; the host then restores x and repeats the
+// sweep with a larger pool.  Results equal the dense sweep's bit for bit.
 #include <vector>
 
 #include "common.hpp"
@@ -178,11 +186,12 @@ __device__ __forceinline__ bool wait_counts(const uint32_t *c0, uint32_t n0, con
     return res;
 }
 
-template <typename T, int B, int D, bool SP>
+template <typename T, int B, int D, bool SP, bool CP>
 __global__ void __launch_bounds__(B * B)
 k_sweep_dataflow(DataflowArgs a, int64_t n, T *__restrict__ x, const T *__restrict__ g,
-                 T *__restrict__ y, typename MaskWord<B>::type *__restrict__ mask) {
+                 T *__restrict__ y, typename MaskWord<B>::type *__restrict__ mask, CompactArgs<T> cp) {
     using MW = typename MaskWord<B>::type;
+    static_assert(!CP || (!SP && B <= 16), "compacted lists: b = 8 or 16, 16-bit slot indices");
     // the first and last groups of D sub-steps are peeled: refills of the
     // other groups stay inside the step
     static_assert(B % D == 0 && B >= 2 * D, "ring depth must divide b, twice at least");
@@ -206,6 +215,8 @@ k_sweep_dataflow(DataflowArgs a, int64_t n, T *__restrict__ x, const T *__restri
     T *const lds = reinterpret_cast<T *>(smem_raw);
     T *const Ax0 = lds, *const Ag0 = lds + bb, *const Bx0 = lds + 2 * bb, *const Bg0 = lds + 3 * bb;
     T *const Cx = lds + 4 * bb, *const Cg = lds + 5 * bb;
+    // compacted lists: the current step's 3 b^3 duals, [t][o][lane]
+    T *const ly = lds + 6 * bb;
     __shared__ int s_tix, s_ok;
 
     // Control structure: every `if (tid == 0)` region is closed by a
@@ -405,9 +416,21 @@ k_sweep_dataflow(DataflowArgs a, int64_t n, T *__restrict__ x, const T *__restri
                 }
                 if (m < Q - P) load_mask(m + 1);
             }
-            fill_ring(m);
+            if constexpr (!CP) fill_ring(m);
             blk_store(P, J, vax, vag, Ax0, Ag0);
             blk_store(J, Q, vbx, vbg, Bx0, Bg0);
+            if constexpr (CP) {
+                // the step's duals: zeros, then its list's entries
+                for (int e = tid; e < 3 * b * bb; e += bb) ly[e] = T(0);
+                lds_barrier();
+                const int64_t c = int64_t(tl.jsbase) + m;
+                const uint32_t cnt = cp.cnt_in[c];
+                const int64_t off = cp.off_in[c];
+                for (uint32_t e = uint32_t(tid); e < cnt; e += uint32_t(bb)) {
+                    const uint32_t sl = cp.idx_in[off + e];
+                    if (sl < uint32_t(3 * b * bb)) ly[sl] = cp.val_in[off + e];
+                }
+            }
             lds_barrier();
             const T gC = Cg[tid];
             if (tid == 0 && a.prof) mark(1);
@@ -434,7 +457,17 @@ k_sweep_dataflow(DataflowArgs a, int64_t n, T *__restrict__ x, const T *__restri
                 for (int d = 0; d < D; ++d) {
                     const int t = t0 + d;
                     const int u = m * b + t;
-                    T y0 = yq[d][0], y1 = yq[d][1], y2 = yq[d][2];
+                    const int sl = 3 * t * bb + int(lane);
+                    T y0, y1, y2;
+                    if constexpr (CP) {
+                        y0 = ly[sl];
+                        y1 = ly[sl + bb];
+                        y2 = ly[sl + 2 * bb];
+                    } else {
+                        y0 = yq[d][0];
+                        y1 = yq[d][1];
+                        y2 = yq[d][2];
+                    }
                     const T q = qn, ga = gan, gb = gbn;
                     if (t + 1 < b) qn = gq(t + 1, gan, gbn);
                     const int jl = mid_offset(t, il, kl, b);
@@ -463,7 +496,11 @@ k_sweep_dataflow(DataflowArgs a, int64_t n, T *__restrict__ x, const T *__restri
                         }
                     }
                     T *dst = ytile + int64_t(__builtin_amdgcn_readfirstlane(u)) * ystep;
-                    if constexpr (SP) {
+                    if constexpr (CP) {
+                        ly[sl] = y0;
+                        ly[sl + bb] = y1;
+                        ly[sl + 2 * bb] = y2;
+                    } else if constexpr (SP) {
                         // store only changed duals; mark the nonzero ones
                         const uint64_t b0 = dual_bits(y0), b1 = dual_bits(y1), b2 = dual_bits(y2);
                         const uint32_t ou = uint32_t(int64_t(u) * ystep * int64_t(sizeof(T)));
@@ -489,7 +526,7 @@ k_sweep_dataflow(DataflowArgs a, int64_t n, T *__restrict__ x, const T *__restri
                         __builtin_nontemporal_store(y1, &dst[lane + bb]);
                         __builtin_nontemporal_store(y2, &dst[lane + 2 * bb]);
                     }
-                    if (refill) {
+                    if (refill && !CP) {
                         // Refill slot d after its duals are consumed, so the
                         // old and new values never live at once (no register
                         // copies of loads in flight).
@@ -502,6 +539,54 @@ k_sweep_dataflow(DataflowArgs a, int64_t n, T *__restrict__ x, const T *__restri
 #pragma nounroll
             for (int t0 = D; t0 < b - D; t0 += D) group(t0, true);
             group(b - D, false);
+            if constexpr (CP) {
+                // Write the step's nonzero duals to the output pool: a block
+                // prefix over the threads' counts (slots k b^2 + tid), one
+                // allocation per step, then each thread's entries in order.
+                __shared__ uint32_t s_wave[B * B / 64];
+                __shared__ unsigned long long s_base;
+                __shared__ int s_fit;
+                uint32_t nz = 0;
+                for (int k = 0; k < 3 * b; ++k) nz += nonzero01(ly[k * bb + tid]);
+                uint32_t incl = nz;
+#pragma unroll
+                for (int sh = 1; sh < 64; sh <<= 1) {
+                    const uint32_t v = __shfl_up(incl, sh, 64);
+                    if ((tid & 63) >= sh) incl += v;
+                }
+                if ((tid & 63) == 63) s_wave[tid >> 6] = incl;
+                lds_barrier();
+                uint32_t before = 0, total = 0;
+#pragma unroll
+                for (int w = 0; w < bb / 64; ++w) {
+                    const uint32_t v = s_wave[w];
+                    if (w < (tid >> 6)) before += v;
+                    total += v;
+                }
+                const int64_t c = int64_t(tl.jsbase) + m;
+                if (tid == 0) {
+                    const unsigned long long base = atomicAdd(cp.alloc, (unsigned long long)total);
+                    const int fit = (base + total <= (unsigned long long)cp.cap) ? 1 : 0;
+                    if (!fit) atomicOr(cp.overflow, 1u);
+                    cp.off_out[c] = int64_t(base);
+                    cp.cnt_out[c] = fit ? total : 0u;
+                    s_base = base;
+                    s_fit = fit;
+                }
+                lds_barrier();
+                if (__builtin_amdgcn_readfirstlane(s_fit)) {
+                    int64_t pos = int64_t(s_base) + before + (incl - nz);
+                    for (int k = 0; k < 3 * b; ++k) {
+                        const int e = k * bb + tid;
+                        const T v = ly[e];
+                        if (nonzero01(v)) {
+                            cp.idx_out[pos] = uint16_t(e);
+                            cp.val_out[pos] = v;
+                            ++pos;
+                        }
+                    }
+                }
+            }
             if constexpr (SP) {
                 MW *r = mask_row(m);
                 const uint32_t flip = lean ? ~0u : 0u;
@@ -783,31 +868,115 @@ size_t dataflow_lds_bytes(int b) {
 
 template <typename T, int B, int D>
 static int launch_df_t(const DataflowArgs &a, int grid, int64_t n, T *x, const T *g, T *y,
-                       void *mask, hipStream_t s) {
+                       void *mask, const CompactArgs<T> *cp, hipStream_t s) {
     using MW = typename MaskWord<B>::type;
     const size_t lds = dataflow_lds_bytes<T>(B);
     hipLaunchKernelGGL(k_dataflow_reset, dim3(1), dim3(64), 0, s, a.ctl);
     CCP_LAUNCH_CHECK("k_dataflow_reset");
-    if (mask)
-        hipLaunchKernelGGL((k_sweep_dataflow<T, B, D, true>), dim3(grid), dim3(B * B), lds, s, a, n, x, g, y,
-                           static_cast<MW *>(mask));
-    else
-        hipLaunchKernelGGL((k_sweep_dataflow<T, B, D, false>), dim3(grid), dim3(B * B), lds, s, a, n, x, g, y,
-                           static_cast<MW *>(nullptr));
+    if (cp) {
+        if constexpr (B <= 16) {
+            const size_t lds_cp = lds + size_t(3) * B * B * B * sizeof(T);
+            const hipError_t e = hipFuncSetAttribute((const void *)k_sweep_dataflow<T, B, D, false, true>,
+                                                     hipFuncAttributeMaxDynamicSharedMemorySize, int(lds_cp));
+            if (e != hipSuccess) return fail(CC_EHIP, std::string("hipFuncSetAttribute: ") + hipGetErrorString(e));
+            hipLaunchKernelGGL((k_sweep_dataflow<T, B, D, false, true>), dim3(grid), dim3(B * B), lds_cp, s, a, n,
+                               x, g, y, static_cast<MW *>(nullptr), *cp);
+        } else {
+            return fail(CC_EINVAL, "compacted dual lists need b = 8 or 16");
+        }
+    } else if (mask) {
+        hipLaunchKernelGGL((k_sweep_dataflow<T, B, D, true, false>), dim3(grid), dim3(B * B), lds, s, a, n, x, g,
+                           y, static_cast<MW *>(mask), CompactArgs<T>{});
+    } else {
+        hipLaunchKernelGGL((k_sweep_dataflow<T, B, D, false, false>), dim3(grid), dim3(B * B), lds, s, a, n, x, g,
+                           y, static_cast<MW *>(nullptr), CompactArgs<T>{});
+    }
     CCP_LAUNCH_CHECK("k_sweep_dataflow");
     return CC_OK;
 }
 
-// mask == nullptr: the dense sweep; otherwise the sparse one with this mask.
+// mask == nullptr and cp == nullptr: the dense sweep; mask: the sparse one
+// with this mask; cp: the compacted-list one (y unused).
 template <typename T>
 int launch_sweep_dataflow(const DataflowArgs &a, int grid, int b, int64_t n, T *x, const T *g,
-                          T *y, void *mask, hipStream_t s) {
+                          T *y, void *mask, const CompactArgs<T> *cp, hipStream_t s) {
     switch (b) {
-        case 8: return launch_df_t<T, 8, 4>(a, grid, n, x, g, y, mask, s);
-        case 16: return launch_df_t<T, 16, 8>(a, grid, n, x, g, y, mask, s);
-        case 32: return launch_df_t<T, 32, 4>(a, grid, n, x, g, y, mask, s);
+        case 8: return launch_df_t<T, 8, 4>(a, grid, n, x, g, y, mask, cp, s);
+        case 16: return launch_df_t<T, 16, 8>(a, grid, n, x, g, y, mask, cp, s);
+        case 32: return launch_df_t<T, 32, 4>(a, grid, n, x, g, y, mask, cp, s);
         default: return fail(CC_EINVAL, "the dataflow executor supports b = 8, 16, 32");
     }
+}
+
+// Dense schedule-ordered duals from compacted lists (y zero-filled first):
+// one block per step, threads over its entries.
+template <typename T, int B>
+__global__ void __launch_bounds__(256)
+k_compact_to_slots(int64_t nsteps, const uint16_t *__restrict__ idx, const T *__restrict__ val,
+                   const int64_t *__restrict__ off, const uint32_t *__restrict__ cnt, T *__restrict__ y) {
+    constexpr int64_t per = int64_t(3) * B * B * B;
+    for (int64_t c = blockIdx.x; c < nsteps; c += gridDim.x) {
+        const uint32_t k = cnt[c];
+        const int64_t o = off[c];
+        for (uint32_t e = threadIdx.x; e < k; e += blockDim.x) {
+            const uint32_t sl = idx[o + e];
+            if (sl < uint32_t(per)) y[c * per + sl] = val[o + e];
+        }
+    }
+}
+
+// The entries of compacted lists as (colex row index 3 tidx(i,j,k) + o,
+// dual), at their pool positions.  step_tile[c] is step c's tile.
+template <typename T, int B>
+__global__ void __launch_bounds__(256)
+k_compact_export(int64_t nsteps, int nb, const DTile *__restrict__ tiles, const int32_t *__restrict__ step_tile,
+                 const uint16_t *__restrict__ idx, const T *__restrict__ val, const int64_t *__restrict__ off,
+                 const uint32_t *__restrict__ cnt, int64_t *__restrict__ lex, T *__restrict__ out) {
+    constexpr int bb = B * B;
+    for (int64_t c = blockIdx.x; c < nsteps; c += gridDim.x) {
+        const DTile tl = tiles[step_tile[c]];
+        const int m = int(c - tl.jsbase);
+        const int J = tile_J(tl.P, tl.Q, m, tile_desc(tl.P, tl.Q, nb));
+        const uint32_t k = cnt[c];
+        const int64_t o = off[c];
+        for (uint32_t e = threadIdx.x; e < k; e += blockDim.x) {
+            const int sl = idx[o + e];
+            const int t = sl / (3 * bb), rem = sl % (3 * bb), or_ = rem / bb, lane = rem % bb;
+            const int il = lane / B, kl = lane % B, jl = mid_offset(t, il, kl, B);
+            const int64_t i = int64_t(tl.P) * B + il, j = int64_t(J) * B + jl, kk = int64_t(tl.Q) * B + kl;
+            lex[o + e] = 3 * tidx(i, j, kk) + or_;
+            out[o + e] = val[o + e];
+        }
+    }
+}
+
+template <typename T>
+int launch_compact_to_slots(int b, int64_t nsteps, const uint16_t *idx, const T *val, const int64_t *off,
+                            const uint32_t *cnt, T *y, hipStream_t s) {
+    const int64_t grid = nsteps < (int64_t(1) << 20) ? nsteps : (int64_t(1) << 20);
+    if (grid <= 0) return CC_OK;
+    switch (b) {
+        case 8: hipLaunchKernelGGL((k_compact_to_slots<T, 8>), dim3(unsigned(grid)), dim3(256), 0, s, nsteps, idx, val, off, cnt, y); break;
+        case 16: hipLaunchKernelGGL((k_compact_to_slots<T, 16>), dim3(unsigned(grid)), dim3(256), 0, s, nsteps, idx, val, off, cnt, y); break;
+        default: return fail(CC_EINVAL, "compacted dual lists need b = 8 or 16");
+    }
+    CCP_LAUNCH_CHECK("k_compact_to_slots");
+    return CC_OK;
+}
+
+template <typename T>
+int launch_compact_export(int b, int64_t nsteps, int nb, const DTile *tiles, const int32_t *step_tile,
+                          const uint16_t *idx, const T *val, const int64_t *off, const uint32_t *cnt,
+                          int64_t *lex, T *out, hipStream_t s) {
+    const int64_t grid = nsteps < (int64_t(1) << 20) ? nsteps : (int64_t(1) << 20);
+    if (grid <= 0) return CC_OK;
+    switch (b) {
+        case 8: hipLaunchKernelGGL((k_compact_export<T, 8>), dim3(unsigned(grid)), dim3(256), 0, s, nsteps, nb, tiles, step_tile, idx, val, off, cnt, lex, out); break;
+        case 16: hipLaunchKernelGGL((k_compact_export<T, 16>), dim3(unsigned(grid)), dim3(256), 0, s, nsteps, nb, tiles, step_tile, idx, val, off, cnt, lex, out); break;
+        default: return fail(CC_EINVAL, "compacted dual lists need b = 8 or 16");
+    }
+    CCP_LAUNCH_CHECK("k_compact_export");
+    return CC_OK;
 }
 
 template <typename T>
@@ -816,19 +985,19 @@ int dataflow_occupancy(int b, int *blocks_per_cu) {
     const int lds = int(dataflow_lds_bytes<T>(b));
     switch (b) {
         case 8:
-            e = hipFuncSetAttribute((const void *)k_sweep_dataflow<T, 8, 4, false>, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
-            if (e == hipSuccess) e = hipFuncSetAttribute((const void *)k_sweep_dataflow<T, 8, 4, true>, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
-            if (e == hipSuccess) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, k_sweep_dataflow<T, 8, 4, false>, 64, lds);
+            e = hipFuncSetAttribute((const void *)k_sweep_dataflow<T, 8, 4, false, false>, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+            if (e == hipSuccess) e = hipFuncSetAttribute((const void *)k_sweep_dataflow<T, 8, 4, true, false>, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+            if (e == hipSuccess) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, k_sweep_dataflow<T, 8, 4, false, false>, 64, lds);
             break;
         case 16:
-            e = hipFuncSetAttribute((const void *)k_sweep_dataflow<T, 16, 8, false>, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
-            if (e == hipSuccess) e = hipFuncSetAttribute((const void *)k_sweep_dataflow<T, 16, 8, true>, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
-            if (e == hipSuccess) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, k_sweep_dataflow<T, 16, 8, false>, 256, lds);
+            e = hipFuncSetAttribute((const void *)k_sweep_dataflow<T, 16, 8, false, false>, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+            if (e == hipSuccess) e = hipFuncSetAttribute((const void *)k_sweep_dataflow<T, 16, 8, true, false>, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+            if (e == hipSuccess) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, k_sweep_dataflow<T, 16, 8, false, false>, 256, lds);
             break;
         case 32:
-            e = hipFuncSetAttribute((const void *)k_sweep_dataflow<T, 32, 4, false>, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
-            if (e == hipSuccess) e = hipFuncSetAttribute((const void *)k_sweep_dataflow<T, 32, 4, true>, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
-            if (e == hipSuccess) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, k_sweep_dataflow<T, 32, 4, false>, 1024, lds);
+            e = hipFuncSetAttribute((const void *)k_sweep_dataflow<T, 32, 4, false, false>, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+            if (e == hipSuccess) e = hipFuncSetAttribute((const void *)k_sweep_dataflow<T, 32, 4, true, false>, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+            if (e == hipSuccess) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, k_sweep_dataflow<T, 32, 4, false, false>, 1024, lds);
             break;
         default:
             *blocks_per_cu = 0;
@@ -882,9 +1051,21 @@ int launch_fill_u32(int64_t count, uint32_t *a, hipStream_t s) {
 }
 
 template int launch_sweep_dataflow<double>(const DataflowArgs &, int, int, int64_t, double *,
-                                           const double *, double *, void *, hipStream_t);
+                                           const double *, double *, void *, const CompactArgs<double> *,
+                                           hipStream_t);
 template int launch_sweep_dataflow<float>(const DataflowArgs &, int, int, int64_t, float *,
-                                          const float *, float *, void *, hipStream_t);
+                                          const float *, float *, void *, const CompactArgs<float> *,
+                                          hipStream_t);
+template int launch_compact_to_slots<double>(int, int64_t, const uint16_t *, const double *, const int64_t *,
+                                             const uint32_t *, double *, hipStream_t);
+template int launch_compact_to_slots<float>(int, int64_t, const uint16_t *, const float *, const int64_t *,
+                                            const uint32_t *, float *, hipStream_t);
+template int launch_compact_export<double>(int, int64_t, int, const DTile *, const int32_t *, const uint16_t *,
+                                           const double *, const int64_t *, const uint32_t *, int64_t *,
+                                           double *, hipStream_t);
+template int launch_compact_export<float>(int, int64_t, int, const DTile *, const int32_t *, const uint16_t *,
+                                          const float *, const int64_t *, const uint32_t *, int64_t *, float *,
+                                          hipStream_t);
 template int launch_mask_build<double>(int, int64_t, const double *, void *, hipStream_t);
 template int launch_mask_build<float>(int, int64_t, const float *, void *, hipStream_t);
 template int launch_aty_dataflow<double>(const DataflowArgs &, int, int, int64_t, const double *, double *, hipStream_t);

@@ -335,3 +335,19 @@ def test_solve_not_converged_reports():
                                    max_sweeps=5, mode=C.CC_MODE_F64)
     assert rc == C.CC_ENOTCONV and info["sweeps"] == 5
     assert info["resid"]["max_viol_metric"] > 1e-12
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_prepare_and_cold_start_are_exact(prec):
+    """a1: g = gamma / w, rounded once to the working precision; a2: the
+    starting point of Algorithm 1, x = 0, f = -gamma, every dual 0, equal
+    to the oracle's."""
+    inst = I.random_signed(23, seed=3, gamma=2.5, weighted=True)
+    g = C.Solver.from_instance(inst, b=8, prec=prec)
+    dt = np.float64 if prec == "f64" else np.float32
+    assert np.array_equal(g.g.cpu().numpy(), (inst.gamma / inst.w).astype(dt))
+    o = oracle.State.from_instance(inst)
+    assert np.array_equal(g.x.cpu().numpy().astype(np.float64), o.x)
+    assert np.array_equal(g.f.cpu().numpy().astype(np.float64), o.f)
+    assert np.array_equal(g.y_pair.cpu().numpy().astype(np.float64), o.y_pair)
+    assert not g.y.any()
