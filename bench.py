@@ -354,6 +354,60 @@ def schedule_report(cases=((1, 16, "f64"), (3, 16, "f32")), tol=1e-4):
     return out
 
 
+def compact_report(big_n=6000, tol=1e-4, settle=20, steps=5):
+    """Compacted dual lists (the memory form of Sec. III-D): per-sweep time
+    and device memory on the n = 2000 and n = 4000 workloads after `settle`
+    sweeps from the cold start (wall clock around `steps` sweeps: each
+    compacted sweep synchronises once for its overflow check), against the
+    bytes a dense dual array would take; then a solve to max violation
+    `tol` at n = big_n (the n = 4000 workload's Chung-Lu family: exponent
+    2.2, mean degree 20, weights U[0.5, 1.5], gamma 10), whose dense dual
+    array would not fit in one GPU's memory."""
+    import torch
+    from paper_1901_10084_amd import ccproj as C
+    from paper_1901_10084_amd import instances as I
+    out = {"sweeps": []}
+    for config, prec in ((3, "f32"), (4, "f32")):
+        inst = I.workload(config)
+        s = C.CompactSolver.from_instance(inst, b=16, prec=prec)
+        s.sweep(settle)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        s.sweep(steps)
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) / steps * 1e3
+        info = s.info()
+        row = {"workload": inst.name, "n": inst.n, "b": 16, "prec": prec, "ms_per_sweep": ms,
+               "nonzero_duals": info["nnz"], "device_bytes": info["bytes"],
+               "dense_dual_bytes": s.ctx.slots * (4 if prec == "f32" else 8), "regrows": info["regrows"]}
+        log(f"compact report: {row}")
+        out["sweeps"].append(row)
+        del s
+        torch.cuda.empty_cache()
+    inst = I.chung_lu(big_n, 2.2, 20.0, seed=0, gamma=10.0, weights="uniform_0.5_1.5")
+    s = C.CompactSolver.from_instance(inst, b=16, prec="f32")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ok, r = False, None
+    while not ok and s.sweeps < 400:
+        r, ok, _ = s.solve(tol=tol, max_sweeps=s.sweeps + 25, check_every=5)
+        log(f"compact solve n={big_n}: {s.sweeps} sweeps, max violation "
+            f"{max(r['max_viol_metric'], r['max_viol_pair']):.3e}, {s.info()}")
+    sec = time.perf_counter() - t0
+    info = s.info()
+    out["beyond_dense"] = {"workload": inst.name, "n": big_n, "b": 16, "prec": "f32", "tol": tol,
+                           "seconds": sec, "sweeps": s.sweeps, "converged": ok,
+                           "primal_qp": r["primal_qp"],
+                           "max_viol": max(r["max_viol_metric"], r["max_viol_pair"]),
+                           "nonzero_duals": info["nnz"], "device_bytes_lists": info["bytes"],
+                           "dense_dual_bytes": s.ctx.slots * 4,
+                           "gpu_memory_bytes": torch.cuda.get_device_properties(0).total_memory}
+    log(f"compact beyond dense: {out['beyond_dense']}")
+    del s
+    torch.cuda.empty_cache()
+    return out
+
+
 def tile_report(cases=((1, "f64", (8, 16, 32)), (2, "f32", (8, 16, 32)), (2, "f64", (8, 16, 32)),
                        (3, "f32", (8, 16, 32)), (4, "f32", (16, 32))), steps=5):
     """The GPU counterpart of the paper's tile-size and core-count curves
@@ -672,6 +726,8 @@ def main():
     ap.add_argument("--no-sparse", action="store_true", help="skip the sparse dual access report")
     ap.add_argument("--sparse", action="store_true",
                     help="with --warm-report: repeat its solves with sparse dual access")
+    ap.add_argument("--compact-report", action="store_true",
+                    help="compacted dual lists at n = 2000, 4000 and a solve at n = 6000")
     ap.add_argument("--tile-report", action="store_true",
                     help="sweep time against the tile size b on each workload (dense and sparse)")
     ap.add_argument("--l1-report", action="store_true",
@@ -828,6 +884,9 @@ def main():
 
     if args.schedule_report:
         out["orders"] = schedule_report()
+
+    if args.compact_report:
+        out["compact"] = compact_report()
 
     if args.tile_report:
         out["tiles"] = tile_report()
