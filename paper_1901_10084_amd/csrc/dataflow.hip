@@ -244,6 +244,8 @@ k_sweep_dataflow(DataflowArgs a, int64_t n, T *__restrict__ x, const T *__restri
     };
     if (tid == 0)
         for (int e = 0; e < 6; ++e) s_pt[e] = 0;
+    if constexpr (CP)
+        for (int e = tid; e < 3 * B * B * B; e += B * B) ly[e] = T(0);
     if (tid == 0) s_tix = int(atomicAdd(&a.ctl[0], 1u));
     __syncthreads();
     for (;;) {
@@ -420,9 +422,10 @@ k_sweep_dataflow(DataflowArgs a, int64_t n, T *__restrict__ x, const T *__restri
             blk_store(P, J, vax, vag, Ax0, Ag0);
             blk_store(J, Q, vbx, vbg, Bx0, Bg0);
             if constexpr (CP) {
-                // the step's duals: zeros, then its list's entries
-                for (int e = tid; e < 3 * b * bb; e += bb) ly[e] = T(0);
-                lds_barrier();
+                // the step's duals: the array is all zeros between steps
+                // (zeroed once per workgroup, and each step's write-out
+                // clears the slots it wrote), so only the list's entries
+                // are stored
                 const int64_t c = int64_t(tl.jsbase) + m;
                 const uint32_t cnt = cp.cnt_in[c];
                 const int64_t off = cp.off_in[c];
@@ -445,6 +448,9 @@ k_sweep_dataflow(DataflowArgs a, int64_t n, T *__restrict__ x, const T *__restri
             };
             T gan, gbn;
             T qn = gq(0, gan, gbn);
+            // compacted lists: bit 3t + o set where this lane's dual (t, o)
+            // ends the step nonzero (each is final once its sub-step ran)
+            uint64_t nzm = 0;
             // D sub-steps, one per ring slot.  The first group is peeled off
             // the loop so that the loop is entered with the ring in the
             // state it has at every later iteration; the compiler's memory
@@ -500,6 +506,7 @@ k_sweep_dataflow(DataflowArgs a, int64_t n, T *__restrict__ x, const T *__restri
                         ly[sl] = y0;
                         ly[sl + bb] = y1;
                         ly[sl + 2 * bb] = y2;
+                        nzm |= uint64_t(nonzero01(y0) | (nonzero01(y1) << 1) | (nonzero01(y2) << 2)) << (3 * t);
                     } else if constexpr (SP) {
                         // store only changed duals; mark the nonzero ones
                         const uint64_t b0 = dual_bits(y0), b1 = dual_bits(y1), b2 = dual_bits(y2);
@@ -546,8 +553,7 @@ k_sweep_dataflow(DataflowArgs a, int64_t n, T *__restrict__ x, const T *__restri
                 __shared__ uint32_t s_wave[B * B / 64];
                 __shared__ unsigned long long s_base;
                 __shared__ int s_fit;
-                uint32_t nz = 0;
-                for (int k = 0; k < 3 * b; ++k) nz += nonzero01(ly[k * bb + tid]);
+                const uint32_t nz = uint32_t(__builtin_popcountll(nzm));
                 uint32_t incl = nz;
 #pragma unroll
                 for (int sh = 1; sh < 64; sh <<= 1) {
@@ -574,17 +580,18 @@ k_sweep_dataflow(DataflowArgs a, int64_t n, T *__restrict__ x, const T *__restri
                     s_fit = fit;
                 }
                 lds_barrier();
-                if (__builtin_amdgcn_readfirstlane(s_fit)) {
-                    int64_t pos = int64_t(s_base) + before + (incl - nz);
-                    for (int k = 0; k < 3 * b; ++k) {
-                        const int e = k * bb + tid;
-                        const T v = ly[e];
-                        if (nonzero01(v)) {
-                            cp.idx_out[pos] = uint16_t(e);
-                            cp.val_out[pos] = v;
-                            ++pos;
-                        }
+                const bool fit = __builtin_amdgcn_readfirstlane(s_fit) != 0;
+                int64_t pos = int64_t(s_base) + before + (incl - nz);
+                while (nzm) {
+                    const int k = __builtin_ctzll(nzm);
+                    nzm &= nzm - 1;
+                    const int e = k * bb + tid;
+                    if (fit) {
+                        cp.idx_out[pos] = uint16_t(e);
+                        cp.val_out[pos] = ly[e];
+                        ++pos;
                     }
+                    ly[e] = T(0);  // leave the array all zeros for the next step
                 }
             }
             if constexpr (SP) {
