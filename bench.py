@@ -408,14 +408,15 @@ def compact_report(big_n=6000, tol=1e-4, settle=20, steps=5):
     return out
 
 
-def tile_report(cases=((1, "f64", (8, 16, 32)), (2, "f32", (8, 16, 32)), (2, "f64", (8, 16, 32)),
-                       (3, "f32", (8, 16, 32)), (4, "f32", (16, 32))), steps=5):
-    """The GPU counterpart of the paper's tile-size and core-count curves
-    (Figs. 5-6): one metric sweep (dense, and with sparse dual access after
-    20 sweeps into a solve) per tile size b on each workload, HIP events
-    around `steps` launches after 2, with the number of tiles that can run
-    at once on average, about (nb+1)(nb+2)/24 for nb = ceil(n/b), against
-    the chip's 256 compute units."""
+def tile_report(cases=((1, "f64", (8, 16, 24, 32)), (2, "f32", (8, 16, 24, 32)),
+                       (2, "f64", (8, 16, 24, 32)), (3, "f32", (8, 16, 24, 32)),
+                       (4, "f32", (16, 24, 32))), steps=5):
+    """The GPU counterpart of the paper's tile-size curve (Fig. 6): one
+    metric sweep (dense, and with sparse dual access after 20 sweeps into a
+    solve; b = 24 has no sparse form) per tile size b on each workload, HIP
+    events around `steps` launches after 2, with the number of tiles that
+    can run at once on average, about (nb+1)(nb+2)/24 for nb = ceil(n/b),
+    against the chip's 256 compute units."""
     import torch
     from paper_1901_10084_amd import ccproj as C
     from paper_1901_10084_amd import instances as I
@@ -427,7 +428,7 @@ def tile_report(cases=((1, "f64", (8, 16, 32)), (2, "f32", (8, 16, 32)), (2, "f6
             row = {"workload": inst.name, "n": inst.n, "prec": prec, "b": b,
                    "tiles_in_flight": (-(-inst.n // b) + 1) * (-(-inst.n // b) + 2) / 24}
             s.sweep(20)
-            for sp in (False, True):
+            for sp in ((False, True) if b != 24 else (False,)):
                 s.sweep_metric(sparse=sp)
                 s.sweep_metric(sparse=sp)
                 torch.cuda.synchronize()
@@ -443,6 +444,50 @@ def tile_report(cases=((1, "f64", (8, 16, 32)), (2, "f32", (8, 16, 32)), (2, "f6
             out.append(row)
             del s
             torch.cuda.empty_cache()
+    return out
+
+
+def workgroup_report(cases=((1, "f64", 16), (3, "f32", 16), (4, "f32", 32)),
+                     counts=(8, 16, 32, 64, 128, 256, 512, 768, 1024), steps=5):
+    """The GPU counterpart of the paper's core-count curve (Fig. 5): one
+    dense metric sweep, 20 sweeps into a solve, with the dataflow sweep's
+    workgroup count fixed (each workgroup is one tile worker, as a core is
+    in the paper), HIP events around `steps` launches after 2; requests
+    above what the GPU holds at once are capped, and the default count is
+    timed beside them."""
+    import torch
+    from paper_1901_10084_amd import ccproj as C
+    from paper_1901_10084_amd import instances as I
+    out = []
+    for config, prec, b in cases:
+        inst = I.workload(config)
+        s = C.Solver.from_instance(inst, b=b, prec=prec)
+        s.sweep(20)
+        row = {"workload": inst.name, "n": inst.n, "prec": prec, "b": b, "ms": {}}
+        for wg in (0,) + tuple(counts):
+            eff = s.ctx.set_dataflow_workgroups(wg)
+            if wg and eff < wg and str(eff) in row["ms"]:
+                continue
+            s.sweep_metric()
+            s.sweep_metric()
+            torch.cuda.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            for _ in range(steps):
+                s.sweep_metric()
+            e1.record()
+            torch.cuda.synchronize()
+            s.status()
+            ms = e0.elapsed_time(e1) / steps
+            if wg == 0:
+                row["default_workgroups"], row["default_ms"] = eff, ms
+            else:
+                row["ms"][str(eff)] = ms
+            log(f"workgroup report {inst.name} b={b} {prec}: asked {wg}, ran {eff}: {ms:.3f} ms")
+        s.ctx.set_dataflow_workgroups(0)
+        out.append(row)
+        del s
+        torch.cuda.empty_cache()
     return out
 
 
@@ -729,7 +774,8 @@ def main():
     ap.add_argument("--compact-report", action="store_true",
                     help="compacted dual lists at n = 2000, 4000 and a solve at n = 6000")
     ap.add_argument("--tile-report", action="store_true",
-                    help="sweep time against the tile size b on each workload (dense and sparse)")
+                    help="sweep time against the tile size b on each workload (dense and sparse) "
+                         "and against the dataflow sweep's workgroup count")
     ap.add_argument("--l1-report", action="store_true",
                     help="l1 metric nearness ((mn1) with real d) at n = 2000 and 500")
     ap.add_argument("--nearness-report", action="store_true",
@@ -890,6 +936,7 @@ def main():
 
     if args.tile_report:
         out["tiles"] = tile_report()
+        out["workgroups"] = workgroup_report()
 
     if args.l1_report:
         out["l1_nearness"] = l1_report()

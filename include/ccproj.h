@@ -136,7 +136,7 @@ int cc_init_cold(cc_ctx *ctx, void *x, void *f, void *y, void *y_pair, double ga
 /* nsweeps full sweeps (Sec. IV-D: one pass over every constraint): all
  * metric rounds in schedule order, then the pair pass.  g from cc_prepare;
  * d: device uint8[N_p].  exec selects the executor (CC_EXEC_ROUNDS: one
- * launch per round; CC_EXEC_DATAFLOW, for b = 8, 16, 32: one persistent
+ * launch per round; CC_EXEC_DATAFLOW, for b = 8, 16, 24, 32: one persistent
  * launch per sweep whose tile steps wait only for the earlier steps that
  * touch the same blocks of x).  Both executors apply the updates of every
  * variable in the same order and give identical results.  Enqueues only
@@ -230,8 +230,9 @@ int cc_compact_release(cc_ctx *ctx);
  * dv: device double[N_p].
  *
  * nsweeps full sweeps (metric rounds, then the pair pass with real d): the
- * dataflow executor for b = 8, 16, 32 (with mask: sparse dual access, see
- * cc_sweep_sparse), else the round executor (mask must be NULL).
+ * dataflow executor for b = 8, 16, 24, 32 (with mask, for b = 8, 16, 32:
+ * sparse dual access, see cc_sweep_sparse), else the round executor (mask
+ * must be NULL).
  * Enqueues only. */
 int cc_l1_sweep(cc_ctx *ctx, void *x, void *f, void *y, void *y_pair, const void *g,
                 const double *dv, void *mask, int32_t nsweeps);
@@ -259,7 +260,22 @@ int cc_sweep_colour(cc_ctx *ctx, void *x, void *f, void *y_lex, void *y_pair, co
  * in colex order (cc_num_metric_duals(n) zeros). */
 int cc_init_cold_lex(cc_ctx *ctx, void *x, void *f, void *y_lex, void *y_pair, double gamma);
 
-/* Diagnostic: one dataflow metric sweep (b = 8, 16, 32) with a time
+/* The number of workgroups of the context's dataflow sweeps (b = 8, 16,
+ * 24, 32): the GPU counterpart of the paper's processor count in its
+ * core-count experiment (Fig. 5).  A count from 1 up applies to every
+ * dataflow sweep of the context, capped at the workgroups the GPU holds at
+ * once and at one per tile.  0 restores the defaults: the schedule's
+ * average parallelism, about (nb+1)(nb+2)/24 tiles, capped at what the GPU
+ * holds at once, for the sparse and compacted sweeps; the same, capped per
+ * compute unit at the counts measured fastest (b = 8: 4; b = 16: 2 in
+ * FP32, 1 in FP64; b = 24, 32: 1), for the dense sweep.  Any count gives
+ * the same results bit for bit (tile steps wait for the earlier steps on
+ * their blocks, and tiles are taken in schedule order).  *effective (may
+ * be NULL) receives the dense sweep's count.  Host only; CC_EINVAL for a
+ * negative count or a b without a dataflow kernel. */
+int cc_set_dataflow_workgroups(cc_ctx *ctx, int32_t workgroups, int32_t *effective);
+
+/* Diagnostic: one dataflow metric sweep (b = 8, 16, 24, 32) with a time
  * breakdown summed over all workgroups, in microseconds: out[0] waiting for
  * the blocks a tile step needs, out[1] loading them into LDS, out[2] the
  * sub-steps, out[3] publishing; out[4] tile steps run, out[5] workgroups.

@@ -76,6 +76,7 @@ _sig("cc_sweep_rounds", ctypes.c_int, _p, _p, _p, _p, _i32, _i32)
 _sig("cc_sweep_metric", ctypes.c_int, _p, _p, _p, _p, _i32)
 _sig("cc_status", ctypes.c_int, _p)
 _sig("cc_dataflow_breakdown", ctypes.c_int, _p, _p, _p, _p, ctypes.POINTER(_dbl))
+_sig("cc_set_dataflow_workgroups", ctypes.c_int, _p, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32))
 _sig("cc_pair_pass", ctypes.c_int, _p, _p, _p, _p, _p, _p)
 _sig("cc_residuals", ctypes.c_int, _p, _p, _p, _p, _p, _p, _p, _dbl, _i32,
      ctypes.POINTER(Resid))
@@ -126,7 +127,7 @@ EXPORTS = ["cc_last_error", "cc_num_metric_duals", "cc_create", "cc_destroy", "c
            "cc_dual_mask_build", "cc_sweep_sparse", "cc_sweep_metric_sparse", "cc_sweep_colour",
            "cc_init_cold_lex", "cc_l1_sweep", "cc_l1_residuals", "cc_compact_init",
            "cc_sweep_compact", "cc_compact_to_slots", "cc_compact_export", "cc_compact_info",
-           "cc_compact_release"]
+           "cc_compact_release", "cc_set_dataflow_workgroups", "cc_dataflow_breakdown"]
 
 
 class CCError(RuntimeError):
@@ -187,10 +188,10 @@ class Context:
 
     def executor(self, executor=None):
         """The given executor, or by default the dataflow executor where it
-        exists (b = 8, 16, 32) and the round-by-round one elsewhere."""
+        exists (b = 8, 16, 24, 32) and the round-by-round one elsewhere."""
         if executor is not None:
             return int(executor)
-        return CC_EXEC_DATAFLOW if self.b in (8, 16, 32) else CC_EXEC_ROUNDS
+        return CC_EXEC_DATAFLOW if self.b in (8, 16, 24, 32) else CC_EXEC_ROUNDS
 
     def close(self):
         if getattr(self, "_h", None):
@@ -237,6 +238,13 @@ class Context:
 
     def status(self):
         check(_L.cc_status(self._h))
+
+    def set_dataflow_workgroups(self, workgroups=0):
+        """Workgroups of the dataflow sweeps (0: the default); returns the
+        count used."""
+        eff = ctypes.c_int32(0)
+        check(_L.cc_set_dataflow_workgroups(self._h, int(workgroups), ctypes.byref(eff)))
+        return int(eff.value)
 
     def dataflow_breakdown(self, x, y, g):
         out = (_dbl * 8)()
@@ -367,7 +375,8 @@ class Solver:
 
     def sweep(self, nsweeps=1, executor=None, sparse=False):
         """nsweeps sweeps; sparse=True reads only the duals the mask marks
-        (dataflow executor, b = 8, 16, 32; the same results bit for bit)."""
+        (dataflow executor, b = 8, 16, 32; the same results bit for bit).
+        The dataflow executor also runs b = 24, without sparse access."""
         if sparse:
             self.ctx.sweep_sparse(self.x, self.f, self.y, self.y_pair, self.g, self.d,
                                   self.ensure_mask(), nsweeps)

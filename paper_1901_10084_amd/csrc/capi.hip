@@ -110,7 +110,13 @@ struct cc_ctx {
     int64_t nblocks = 0;
     uint32_t kmax = 0;
     uint32_t epoch = 0;
-    int df_grid = 0;
+    // workgroups of the dataflow sweeps: a fixed count (0: the defaults),
+    // the defaults of the dense and of the sparse / compacted sweeps, and
+    // the most that are resident at once (occupancy x CUs, one per tile)
+    int df_grid_fixed = 0;
+    int df_grid_dense = 0;
+    int df_grid_sparse = 0;
+    int df_grid_cap = 0;
     int aty_grid = 0;
     uint64_t wait_ticks = 0;
     float *d_mean_deg = nullptr;  // warm-start features
@@ -204,10 +210,18 @@ int sweep_t(cc_ctx *c, T *x, T *f, T *y, T *yp, const T *g, const DT *d, int nsw
     return CC_OK;
 }
 
+// tile sizes with a dataflow kernel (the round-by-round executor takes any b)
+bool dataflow_b(int b) { return b == 8 || b == 16 || b == 24 || b == 32; }
+
+// workgroups of a dataflow sweep (tables built)
+int df_grid(const cc_ctx *c, bool dense) {
+    if (c->df_grid_fixed > 0) return std::min(c->df_grid_fixed, c->df_grid_cap);
+    return dense ? c->df_grid_dense : c->df_grid_sparse;
+}
+
 int ensure_dataflow(cc_ctx *c) {
     if (c->d_dtiles) return CC_OK;
-    if (c->b != 8 && c->b != 16 && c->b != 32)
-        return fail(CC_EINVAL, "the dataflow executor supports b = 8, 16 and 32");
+    if (!dataflow_b(c->b)) return fail(CC_EINVAL, "the dataflow executor supports b = 8, 16, 24 and 32");
     std::vector<DTile> tiles;
     std::vector<uint32_t> needs, K;
     build_dataflow_tables(c->n, c->b, tiles, needs, K);
@@ -241,7 +255,17 @@ int ensure_dataflow(cc_ctx *c) {
     const int64_t nbl = c->nb;
     const int64_t useful = std::max<int64_t>(1, (nbl + 1) * (nbl + 2) / 24);
     const int64_t need_per_cu = std::max<int64_t>(1, (useful + cus - 1) / cus);
-    c->df_grid = int(std::min<int64_t>(c->ntiles, std::min<int64_t>(per_cu, need_per_cu) * cus));
+    // The sparse and compacted sweeps wait on load latency and gain from
+    // every resident workgroup up to that bound.  The dense sweep streams
+    // every dual, and more workgroups per CU than these (measured on
+    // MI355X over n = 500..4000) contend for HBM and L2 and run slower:
+    // b = 8: 4; b = 16: 2 in FP32, 1 in FP64; b = 24, 32: 1.
+    const int dense_per_cu = c->b == 8 ? 4 : (c->b == 16 ? (c->prec == CC_F64 ? 1 : 2) : 1);
+    c->df_grid_sparse = int(std::min<int64_t>(c->ntiles, std::min<int64_t>(per_cu, need_per_cu) * cus));
+    c->df_grid_dense = int(std::min<int64_t>(
+        c->ntiles, std::min<int64_t>(std::min<int64_t>(per_cu, need_per_cu), dense_per_cu) * cus));
+    c->df_grid_cap = int(std::min<int64_t>(c->ntiles, int64_t(per_cu) * cus));
+    c->df_grid_fixed = 0;
     rc = (c->prec == CC_F64) ? aty_dataflow_occupancy<double>(c->b, &per_cu)
                              : aty_dataflow_occupancy<float>(c->b, &per_cu);
     if (rc) return rc;
@@ -304,7 +328,9 @@ int sweep_metric_t(cc_ctx *c, T *x, T *y, const T *g, int exec, unsigned long lo
     DataflowArgs a;
     int rc = dataflow_args(c, prof, a);
     if (rc) return rc;
-    if ((rc = launch_sweep_dataflow<T>(a, c->df_grid, c->b, c->n, x, g, y, mask, nullptr, c->stream))) return rc;
+    if ((rc = launch_sweep_dataflow<T>(a, df_grid(c, mask == nullptr), c->b, c->n, x, g, y, mask, nullptr,
+                                       c->stream)))
+        return rc;
     c->epoch++;
     return CC_OK;
 }
@@ -324,7 +350,7 @@ int aty_t(cc_ctx *c, const T *y) {
     int rc = ensure_ax(c);
     if (rc) return rc;
     CCP_HIP_CHECK(hipMemsetAsync(c->d_ax, 0, size_t(num_pairs(c->n)) * sizeof(double), c->stream));
-    if (c->b == 8 || c->b == 16 || c->b == 32) {
+    if (dataflow_b(c->b)) {
         DataflowArgs a;
         if ((rc = dataflow_args(c, nullptr, a))) return rc;
         if ((rc = launch_aty_dataflow<T>(a, c->aty_grid, c->b, c->n, y, c->d_ax, c->stream))) return rc;
@@ -646,8 +672,8 @@ int cc_l1_sweep(cc_ctx *c, void *x, void *f, void *y, void *yp, const void *g, c
         (rc = need(yp, "y_pair")) || (rc = need(g, "g")) || (rc = need(dv, "d")))
         return rc;
     if (nsweeps < 0) return fail(CC_EINVAL, "nsweeps must be >= 0");
-    const bool df = (c->b == 8 || c->b == 16 || c->b == 32);
-    if (mask && !df) return fail(CC_EINVAL, "sparse sweeps need b = 8, 16 or 32");
+    const bool df = dataflow_b(c->b);
+    if (mask && !(c->b == 8 || c->b == 16 || c->b == 32)) return fail(CC_EINVAL, "sparse sweeps need b = 8, 16 or 32");
     if (mask && int64_t(c->nb) * 3 * c->b * c->b * c->b * int64_t(elem_size(c)) >= (int64_t(1) << 31))
         return fail(CC_EINVAL, "sparse sweeps address a tile's duals with 31-bit offsets: n too large for b");
     if (c->prec == CC_F64) {
@@ -712,7 +738,8 @@ int sweep_compact_t(cc_ctx *c, T *x, T *f, T *yp, const T *g, const uint8_t *d, 
             const CompactArgs<T> ca{c->cp_idx[in], static_cast<const T *>(c->cp_val[in]), c->cp_off[in],
                                     c->cp_cnt[in], c->cp_idx[out], static_cast<T *>(c->cp_val[out]),
                                     c->cp_off[out], c->cp_cnt[out], c->cp_alloc, c->cp_cap[out], c->cp_flag};
-            if ((rc = launch_sweep_dataflow<T>(a, c->df_grid, c->b, c->n, x, g, nullptr, nullptr, &ca, c->stream)))
+            if ((rc = launch_sweep_dataflow<T>(a, df_grid(c, false), c->b, c->n, x, g, nullptr, nullptr, &ca,
+                                               c->stream)))
                 return rc;
             c->epoch++;
             if ((rc = check_dataflow(c))) return rc;
@@ -890,6 +917,16 @@ int cc_sweep_colour(cc_ctx *c, void *x, void *f, void *y_lex, void *yp, const vo
     return CC_OK;
 }
 
+int cc_set_dataflow_workgroups(cc_ctx *c, int32_t workgroups, int32_t *effective) {
+    int rc;
+    if ((rc = check_ctx(c))) return rc;
+    if (workgroups < 0) return fail(CC_EINVAL, "workgroups must be >= 0");
+    if ((rc = ensure_dataflow(c))) return rc;
+    c->df_grid_fixed = workgroups;
+    if (effective) *effective = df_grid(c, true);
+    return CC_OK;
+}
+
 int cc_dataflow_breakdown(cc_ctx *c, void *x, void *y, const void *g, double *out) {
     int rc;
     if ((rc = check_ctx(c)) || (rc = need(x, "x")) || (rc = need(y, "y")) || (rc = need(g, "g")) ||
@@ -913,7 +950,7 @@ int cc_dataflow_breakdown(cc_ctx *c, void *x, void *y, const void *g, double *ou
     const double us = 1e3 / double(khz > 0 ? khz : 100000);
     for (int e = 0; e < 4; ++e) out[e] = double(h[e]) * us;
     out[4] = double(h[4]);
-    out[5] = double(c->df_grid);
+    out[5] = double(df_grid(c, true));
     return CC_OK;
 }
 
@@ -1259,7 +1296,7 @@ int sweep_to_tol(cc_ctx *c, void *x, void *f, void *y, void *yp, void *g, const 
                  const double *w, double gamma, double tol, double gap_tol, int max_sweeps,
                  int *done, cc_resid *r, bool sparse) {
     const int every = c->n <= 1000 ? 1 : 5;
-    const int exec = (c->b == 8 || c->b == 16 || c->b == 32) ? CC_EXEC_DATAFLOW : CC_EXEC_ROUNDS;
+    const int exec = dataflow_b(c->b) ? CC_EXEC_DATAFLOW : CC_EXEC_ROUNDS;
     DevBuf mask;
     if (sparse) {
         int rc;

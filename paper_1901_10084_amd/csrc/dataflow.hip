@@ -50,6 +50,9 @@ template <int B> struct MaskWord;
 template <> struct MaskWord<8> { using type = uint8_t; };
 template <> struct MaskWord<16> { using type = uint16_t; };
 template <> struct MaskWord<32> { using type = uint32_t; };
+// b = 24 has the dense sweep only; the type fills the kernel's signature.
+template <> struct MaskWord<24> { using type = uint32_t; };
+template <int B> constexpr bool kSparseB = (B == 8 || B == 16 || B == 32);
 
 // Bit pattern of a dual: the mask marks every slot whose bits are not those
 // of +0.0 (a -0.0 counts as nonzero), so an unmarked slot reads back exactly.
@@ -192,6 +195,7 @@ k_sweep_dataflow(DataflowArgs a, int64_t n, T *__restrict__ x, const T *__restri
                  T *__restrict__ y, typename MaskWord<B>::type *__restrict__ mask, CompactArgs<T> cp) {
     using MW = typename MaskWord<B>::type;
     static_assert(!CP || (!SP && B <= 16), "compacted lists: b = 8 or 16, 16-bit slot indices");
+    static_assert(!SP || kSparseB<B>, "sparse dual access: one mask word of b bits per lane");
     // the first and last groups of D sub-steps are peeled: refills of the
     // other groups stay inside the step
     static_assert(B % D == 0 && B >= 2 * D, "ring depth must divide b, twice at least");
@@ -892,8 +896,12 @@ static int launch_df_t(const DataflowArgs &a, int grid, int64_t n, T *x, const T
             return fail(CC_EINVAL, "compacted dual lists need b = 8 or 16");
         }
     } else if (mask) {
-        hipLaunchKernelGGL((k_sweep_dataflow<T, B, D, true, false>), dim3(grid), dim3(B * B), lds, s, a, n, x, g,
-                           y, static_cast<MW *>(mask), CompactArgs<T>{});
+        if constexpr (kSparseB<B>) {
+            hipLaunchKernelGGL((k_sweep_dataflow<T, B, D, true, false>), dim3(grid), dim3(B * B), lds, s, a, n, x,
+                               g, y, static_cast<MW *>(mask), CompactArgs<T>{});
+        } else {
+            return fail(CC_EINVAL, "sparse dual access needs b = 8, 16 or 32");
+        }
     } else {
         hipLaunchKernelGGL((k_sweep_dataflow<T, B, D, false, false>), dim3(grid), dim3(B * B), lds, s, a, n, x, g,
                            y, static_cast<MW *>(nullptr), CompactArgs<T>{});
@@ -910,8 +918,9 @@ int launch_sweep_dataflow(const DataflowArgs &a, int grid, int b, int64_t n, T *
     switch (b) {
         case 8: return launch_df_t<T, 8, 4>(a, grid, n, x, g, y, mask, cp, s);
         case 16: return launch_df_t<T, 16, 8>(a, grid, n, x, g, y, mask, cp, s);
+        case 24: return launch_df_t<T, 24, 8>(a, grid, n, x, g, y, mask, cp, s);
         case 32: return launch_df_t<T, 32, 4>(a, grid, n, x, g, y, mask, cp, s);
-        default: return fail(CC_EINVAL, "the dataflow executor supports b = 8, 16, 32");
+        default: return fail(CC_EINVAL, "the dataflow executor supports b = 8, 16, 24, 32");
     }
 }
 
@@ -1001,6 +1010,10 @@ int dataflow_occupancy(int b, int *blocks_per_cu) {
             if (e == hipSuccess) e = hipFuncSetAttribute((const void *)k_sweep_dataflow<T, 16, 8, true, false>, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
             if (e == hipSuccess) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, k_sweep_dataflow<T, 16, 8, false, false>, 256, lds);
             break;
+        case 24:
+            e = hipFuncSetAttribute((const void *)k_sweep_dataflow<T, 24, 8, false, false>, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+            if (e == hipSuccess) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, k_sweep_dataflow<T, 24, 8, false, false>, 576, lds);
+            break;
         case 32:
             e = hipFuncSetAttribute((const void *)k_sweep_dataflow<T, 32, 4, false, false>, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
             if (e == hipSuccess) e = hipFuncSetAttribute((const void *)k_sweep_dataflow<T, 32, 4, true, false>, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
@@ -1030,8 +1043,9 @@ int launch_aty_dataflow(const DataflowArgs &a, int grid, int b, int64_t n, const
     switch (b) {
         case 8: return launch_aty_df_t<T, 8, 4>(a, grid, n, y, ax, s);
         case 16: return launch_aty_df_t<T, 16, 8>(a, grid, n, y, ax, s);
+        case 24: return launch_aty_df_t<T, 24, 8>(a, grid, n, y, ax, s);
         case 32: return launch_aty_df_t<T, 32, 4>(a, grid, n, y, ax, s);
-        default: return fail(CC_EINVAL, "the dataflow executor supports b = 8, 16, 32");
+        default: return fail(CC_EINVAL, "the dataflow executor supports b = 8, 16, 24, 32");
     }
 }
 
@@ -1041,6 +1055,7 @@ int aty_dataflow_occupancy(int b, int *blocks_per_cu) {
     switch (b) {
         case 8: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, k_aty_dataflow<T, 8, 4>, 64, 0); break;
         case 16: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, k_aty_dataflow<T, 16, 8>, 256, 0); break;
+        case 24: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, k_aty_dataflow<T, 24, 8>, 576, 0); break;
         case 32: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, k_aty_dataflow<T, 32, 4>, 1024, 0); break;
         default: *blocks_per_cu = 0; return CC_OK;
     }

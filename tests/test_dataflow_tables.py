@@ -89,7 +89,8 @@ def simulate(tab, b, nb, workers, sweeps=2):
 
 
 @pytest.mark.parametrize("n,b,workers", [(20, 8, 1), (20, 8, 3), (61, 8, 5), (70, 16, 2),
-                                         (100, 8, 16), (47, 16, 64), (33, 8, 4), (65, 32, 3)])
+                                         (100, 8, 16), (47, 16, 64), (33, 8, 4), (65, 32, 3),
+                                         (50, 24, 2), (73, 24, 5)])
 def test_dataflow_tables_respect_the_schedule(n, b, workers):
     from paper_1901_10084_amd import ccproj as C
     tab = C.dataflow_tables(n, b)

@@ -52,6 +52,7 @@ CASES = [
     (lambda: I.random_signed(37, seed=3, gamma=2.0, weighted=True), 8, 4),
     (lambda: I.random_signed(45, seed=4, gamma=1.0, weighted=False), 5, 3),
     (lambda: I.random_signed(70, seed=5, gamma=3.0, weighted=True), 32, 2),
+    (lambda: I.random_signed(50, seed=9, gamma=2.0, weighted=True), 24, 3),  # b = 24, ragged tail of 2
     (lambda: I.random_signed(5, seed=6, gamma=1.0, weighted=True), 8, 6),    # one tile
     (lambda: I.random_signed(3, seed=7, gamma=1.0, weighted=True), 1, 10),   # one triplet
     (lambda: I.random_signed(17, seed=8, gamma=1.0, weighted=True), 1, 3),   # b = 1: Fig. 2
@@ -153,9 +154,9 @@ def test_residuals_and_x_from_y(prec):
 
 
 @pytest.mark.parametrize("n,b,prec", [(45, 8, "f64"), (70, 16, "f64"), (100, 32, "f64"),
-                                      (70, 16, "f32")])
+                                      (70, 16, "f32"), (73, 24, "f64")])
 def test_x_from_y_dataflow(n, b, prec):
-    """A'y runs on the dataflow schedule for b = 8, 16, 32: equal to the
+    """A'y runs on the dataflow schedule for b = 8, 16, 24, 32: equal to the
     oracle's x(y), and the same bits on every call (fixed summation order)."""
     inst = I.random_signed(n, seed=n + b, gamma=1.5, weighted=True)
     g = C.Solver.from_instance(inst, b=b, prec=prec)
@@ -239,7 +240,8 @@ def test_duals_nonnegative_and_stationary():
                                         (16, 16, "f64", 2), (17, 16, "f32", 2), (33, 32, "f64", 2),
                                         (500, 16, "f64", 2), (300, 8, "f32", 2),
                                         (1000, 32, "f32", 1), (200, 8, "f64", 10),
-                                        (600, 16, "f32", 5)])
+                                        (600, 16, "f32", 5), (50, 24, "f64", 3), (97, 24, "f32", 2),
+                                        (24, 24, "f64", 2), (500, 24, "f64", 2)])
 def test_dataflow_equals_rounds(n, b, prec, K):
     inst = I.workload(1) if n == 500 else I.random_signed(n, seed=n, gamma=2.0, weighted=True)
     print(f"dataflow n={n} b={b} {prec} K={K}", flush=True)
@@ -251,6 +253,30 @@ def test_dataflow_equals_rounds(n, b, prec, K):
     for name in ("x", "f", "y", "y_pair"):
         a, bb = getattr(r, name), getattr(d, name)
         assert torch.equal(a, bb), (name, float((a - bb).abs().max()))
+
+
+@pytest.mark.parametrize("n,b,prec", [(100, 16, "f64"), (130, 24, "f32"), (70, 8, "f64")])
+def test_dataflow_workgroup_count_leaves_results_unchanged(n, b, prec):
+    """Any number of workgroups gives the default sweep's bits: one
+    workgroup runs the tiles one after another in schedule order; a request
+    above what the GPU holds at once is capped."""
+    inst = I.random_signed(n, seed=n + b, gamma=2.0, weighted=True)
+    ref = C.Solver.from_instance(inst, b=b, prec=prec)
+    ref.sweep(3, C.CC_EXEC_DATAFLOW)
+    ref.status()
+    default = ref.ctx.set_dataflow_workgroups(0)
+    assert default >= 1
+    for wg in (1, 2, 7, 1 << 20):
+        s = C.Solver.from_instance(inst, b=b, prec=prec)
+        eff = s.ctx.set_dataflow_workgroups(wg)
+        assert eff == wg if wg < default else 1 <= eff <= max(wg, default)
+        print(f"workgroups n={n} b={b} {prec}: asked {wg}, ran {eff}", flush=True)
+        s.sweep(3, C.CC_EXEC_DATAFLOW)
+        s.status()
+        for name in ("x", "f", "y", "y_pair"):
+            assert torch.equal(getattr(ref, name), getattr(s, name)), (wg, name)
+    with pytest.raises(C.CCError):
+        ref.ctx.set_dataflow_workgroups(-1)
 
 
 def test_dataflow_breakdown_counts_every_step():
