@@ -413,7 +413,7 @@ def tile_report(cases=((1, "f64", (8, 16, 24, 32)), (2, "f32", (8, 16, 24, 32)),
                        (4, "f32", (16, 24, 32))), steps=5):
     """The GPU counterpart of the paper's tile-size curve (Fig. 6): one
     metric sweep (dense, and with sparse dual access after 20 sweeps into a
-    solve; b = 24 has no sparse form) per tile size b on each workload, HIP
+    solve) per tile size b on each workload, HIP
     events around `steps` launches after 2, with the number of tiles that
     can run at once on average, about (nb+1)(nb+2)/24 for nb = ceil(n/b),
     against the chip's 256 compute units."""
@@ -428,7 +428,7 @@ def tile_report(cases=((1, "f64", (8, 16, 24, 32)), (2, "f32", (8, 16, 24, 32)),
             row = {"workload": inst.name, "n": inst.n, "prec": prec, "b": b,
                    "tiles_in_flight": (-(-inst.n // b) + 1) * (-(-inst.n // b) + 2) / 24}
             s.sweep(20)
-            for sp in ((False, True) if b != 24 else (False,)):
+            for sp in (False, True):
                 s.sweep_metric(sparse=sp)
                 s.sweep_metric(sparse=sp)
                 torch.cuda.synchronize()

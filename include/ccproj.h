@@ -157,7 +157,8 @@ int cc_sweep_metric(cc_ctx *ctx, void *x, void *y, const void *g, int32_t exec);
  * with one bit per dual slot marks the slots that may hold a nonzero dual.
  * Layout: tile step c (the steps of the tiles in schedule order, each tile's
  * steps in order) owns 3 b^2 words of b bits (uint8 for b = 8, uint16 for
- * 16, uint32 for 32); bit t of word [c][o][il*b + kl] belongs to dual slot
+ * 16, uint32 for 24 and 32; at b = 24 the top 8 bits stay clear); bit t of
+ * word [c][o][il*b + kl] belongs to dual slot
  * [c][t][o][il*b + kl] of y.  Invariant: a clear bit means the slot holds
  * +0.0 (bit pattern).  The sparse sweeps keep it (they store a dual only
  * where its bits changed and rewrite the mask); any other writer of y
@@ -165,16 +166,17 @@ int cc_sweep_metric(cc_ctx *ctx, void *x, void *y, const void *g, int32_t exec);
  * cc_dual_mask_build is called again.  A stale mask gives wrong results,
  * not a fault: every access stays inside y and the mask.
  *
- * Bytes of the mask: cc_dual_slots / 8; -1 unless b is 8, 16 or 32. */
+ * Bytes of the mask: cc_dual_slots / 8 (cc_dual_slots / 6 at b = 24); -1
+ * unless b is 8, 16, 24 or 32. */
 int64_t cc_dual_mask_bytes(const cc_ctx *ctx);
 
 /* mask = nonzero pattern of y (device, cc_dual_mask_bytes bytes, caller
- * owned).  One read of y.  Enqueues only.  CC_EINVAL unless b = 8, 16, 32. */
+ * owned).  One read of y.  Enqueues only.  CC_EINVAL unless b = 8, 16, 24, 32. */
 int cc_dual_mask_build(cc_ctx *ctx, const void *y, void *mask);
 
 /* nsweeps full sweeps on the dataflow executor (as cc_sweep with
  * CC_EXEC_DATAFLOW), reading only the marked duals and storing only changed
- * ones.  x, f, y, y_pair equal cc_sweep's bit for bit.  Needs b = 8, 16, 32
+ * ones.  x, f, y, y_pair equal cc_sweep's bit for bit.  Needs b = 8, 16, 24, 32
  * and a mask that satisfies the invariant above.  Enqueues only. */
 int cc_sweep_sparse(cc_ctx *ctx, void *x, void *f, void *y, void *y_pair, const void *g,
                     const uint8_t *d, void *mask, int32_t nsweeps);
@@ -230,7 +232,7 @@ int cc_compact_release(cc_ctx *ctx);
  * dv: device double[N_p].
  *
  * nsweeps full sweeps (metric rounds, then the pair pass with real d): the
- * dataflow executor for b = 8, 16, 24, 32 (with mask, for b = 8, 16, 32:
+ * dataflow executor for b = 8, 16, 24, 32 (with mask:
  * sparse dual access, see cc_sweep_sparse), else the round executor (mask
  * must be NULL).
  * Enqueues only. */
@@ -442,7 +444,7 @@ int cc_warm_start_mlp(cc_ctx *ctx, const float *params, const float *deg, const 
  * CC_MODE_F64, CC_MODE_F32 (FP32 sweeps to tol)
  * or CC_MODE_F32_POLISH (FP32 sweeps to max(tol, 1e-4), then duals widened,
  * x recomputed from them in FP64 and FP64 sweeps to tol), or-ed with
- * CC_MODE_SPARSE for sparse dual access (b = 8, 16, 32; same results, the
+ * CC_MODE_SPARSE for sparse dual access (b = 8, 16, 24, 32; same results, the
  * mask allocated and built per phase); warm: CC_WARM_NONE
  * or CC_WARM_MLP (then mlp_weights_host must point to cc_mlp_num_params()
  * floats and deg_host to n floats; see cc_warm_start_mlp for the gate;

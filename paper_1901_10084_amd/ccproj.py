@@ -223,7 +223,7 @@ class Context:
     def mask_bytes(self) -> int:
         nbytes = _L.cc_dual_mask_bytes(self._h)
         if nbytes < 0:
-            raise CCError(CC_EINVAL, "sparse dual access needs b = 8, 16 or 32")
+            raise CCError(CC_EINVAL, "sparse dual access needs b = 8, 16, 24 or 32")
         return nbytes
 
     def mask_build(self, y, mask):
@@ -375,8 +375,8 @@ class Solver:
 
     def sweep(self, nsweeps=1, executor=None, sparse=False):
         """nsweeps sweeps; sparse=True reads only the duals the mask marks
-        (dataflow executor, b = 8, 16, 32; the same results bit for bit).
-        The dataflow executor also runs b = 24, without sparse access."""
+        (dataflow executor, b = 8, 16, 24, 32; the same results bit for
+        bit)."""
         if sparse:
             self.ctx.sweep_sparse(self.x, self.f, self.y, self.y_pair, self.g, self.d,
                                   self.ensure_mask(), nsweeps)

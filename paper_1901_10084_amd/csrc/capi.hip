@@ -623,8 +623,9 @@ int cc_sweep_metric(cc_ctx *c, void *x, void *y, const void *g, int32_t exec) {
 }
 
 int64_t cc_dual_mask_bytes(const cc_ctx *c) {
-    if (!c || !(c->b == 8 || c->b == 16 || c->b == 32)) return -1;
-    return c->slots / 8;
+    if (!c || !dataflow_b(c->b)) return -1;
+    // one word per b slots: b / 8 bytes, 4 for b = 24
+    return c->slots / c->b * (c->b == 24 ? 4 : c->b / 8);
 }
 
 int cc_dual_mask_build(cc_ctx *c, const void *y, void *mask) {
@@ -642,7 +643,7 @@ int cc_sweep_sparse(cc_ctx *c, void *x, void *f, void *y, void *yp, const void *
         (rc = need(yp, "y_pair")) || (rc = need(g, "g")) || (rc = need(d, "d")) || (rc = need(mask, "mask")))
         return rc;
     if (nsweeps < 0) return fail(CC_EINVAL, "nsweeps must be >= 0");
-    if (!(c->b == 8 || c->b == 16 || c->b == 32)) return fail(CC_EINVAL, "sparse sweeps need b = 8, 16 or 32");
+    if (!dataflow_b(c->b)) return fail(CC_EINVAL, "sparse sweeps need b = 8, 16, 24 or 32");
     if (int64_t(c->nb) * 3 * c->b * c->b * c->b * int64_t(elem_size(c)) >= (int64_t(1) << 31))
         return fail(CC_EINVAL, "sparse sweeps address a tile's duals with 31-bit offsets: n too large for b");
     if (c->prec == CC_F64)
@@ -657,7 +658,7 @@ int cc_sweep_metric_sparse(cc_ctx *c, void *x, void *y, const void *g, void *mas
     if ((rc = check_ctx(c)) || (rc = need(x, "x")) || (rc = need(y, "y")) || (rc = need(g, "g")) ||
         (rc = need(mask, "mask")))
         return rc;
-    if (!(c->b == 8 || c->b == 16 || c->b == 32)) return fail(CC_EINVAL, "sparse sweeps need b = 8, 16 or 32");
+    if (!dataflow_b(c->b)) return fail(CC_EINVAL, "sparse sweeps need b = 8, 16, 24 or 32");
     if (int64_t(c->nb) * 3 * c->b * c->b * c->b * int64_t(elem_size(c)) >= (int64_t(1) << 31))
         return fail(CC_EINVAL, "sparse sweeps address a tile's duals with 31-bit offsets: n too large for b");
     if (c->prec == CC_F64)
@@ -673,7 +674,7 @@ int cc_l1_sweep(cc_ctx *c, void *x, void *f, void *y, void *yp, const void *g, c
         return rc;
     if (nsweeps < 0) return fail(CC_EINVAL, "nsweeps must be >= 0");
     const bool df = dataflow_b(c->b);
-    if (mask && !(c->b == 8 || c->b == 16 || c->b == 32)) return fail(CC_EINVAL, "sparse sweeps need b = 8, 16 or 32");
+    if (mask && !df) return fail(CC_EINVAL, "sparse sweeps need b = 8, 16, 24 or 32");
     if (mask && int64_t(c->nb) * 3 * c->b * c->b * c->b * int64_t(elem_size(c)) >= (int64_t(1) << 31))
         return fail(CC_EINVAL, "sparse sweeps address a tile's duals with 31-bit offsets: n too large for b");
     if (c->prec == CC_F64) {
@@ -1341,8 +1342,8 @@ extern "C" int cc_solve_cc_lp(int64_t n, const double *w_host, const uint8_t *d_
     mode &= ~CC_MODE_SPARSE;
     if (mode != CC_MODE_F64 && mode != CC_MODE_F32 && mode != CC_MODE_F32_POLISH)
         return fail(CC_EINVAL, "unknown mode");
-    if (sparse && !(b == 8 || b == 16 || b == 32))
-        return fail(CC_EINVAL, "CC_MODE_SPARSE needs b = 8, 16 or 32");
+    if (sparse && !dataflow_b(b))
+        return fail(CC_EINVAL, "CC_MODE_SPARSE needs b = 8, 16, 24 or 32");
     if (warm != CC_WARM_NONE && warm != CC_WARM_MLP) return fail(CC_EINVAL, "unknown warm start");
     if (warm == CC_WARM_MLP && (!mlp_weights_host || !deg_host))
         return fail(CC_EINVAL, "warm start needs network weights and degrees");

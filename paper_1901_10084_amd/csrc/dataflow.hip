@@ -50,9 +50,9 @@ template <int B> struct MaskWord;
 template <> struct MaskWord<8> { using type = uint8_t; };
 template <> struct MaskWord<16> { using type = uint16_t; };
 template <> struct MaskWord<32> { using type = uint32_t; };
-// b = 24 has the dense sweep only; the type fills the kernel's signature.
+// b = 24: 24 bits of a 32-bit word, the top 8 always clear.
 template <> struct MaskWord<24> { using type = uint32_t; };
-template <int B> constexpr bool kSparseB = (B == 8 || B == 16 || B == 32);
+template <int B> constexpr bool kSparseB = (B == 8 || B == 16 || B == 24 || B == 32);
 
 // Bit pattern of a dual: the mask marks every slot whose bits are not those
 // of +0.0 (a -0.0 counts as nonzero), so an unmarked slot reads back exactly.
@@ -867,8 +867,9 @@ int launch_mask_build(int b, int64_t nsteps, const T *y, void *mask, hipStream_t
     switch (b) {
         case 8: return launch_mask_build_t<T, 8>(nsteps, y, mask, s);
         case 16: return launch_mask_build_t<T, 16>(nsteps, y, mask, s);
+        case 24: return launch_mask_build_t<T, 24>(nsteps, y, mask, s);
         case 32: return launch_mask_build_t<T, 32>(nsteps, y, mask, s);
-        default: return fail(CC_EINVAL, "sparse dual access supports b = 8, 16, 32");
+        default: return fail(CC_EINVAL, "sparse dual access supports b = 8, 16, 24, 32");
     }
 }
 
@@ -876,6 +877,11 @@ template <typename T>
 size_t dataflow_lds_bytes(int b) {
     return size_t(6) * b * b * sizeof(T);
 }
+
+// Ring depth of the sparse sweep: at b = 24 (576 threads, at most 168
+// VGPRs a lane) the mask state does not fit beside a ring of 8 sub-steps
+// without spilling, so it keeps 4.
+template <int B, int D> constexpr int sparse_ring() { return B == 24 ? 4 : D; }
 
 template <typename T, int B, int D>
 static int launch_df_t(const DataflowArgs &a, int grid, int64_t n, T *x, const T *g, T *y,
@@ -897,10 +903,10 @@ static int launch_df_t(const DataflowArgs &a, int grid, int64_t n, T *x, const T
         }
     } else if (mask) {
         if constexpr (kSparseB<B>) {
-            hipLaunchKernelGGL((k_sweep_dataflow<T, B, D, true, false>), dim3(grid), dim3(B * B), lds, s, a, n, x,
-                               g, y, static_cast<MW *>(mask), CompactArgs<T>{});
+            hipLaunchKernelGGL((k_sweep_dataflow<T, B, sparse_ring<B, D>(), true, false>), dim3(grid), dim3(B * B),
+                               lds, s, a, n, x, g, y, static_cast<MW *>(mask), CompactArgs<T>{});
         } else {
-            return fail(CC_EINVAL, "sparse dual access needs b = 8, 16 or 32");
+            return fail(CC_EINVAL, "sparse dual access needs b = 8, 16, 24 or 32");
         }
     } else {
         hipLaunchKernelGGL((k_sweep_dataflow<T, B, D, false, false>), dim3(grid), dim3(B * B), lds, s, a, n, x, g,
@@ -1012,6 +1018,7 @@ int dataflow_occupancy(int b, int *blocks_per_cu) {
             break;
         case 24:
             e = hipFuncSetAttribute((const void *)k_sweep_dataflow<T, 24, 8, false, false>, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+            if (e == hipSuccess) e = hipFuncSetAttribute((const void *)k_sweep_dataflow<T, 24, 4, true, false>, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
             if (e == hipSuccess) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, k_sweep_dataflow<T, 24, 8, false, false>, 576, lds);
             break;
         case 32:

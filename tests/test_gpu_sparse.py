@@ -29,8 +29,11 @@ def steps_of(ctx_b, y):
 def decode_mask(mask, b, nsteps):
     """Bits of the mask as a bool tensor shaped like the duals:
     [step][sub-step t][orientation o][lane]."""
-    wt = {8: torch.uint8, 16: torch.int16, 32: torch.int32}[b]
-    words = mask.view(wt).to(torch.int64) & ((1 << b) - 1)
+    wt = {8: torch.uint8, 16: torch.int16, 24: torch.int32, 32: torch.int32}[b]
+    raw = mask.view(wt).to(torch.int64)
+    if b == 24:
+        assert not torch.any((raw >> 24) & 0xFF)  # the unused top bits stay clear
+    words = raw & ((1 << b) - 1)
     words = words.view(nsteps, 3, b * b)
     t = torch.arange(b, device=mask.device).view(1, b, 1, 1)
     return ((words.unsqueeze(1) >> t) & 1).bool()
@@ -56,7 +59,7 @@ def assert_same_state(a, b_):
 
 def test_mask_build_is_the_nonzero_pattern():
     inst = I.workload(0)
-    for b, prec in ((8, "f64"), (16, "f32"), (32, "f64")):
+    for b, prec in ((8, "f64"), (16, "f32"), (24, "f32"), (32, "f64")):
         s = C.Solver.from_instance(inst, b=b, prec=prec)
         g = torch.Generator(device="cpu").manual_seed(b)
         vals = torch.rand(s.y.numel(), generator=g, dtype=torch.float64)
@@ -67,14 +70,15 @@ def test_mask_build_is_the_nonzero_pattern():
         s.invalidate_mask()
         s.ensure_mask()
         torch.cuda.synchronize()
-        assert s.mask.numel() == s.y.numel() // 8
+        assert s.mask.numel() == s.y.numel() // b * {8: 1, 16: 2, 24: 4, 32: 4}[b]
         assert_mask_is_pattern(s)
 
 
 @pytest.mark.parametrize("wl,n,b,prec,K", [
     (None, 40, 8, "f64", 3), (None, 33, 16, "f64", 4), (None, 70, 16, "f32", 3),
     (None, 65, 32, "f64", 3), (None, 100, 32, "f32", 3), (None, 300, 16, "f64", 4),
-    (1, 500, 16, "f64", 3), (None, 1000, 32, "f32", 2)])
+    (1, 500, 16, "f64", 3), (None, 1000, 32, "f32", 2), (None, 50, 24, "f64", 3),
+    (None, 97, 24, "f32", 3), (1, 500, 24, "f64", 2)])
 def test_sparse_sweeps_equal_dense(wl, n, b, prec, K):
     inst = I.workload(wl) if wl is not None else I.random_signed(n, seed=n, gamma=3.0)
     print(f"sparse vs dense n={inst.n} b={b} {prec} K={K}", flush=True)
@@ -142,7 +146,8 @@ def test_sparse_flag_rejects_unsupported_tile_sizes():
         s.sweep(1, sparse=True)
 
 
-@pytest.mark.parametrize("n,b,prec", [(60, 8, "f64"), (90, 16, "f64"), (130, 32, "f32")])
+@pytest.mark.parametrize("n,b,prec", [(60, 8, "f64"), (90, 16, "f64"), (130, 32, "f32"),
+                                      (75, 24, "f64")])
 def test_nearness_sparse_equals_dense(n, b, prec):
     inst = I.noisy_distances(n, seed=4, noise=0.6)
     dense = C.NearnessSolver.from_instance(inst, b=b, prec=prec)
