@@ -878,10 +878,13 @@ size_t dataflow_lds_bytes(int b) {
     return size_t(6) * b * b * sizeof(T);
 }
 
-// Ring depth of the sparse sweep: at b = 24 (576 threads, at most 168
-// VGPRs a lane) the mask state does not fit beside a ring of 8 sub-steps
-// without spilling, so it keeps 4.
-template <int B, int D> constexpr int sparse_ring() { return B == 24 ? 4 : D; }
+// Ring depth of the sparse sweep: the mask state does not fit beside the
+// dense sweep's ring without spilling at b = 24 (576 threads, at most 168
+// VGPRs a lane; a ring of 8 sub-steps) nor at b = 32 in FP64 (1024
+// threads, at most 128; a ring of 4), so those keep 4 and 2.
+template <typename T, int B, int D> constexpr int sparse_ring() {
+    return B == 24 ? 4 : (B == 32 && sizeof(T) == 8 ? 2 : D);
+}
 
 template <typename T, int B, int D>
 static int launch_df_t(const DataflowArgs &a, int grid, int64_t n, T *x, const T *g, T *y,
@@ -903,7 +906,7 @@ static int launch_df_t(const DataflowArgs &a, int grid, int64_t n, T *x, const T
         }
     } else if (mask) {
         if constexpr (kSparseB<B>) {
-            hipLaunchKernelGGL((k_sweep_dataflow<T, B, sparse_ring<B, D>(), true, false>), dim3(grid), dim3(B * B),
+            hipLaunchKernelGGL((k_sweep_dataflow<T, B, sparse_ring<T, B, D>(), true, false>), dim3(grid), dim3(B * B),
                                lds, s, a, n, x, g, y, static_cast<MW *>(mask), CompactArgs<T>{});
         } else {
             return fail(CC_EINVAL, "sparse dual access needs b = 8, 16, 24 or 32");
@@ -1008,22 +1011,22 @@ int dataflow_occupancy(int b, int *blocks_per_cu) {
     switch (b) {
         case 8:
             e = hipFuncSetAttribute((const void *)k_sweep_dataflow<T, 8, 4, false, false>, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
-            if (e == hipSuccess) e = hipFuncSetAttribute((const void *)k_sweep_dataflow<T, 8, 4, true, false>, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+            if (e == hipSuccess) e = hipFuncSetAttribute((const void *)k_sweep_dataflow<T, 8, sparse_ring<T, 8, 4>(), true, false>, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
             if (e == hipSuccess) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, k_sweep_dataflow<T, 8, 4, false, false>, 64, lds);
             break;
         case 16:
             e = hipFuncSetAttribute((const void *)k_sweep_dataflow<T, 16, 8, false, false>, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
-            if (e == hipSuccess) e = hipFuncSetAttribute((const void *)k_sweep_dataflow<T, 16, 8, true, false>, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+            if (e == hipSuccess) e = hipFuncSetAttribute((const void *)k_sweep_dataflow<T, 16, sparse_ring<T, 16, 8>(), true, false>, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
             if (e == hipSuccess) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, k_sweep_dataflow<T, 16, 8, false, false>, 256, lds);
             break;
         case 24:
             e = hipFuncSetAttribute((const void *)k_sweep_dataflow<T, 24, 8, false, false>, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
-            if (e == hipSuccess) e = hipFuncSetAttribute((const void *)k_sweep_dataflow<T, 24, 4, true, false>, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+            if (e == hipSuccess) e = hipFuncSetAttribute((const void *)k_sweep_dataflow<T, 24, sparse_ring<T, 24, 8>(), true, false>, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
             if (e == hipSuccess) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, k_sweep_dataflow<T, 24, 8, false, false>, 576, lds);
             break;
         case 32:
             e = hipFuncSetAttribute((const void *)k_sweep_dataflow<T, 32, 4, false, false>, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
-            if (e == hipSuccess) e = hipFuncSetAttribute((const void *)k_sweep_dataflow<T, 32, 4, true, false>, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+            if (e == hipSuccess) e = hipFuncSetAttribute((const void *)k_sweep_dataflow<T, 32, sparse_ring<T, 32, 4>(), true, false>, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
             if (e == hipSuccess) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, k_sweep_dataflow<T, 32, 4, false, false>, 1024, lds);
             break;
         default:
