@@ -63,8 +63,8 @@ enum { CC_EXEC_ROUNDS = 0, CC_EXEC_DATAFLOW = 1 };       /* sweep executors   */
 
 typedef struct cc_ctx cc_ctx;
 
-/* Convergence measures, all evaluated in FP64 (Sec. IV-D: constraint
- * satisfaction and duality gap).  Fields a solve cannot fill are NaN. */
+/* Convergence measures, all evaluated in FP64 (Sec. IV-D stops on how well
+ * the rows hold and on the primal-dual gap).  Fields a solve cannot fill are NaN. */
 typedef struct {
     double max_viol_metric;  /* max over metric rows of (x_L - x_S1 - x_S2)^+ */
     double max_viol_pair;    /* max over pairs of (|x - d| - f)^+             */

@@ -3,9 +3,10 @@
 Test infrastructure only: the tests, the smoke check and the CPU-baseline leg
 of the benchmark use it to check and time the GPU library; the GPU library
 never loads it and it never loads the GPU library.  The arithmetic lives in
-``ccoracle.c`` (Algorithm 1 taken literally, in the tiled schedule order of
-Sec. III); this file only marshals numpy arrays, plus a float64 reference of
-the warm-start network in ``mlp_ref``.
+``ccoracle.c`` (Algorithm 1 of Sec. II-B, one row at a time as dual
+coordinate ascent, in the tiled schedule order of Sec. III); this file only
+marshals numpy arrays, plus a float64 reference of the warm-start network in
+``mlp_ref``.
 
 Layouts: pairs packed column-major, p(i, j) = j (j - 1) / 2 + i; metric duals
 in colex triplet order y[3 t + o], t = C(k,3) + C(j,2) + i; pair duals

@@ -4,8 +4,7 @@
  *
  * Only the tests, the smoke check and the CPU-baseline leg of the benchmark
  * may load this library.  It shares no code with the GPU library: it is a
- * plain, slow, literal transcription of the method, used to check the GPU
- * path.
+ * plain, slow, serial statement of the method, used to check the GPU path.
  *
  * What it computes (paper, Sec. II-B and Sec. III):
  *   problem (mn1):  min sum_p w_p f_p
@@ -14,9 +13,9 @@
  *                        x_p - d_p <= f_p,  d_p - x_p <= f_p   per pair;
  *   regularised (qp): min c'v + (eps/2) v'Wv  s.t. Av <= b, with v = (x, f),
  *                   c = (0, w), W = diag(w) on both x and f, gamma = 1/eps;
- *   Algorithm 1 (Dykstra = Hildreth): per constraint a correction step, a
- *                   projection step and a dual update, visiting constraints
- *                   cyclically;
+ *   Algorithm 1 (Dykstra = Hildreth): the constraints are visited
+ *                   cyclically, and a visit makes the exact best move of
+ *                   that constraint's dual in the dual of (qp) (visit_row);
  *   visiting order: the tiled block-diagonal schedule of Sec. III-B/C.
  * Other visiting orders (Sec. IV-E: the order changes the iteration count,
  * not the limit): plain lexicographic order, and the sum-mod-n colouring
@@ -161,34 +160,37 @@ int64_t orc_colour_order(int64_t n, int64_t *out, int64_t cap)
 }
 
 /* ------------------------------------------------------------------------ */
-/* Algorithm 1, one constraint at a time.                                    */
+/* One visit of one row (Sec. II-B, Algorithm 1).                            */
 /*                                                                           */
-/* A constraint is a'v <= beta with a sparse row a (entries coef[] at        */
-/* positions var[] of v).  rinv[] holds the matching diagonal entries of     */
-/* W^{-1}.  With gamma = 1/eps the three steps read                          */
-/*   correction:  v += y * gamma * W^{-1} a                                  */
-/*   projection:  theta = max(a'v - beta, 0) / (gamma * a'W^{-1}a),          */
-/*                v -= theta * gamma * W^{-1} a                              */
-/*   dual update: y = theta                                                  */
+/* A row is a'v <= beta with a sparse a (entries coef[] at the variables     */
+/* *v[]) and its dual y >= 0; rinv[] holds the matching diagonal entries of  */
+/* W^{-1}, and gamma = 1/eps.  The iterate always satisfies the stationarity */
+/* condition v = -gamma W^{-1} (c + A'y).  Along this row's dual alone the   */
+/* dual objective of (qp) is then a concave parabola: its slope at the       */
+/* current y is a'v - beta (the row's violation) and its curvature is        */
+/* -gamma a'W^{-1}a.  A visit moves y to the top of that parabola, kept at   */
+/* or above zero, and moves v with it (v changes by -gamma W^{-1}a per unit  */
+/* of y).  This is the point Algorithm 1 reaches through its two steps: the  */
+/* correction adds y gamma W^{-1}a back to v, the projection onto the        */
+/* halfspace takes theta gamma W^{-1}a off again, and theta is the new dual. */
 /* ------------------------------------------------------------------------ */
-static void dykstra_step(double *v[], const double coef[], const double rinv[],
-                         int m, double beta, double *y, double gamma)
+static void visit_row(double *v[], const double coef[], const double rinv[],
+                      int m, double beta, double *y, double gamma)
 {
-    /* correction step */
-    for (int e = 0; e < m; e++)
-        *v[e] += (*y) * gamma * (rinv[e] * coef[e]);
-    /* projection step */
-    double ax = 0.0, awa = 0.0;
+    double slope = 0.0, awa = 0.0;
     for (int e = 0; e < m; e++) {
-        ax += coef[e] * (*v[e]);
-        awa += coef[e] * rinv[e] * coef[e];
+        slope += coef[e] * (*v[e]);
+        awa += coef[e] * coef[e] * rinv[e];
     }
-    double viol = ax - beta;
-    double theta = (viol > 0.0 ? viol : 0.0) / (gamma * awa);
+    slope -= beta;
+    /* top of the parabola, clipped to the feasible dual set y >= 0 */
+    double ynew = *y + slope / (gamma * awa);
+    if (!(ynew > 0.0)) ynew = 0.0;
+    /* v follows: dv = -gamma W^{-1} a (ynew - y) */
+    double dy = ynew - *y;
     for (int e = 0; e < m; e++)
-        *v[e] -= theta * gamma * (rinv[e] * coef[e]);
-    /* dual update */
-    *y = theta;
+        *v[e] -= gamma * dy * (rinv[e] * coef[e]);
+    *y = ynew;
 }
 
 typedef struct {
@@ -220,11 +222,11 @@ static void metric_triplet(sweep_ctx *c, int64_t i, int64_t j, int64_t k)
             rinv[e] = c->r[sides[o][e]];
         }
         if (c->y) {
-            dykstra_step(v, coef, rinv, 3, 0.0, &c->y[3 * t + o], c->gamma);
+            visit_row(v, coef, rinv, 3, 0.0, &c->y[3 * t + o], c->gamma);
         } else {
             /* prefix mode: every dual is 0 before its first visit */
             double yv = 0.0;
-            dykstra_step(v, coef, rinv, 3, 0.0, &yv, c->gamma);
+            visit_row(v, coef, rinv, 3, 0.0, &yv, c->gamma);
             if (yv != 0.0 && c->lst_cnt < c->lst_cap) {
                 c->lst_t[c->lst_cnt] = t;
                 c->lst_o[c->lst_cnt] = (int8_t)o;
@@ -251,8 +253,8 @@ static void pair_pass(int64_t np, double gamma, const double *r, const uint8_t *
         double rinv[2] = { r[p], r[p] };
         const double c1[2] = { 1.0, -1.0 };
         const double c2[2] = { -1.0, -1.0 };
-        dykstra_step(v, c1, rinv, 2, (double)d[p], &y_pair[2 * p], gamma);
-        dykstra_step(v, c2, rinv, 2, -(double)d[p], &y_pair[2 * p + 1], gamma);
+        visit_row(v, c1, rinv, 2, (double)d[p], &y_pair[2 * p], gamma);
+        visit_row(v, c2, rinv, 2, -(double)d[p], &y_pair[2 * p + 1], gamma);
     }
 }
 
@@ -265,8 +267,8 @@ static void pair_pass_real(int64_t np, double gamma, const double *r, const doub
         double rinv[2] = { r[p], r[p] };
         const double c1[2] = { 1.0, -1.0 };
         const double c2[2] = { -1.0, -1.0 };
-        dykstra_step(v, c1, rinv, 2, dd[p], &y_pair[2 * p], gamma);
-        dykstra_step(v, c2, rinv, 2, -dd[p], &y_pair[2 * p + 1], gamma);
+        visit_row(v, c1, rinv, 2, dd[p], &y_pair[2 * p], gamma);
+        visit_row(v, c2, rinv, 2, -dd[p], &y_pair[2 * p + 1], gamma);
     }
 }
 

@@ -1,6 +1,7 @@
 // resid.hip -- FP64 convergence measures, A'y, and dual layout conversion.
 //
-// Convergence (Sec. IV-D: "constraint satisfaction and duality gap"):
+// Convergence (Sec. IV-D stops once the rows hold to a tolerance and the
+// primal and dual objectives have met):
 //   max violation over every metric row and every pair row;
 //   primal QP value c'v + (eps/2) v'Wv and the LP cost sum w |x - d|;
 //   complementary slackness y (b - a'v) over every row;

@@ -17,7 +17,9 @@
 // index in block P and largest in block Q; a round = every tile on one block
 // anti-diagonal P+Q, run concurrently (one workgroup per tile, no locks: two
 // tiles of a round never share a pair).  Inside a tile the middle block J
-// goes P..Q; inside a (tile, J) cube, sub-step t gives lane (il, kl) the
+// runs from Q down to P in the rounds of Fig. 2's first double loop
+// (P + Q < nb) and from P up to Q in those of the second (tile_J); inside
+// a (tile, J) cube, sub-step t gives lane (il, kl) the
 // middle offset jl with il + jl + kl = t (mod b), so the b*b lanes of a
 // sub-step touch pairwise distinct pairs and run in parallel; sub-steps are
 // separated by workgroup barriers.

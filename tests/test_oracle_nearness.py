@@ -90,3 +90,39 @@ def test_order_does_not_change_the_limit():
         xs.append(s.x.copy())
     for x in xs[1:]:
         np.testing.assert_allclose(x, xs[0], atol=1e-10)
+
+
+# Hand-worked nearness point (every value an exact binary fraction):
+# w = (1, 2, 4), d = (3, 1, 3/2), dual 1/2 on o = 0 (x_01 <= x_02 + x_12,
+# a = (1, -1, -1)).  A'y = (1/2, -1/2, -1/2), so x(y) = d - W^{-1} A'y =
+# (5/2, 5/4, 13/8).  Metric slacks there: o=0: 3/8, o=1: 23/8, o=2: 17/8.
+# D = d'A'y - (1/2) sum (A'y)^2 / w = 1/4 - 7/32 = 1/32;
+# primal (1/2) sum w (x - d)^2 = 7/32; gap 3/16.
+def _near_state():
+    s = oracle.Nearness(3, np.array([1.0, 2.0, 4.0]), np.array([3.0, 1.0, 1.5]))
+    s.y[:] = [0.5, 0.0, 0.0]
+    s.x[:] = [2.5, 1.25, 1.625]
+    return s
+
+
+def test_residuals_at_hand_point():
+    r = _near_state().residuals()
+    assert r["stat_resid"] == 0.0
+    assert r["dual"] == 1 / 32 and r["primal"] == 7 / 32 and r["gap"] == 3 / 16
+    assert r["cs_max"] == 0.5 * 3 / 8
+    assert r["max_viol"] == 0.0
+
+
+@pytest.mark.parametrize("o,slack", [(0, 0.375), (1, 2.875), (2, 2.125)])
+def test_complementary_slackness_one_row(o, slack):
+    s = _near_state()
+    s.y[:] = 0.0
+    s.y[o] = 2.0
+    assert s.residuals()["cs_max"] == 2.0 * slack
+
+
+@pytest.mark.parametrize("var,delta", [(0, 0.25), (1, -0.125), (2, 0.5)])
+def test_stationarity_residual_is_the_perturbation(var, delta):
+    s = _near_state()
+    s.x[var] += delta
+    assert s.residuals()["stat_resid"] == abs(delta)

@@ -227,6 +227,100 @@ def test_residuals_on_known_point():
     assert r["dual_qp"] == pytest.approx(-(2.0 / 2) * w.sum())
 
 
+# Hand-worked point for the measures of Sec. IV-D that read the duals.
+# n = 3, pairs (0,1), (0,2), (1,2); every value below is an exact binary
+# fraction, worked out by hand (no formula of the oracle is re-evaluated).
+#   x = (1/2, 1/4, 1/8), f = (3/4, 11/16, 17/16), d = (0, 1, 1)
+#   metric slacks x_S1 + x_S2 - x_L:  o=0: -1/8, o=1: 3/8, o=2: 5/8
+#   pair slacks, row x - f <= d:   d - x + f  = 1/4, 23/16, 31/16
+#                row -x - f <= -d: x + f - d  = 5/4, -1/16, 3/16
+_CS_X = [0.5, 0.25, 0.125]
+_CS_F = [0.75, 0.6875, 1.0625]
+_CS_METRIC = [0.125, 0.375, 0.625]                 # |slack| per orientation
+_CS_PAIR = [0.25, 1.25, 1.4375, 0.0625, 1.9375, 0.1875]   # |slack| of y_pair[2p + c]
+
+
+@pytest.mark.parametrize("row", range(9))
+def test_complementary_slackness_one_row(row):
+    """cs_max = max over rows of |y (b - a'v)|: with a dual of 2 on one row
+    and 0 elsewhere it is twice that row's |slack| (the nine rows' slacks
+    differ, so a measure that reads the wrong row, side or sign fails)."""
+    s = oracle.State(3, 2.0, np.array([1.0, 2.0, 0.5]), np.array([0, 1, 1], np.uint8))
+    s.x[:] = _CS_X
+    s.f[:] = _CS_F
+    s.y[:] = 0.0
+    s.y_pair[:] = 0.0
+    if row < 3:
+        s.y[row] = 2.0
+        expect = 2.0 * _CS_METRIC[row]
+    else:
+        s.y_pair[row - 3] = 2.0
+        expect = 2.0 * _CS_PAIR[row - 3]
+    assert s.residuals()["cs_max"] == expect
+
+
+def test_complementary_slackness_all_rows():
+    """Duals (1, 2, 3) on the metric rows and 1..6 on the pair rows: the
+    products are 1/8, 3/4, 15/8 and 1/4, 5/2, 69/16, 1/4, 155/16, 9/8; the
+    largest, 155/16, is the row x - f <= d of pair (1,2)."""
+    s = oracle.State(3, 2.0, np.array([1.0, 2.0, 0.5]), np.array([0, 1, 1], np.uint8))
+    s.x[:] = _CS_X
+    s.f[:] = _CS_F
+    s.y[:] = [1.0, 2.0, 3.0]
+    s.y_pair[:] = [1.0, 2.0, 3.0, 4.0, 5.0, 6.0]
+    assert s.residuals()["cs_max"] == 155 / 16
+    s.y_pair[4] = 0.0            # next largest: 69/16 on x - f <= d of pair (0,2)
+    assert s.residuals()["cs_max"] == 69 / 16
+
+
+# A point with nonzero duals and its v(y), by hand.  gamma = 2,
+# w = (1, 2, 4), d = (0, 1, 1); dual 1 on the row x_12 <= x_01 + x_02
+# (a = (-1, -1, +1) on x) and 1/2 on x_02 - f_02 <= 1.
+#   A'y on x: (-1, -1 + 1/2, +1) = (-1, -1/2, 1); on f: (0, -1/2, 0)
+#   v(y) = -gamma W^{-1} (c + A'y), c = (0 on x, w on f):
+#     x = (2, 1/2, -1/2),  f = (-2, -3/2, -2)
+#   D = -b'y - (gamma/2) sum (gx^2 + gf^2)/w
+#     = -1/2 - ((1 + 1)/1 + (1/4 + 9/4)/2 + (1 + 16)/4) = -1/2 - 15/2 = -8
+#   P(v(y)) = sum w f + sum w (x^2 + f^2)/(2 gamma) = -13 + 30/4 = -11/2
+_ST_W = np.array([1.0, 2.0, 4.0])
+_ST_D = np.array([0, 1, 1], np.uint8)
+_ST_X = [2.0, 0.5, -0.5]
+_ST_F = [-2.0, -1.5, -2.0]
+
+
+def _stat_state():
+    s = oracle.State(3, 2.0, _ST_W, _ST_D)
+    s.y[:] = [0.0, 0.0, 1.0]
+    s.y_pair[:] = [0.0, 0.0, 0.5, 0.0, 0.0, 0.0]
+    s.x[:] = _ST_X
+    s.f[:] = _ST_F
+    return s
+
+
+def test_dual_and_stationarity_at_hand_point():
+    s = _stat_state()
+    r = s.residuals()
+    assert r["stat_resid"] == 0.0
+    assert r["dual_qp"] == -8.0
+    assert r["primal_qp"] == -5.5
+    assert r["gap"] == 2.5
+    x, f = s.x_from_y()
+    assert list(x) == _ST_X and list(f) == _ST_F
+
+
+@pytest.mark.parametrize("var,delta", [(0, 0.25), (1, -0.375), (2, 0.125),
+                                       (3, 0.5), (4, -0.0625), (5, 0.75)])
+def test_stationarity_residual_is_the_perturbation(var, delta):
+    """stat_resid = max |v - v(y)|: moving one variable of v(y) by delta
+    gives exactly |delta| (var 0-2: x, 3-5: f)."""
+    s = _stat_state()
+    if var < 3:
+        s.x[var] += delta
+    else:
+        s.f[var - 3] += delta
+    assert s.residuals()["stat_resid"] == abs(delta)
+
+
 # --------------------------------------------------------------------------
 # The schedule (Sec. III-B, III-C).
 # --------------------------------------------------------------------------
