@@ -293,6 +293,17 @@ int cc_status(cc_ctx *ctx);
 int cc_sweep_rounds(cc_ctx *ctx, void *x, void *y, const void *g, int32_t first_round,
                     int32_t nrounds);
 
+/* The metric rows of the first `nrounds` rounds of one sweep (Sec. III-C's
+ * round order), run by the dataflow executor in the launch configuration of
+ * a full dataflow sweep (b = 8, 16, 24, 32): the tiles of later rounds are
+ * not visited.  Equal bit for bit to cc_sweep_rounds(ctx, x, y, g, 0,
+ * nrounds).  For checks of the dataflow kernel against a prefix of the
+ * serial order at sizes where a whole sweep of the oracle is too slow.
+ * Afterwards the executor's touch counters start a new epoch.  Synchronises;
+ * CC_EINVAL for nrounds outside [0, cc_num_rounds], CC_EHIP if a wait timed
+ * out. */
+int cc_sweep_metric_prefix(cc_ctx *ctx, void *x, void *y, const void *g, int32_t nrounds);
+
 /* The pair pass alone. */
 int cc_pair_pass(cc_ctx *ctx, void *x, void *f, void *y_pair, const void *g,
                  const uint8_t *d);

@@ -73,6 +73,7 @@ _sig("cc_prepare", ctypes.c_int, _p, _p, _dbl, _p)
 _sig("cc_init_cold", ctypes.c_int, _p, _p, _p, _p, _p, _dbl)
 _sig("cc_sweep", ctypes.c_int, _p, _p, _p, _p, _p, _p, _p, _i32, _i32)
 _sig("cc_sweep_rounds", ctypes.c_int, _p, _p, _p, _p, _i32, _i32)
+_sig("cc_sweep_metric_prefix", ctypes.c_int, _p, _p, _p, _p, _i32)
 _sig("cc_sweep_metric", ctypes.c_int, _p, _p, _p, _p, _i32)
 _sig("cc_status", ctypes.c_int, _p)
 _sig("cc_dataflow_breakdown", ctypes.c_int, _p, _p, _p, _p, ctypes.POINTER(_dbl))
@@ -120,7 +121,7 @@ _sig("cc_warm_start_mlp", ctypes.c_int, _p, _p, _p, _p, _p, _dbl, _p, _p, _p, _p
 
 EXPORTS = ["cc_last_error", "cc_num_metric_duals", "cc_create", "cc_destroy", "cc_dual_slots",
            "cc_num_rounds", "cc_prepare", "cc_init_cold", "cc_sweep", "cc_sweep_rounds",
-           "cc_sweep_metric", "cc_status",
+           "cc_sweep_metric_prefix", "cc_sweep_metric", "cc_status",
            "cc_pair_pass", "cc_residuals", "cc_x_from_y", "cc_duals_to_lex", "cc_slots_to_lex",
            "cc_dataflow_tables", "cc_widen", "cc_narrow", "cc_solve_cc_lp",
            "cc_nearness_init", "cc_nearness_residuals", "cc_dual_mask_bytes",
@@ -216,6 +217,9 @@ class Context:
 
     def sweep_rounds(self, x, y, g, first, count):
         check(_L.cc_sweep_rounds(self._h, _ptr(x), _ptr(y), _ptr(g), int(first), int(count)))
+
+    def sweep_metric_prefix(self, x, y, g, rounds):
+        check(_L.cc_sweep_metric_prefix(self._h, _ptr(x), _ptr(y), _ptr(g), int(rounds)))
 
     def sweep_metric(self, x, y, g, executor=None):
         check(_L.cc_sweep_metric(self._h, _ptr(x), _ptr(y), _ptr(g), self.executor(executor)))
@@ -389,6 +393,12 @@ class Solver:
         self.ctx.sweep_rounds(self.x, self.y, self.g, first, count)
         self.invalidate_mask()
 
+    def sweep_metric_prefix(self, rounds):
+        """The first `rounds` metric rounds of a sweep on the dataflow
+        executor (the full sweep's kernel and launch shape)."""
+        self.ctx.sweep_metric_prefix(self.x, self.y, self.g, rounds)
+        self.invalidate_mask()
+
     def sweep_metric(self, executor=None, sparse=False):
         if sparse:
             self.ctx.sweep_metric_sparse(self.x, self.y, self.g, self.ensure_mask())
@@ -416,6 +426,18 @@ class Solver:
         y_lex = torch.empty(num_metric_duals(self.n), dtype=self.y.dtype, device=self.y.device)
         self.ctx.duals_to_lex(self.y, y_lex)
         return y_lex
+
+    def nonzero_duals(self, chunk=1 << 28):
+        """The nonzero metric duals as host arrays (colex row index 3t + o,
+        value as float64), in slot order.  Scans y in chunks (torch.nonzero
+        takes at most 2^32 elements)."""
+        parts = [torch.nonzero(self.y[s:s + chunk]).flatten() + s
+                 for s in range(0, self.y.numel(), chunk)]
+        nz = torch.cat(parts)
+        lex = torch.empty_like(nz)
+        if nz.numel():
+            self.ctx.slots_to_lex(nz, lex)
+        return lex.cpu().numpy(), self.y[nz].double().cpu().numpy()
 
     def solve(self, tol=1e-6, max_sweeps=100000, check_every=None, executor=None, sparse=False,
               gap_tol=None):

@@ -335,6 +335,24 @@ int sweep_metric_t(cc_ctx *c, T *x, T *y, const T *g, int exec, unsigned long lo
     return CC_OK;
 }
 
+// The dataflow sweep over the tiles of the first `rounds` rounds only.
+// Tickets run in schedule order, and a tile of round r waits only on
+// touches by tiles of rounds <= r, so the prefix needs nothing beyond it.
+// The counters then hold a partial epoch and are cleared.
+template <typename T>
+int sweep_prefix_t(cc_ctx *c, T *x, T *y, const T *g, int rounds) {
+    DataflowArgs a;
+    int rc = dataflow_args(c, nullptr, a);
+    if (rc) return rc;
+    a.ntiles = int(c->round_start[rounds]);
+    if (a.ntiles > 0 &&
+        (rc = launch_sweep_dataflow<T>(a, df_grid(c, true), c->b, c->n, x, g, y, nullptr, nullptr, c->stream)))
+        return rc;
+    if ((rc = launch_fill_u32(c->nblocks * kCntStride, c->d_cnt, c->stream))) return rc;
+    c->epoch = 0;
+    return check_dataflow(c);
+}
+
 int ensure_ax(cc_ctx *c) {
     if (!c->d_ax) {
         if (hipMalloc(&c->d_ax, size_t(num_pairs(c->n)) * sizeof(double)) != hipSuccess) {
@@ -972,6 +990,16 @@ int cc_sweep_rounds(cc_ctx *c, void *x, void *y, const void *g, int32_t first, i
     if (c->prec == CC_F64)
         return sweep_rounds_t<double>(c, (double *)x, (double *)y, (const double *)g, first, count);
     return sweep_rounds_t<float>(c, (float *)x, (float *)y, (const float *)g, first, count);
+}
+
+int cc_sweep_metric_prefix(cc_ctx *c, void *x, void *y, const void *g, int32_t nrounds) {
+    int rc;
+    if ((rc = check_ctx(c)) || (rc = need(x, "x")) || (rc = need(y, "y")) || (rc = need(g, "g")))
+        return rc;
+    if (nrounds < 0 || nrounds > c->nrounds) return fail(CC_EINVAL, "round count outside the schedule");
+    if (!dataflow_b(c->b)) return fail(CC_EINVAL, "the dataflow executor supports b = 8, 16, 24 and 32");
+    if (c->prec == CC_F64) return sweep_prefix_t<double>(c, (double *)x, (double *)y, (const double *)g, nrounds);
+    return sweep_prefix_t<float>(c, (float *)x, (float *)y, (const float *)g, nrounds);
 }
 
 int cc_pair_pass(cc_ctx *c, void *x, void *f, void *yp, const void *g, const uint8_t *d) {

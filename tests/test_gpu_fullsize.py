@@ -1,12 +1,19 @@
 """The largest workloads at full size, in the launch configuration the
-benchmark times, checked through properties that hold at any size (the
-oracle cannot run whole sweeps here: one FP64 sweep at n = 4000 would take
-about ten minutes on one core).  Smaller sizes are compared with the oracle
-element by element in the other GPU tests."""
+benchmark times.  The oracle cannot run whole sweeps here (one FP64 sweep at
+n = 4000 takes about ten minutes on one core), so these tests compare a
+prefix of the schedule with the oracle element by element (sweep 1 and the
+first rounds of sweep 2), and check properties that hold at any size over
+whole sweeps.  Smaller sizes are compared with the oracle over whole sweeps
+in the other GPU tests."""
+import functools
+
+import numpy as np
 import pytest
 
+import oracle
 from conftest import gpu_available
 from paper_1901_10084_amd import instances as I
+from parity_helpers import U32, U64, one_sided_bound, rel_err, tol_f32, union_duals
 
 pytestmark = pytest.mark.gpu
 
@@ -73,3 +80,58 @@ def test_n2000_f32_sparse_equals_dense():
     assert bits == nonzero > 0
     del dense, sparse
     torch.cuda.empty_cache()
+
+
+ROUNDS4 = 2   # rounds of sweep 2 compared at n = 4000 (about 2.6e8 triplets)
+
+
+@functools.lru_cache(maxsize=1)
+def oracle_prefix_n4000():
+    """The oracle's FP64 run of the same prefix: sweep 1 from the cold start
+    (its metric rows all hold at x = 0, so only the pair pass moves), then
+    the first ROUNDS4 rounds of sweep 2, with sparse dual storage."""
+    inst = I.workload(4)
+    return oracle.second_sweep_prefix(inst.n, 32, inst.gamma, inst.w, inst.d, ROUNDS4,
+                                      cap=1 << 27)
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_n4000_dataflow_prefix_matches_the_oracle(prec):
+    """The benchmark's kernel at the largest workload's own size and
+    arithmetic: n = 4000 Chung-Lu, weights U[0.5, 1.5] (W = diag(w)),
+    gamma = 10, b = 32, dataflow executor in the full sweep's launch shape.
+    Sweep 1, then the first rounds of sweep 2 (cc_sweep_metric_prefix),
+    against the oracle element by element: x, f, y_pair and every nonzero
+    metric dual.  FP64 to 1e-10; FP32 to the rounding model of tol_f32 with
+    the visits a variable gets in these rounds (at most 3 (n - 2))."""
+    inst = I.workload(4)
+    torch.cuda.empty_cache()
+    print(f"n={inst.n} b=32 {prec}: sweep 1 + {ROUNDS4} rounds on the dataflow executor",
+          flush=True)
+    g = C.Solver.from_instance(inst, b=32, prec=prec)
+    g.sweep(1, C.CC_EXEC_DATAFLOW)
+    g.sweep_metric_prefix(ROUNDS4)
+    g.status()
+    gx, gf, gyp = (t.double().cpu().numpy() for t in (g.x, g.f, g.y_pair))
+    gpos, gval = g.nonzero_duals()
+    del g
+    torch.cuda.empty_cache()
+    print("oracle prefix ...", flush=True)
+    x, f, yp, t, o, y = oracle_prefix_n4000()
+    opos = 3 * t + o.astype(np.int64)
+    tol = 1e-10 if prec == "f64" else tol_f32(3 * (inst.n - 2))
+    union, gv, ov, only = union_duals(gpos, gval, opos, y)
+    errs = dict(x=rel_err(gx, x), f=rel_err(gf, f), y_pair=rel_err(gyp, yp), y=rel_err(gv, ov))
+    print(f"{prec}: {len(t)} nonzero duals in the oracle, {len(gpos)} on the GPU, "
+          f"{only.size} on one side only; errors {errs} (tol {tol:.2e})", flush=True)
+    assert len(t) > 0
+    for k, e in errs.items():
+        assert e <= tol, (k, e, tol)
+    x_err = float(np.abs(gx - x).max())
+    q_max = float(inst.w.max()) / (3.0 * inst.gamma)
+    bound = one_sided_bound(U64 if prec == "f64" else U32, x_err, float(np.abs(y).max()),
+                            float(np.abs(x).max()), q_max)
+    if only.size:
+        worst = float(np.abs(gv - ov)[np.searchsorted(union, only)].max())
+        print(f"largest one-sided dual {worst:.3e}, bound {bound:.3e}", flush=True)
+        assert worst <= bound

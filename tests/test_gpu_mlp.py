@@ -49,10 +49,23 @@ def test_gradient_matches_reference(count):
     assert abs(float(loss) - lr_) <= 1e-4 * abs(lr_)
     err = np.abs(g - gr).max() / np.abs(gr).max()
     print("grad rel err", err, flush=True)
-    assert err <= 2e-3
-    # per block of parameters too
-    for lo, hi in ((0, 128), (128, 160), (160, 1184), (1184, 1216), (1216, 1248), (1248, 1249)):
-        assert np.abs(g[lo:hi] - gr[lo:hi]).max() <= 2e-3 * max(1e-6, np.abs(gr).max())
+    # Every block of parameters against its own largest reference gradient:
+    # the reference takes the GPU's bf16 roundings, so what remains is the
+    # fp32 accumulation order of the MFMA products and reductions, a few
+    # fp32 ulps of a block's sums (measured below 1e-6).
+    for name, lo, hi in (("W1", 0, 128), ("b1", 128, 160), ("W2", 160, 1184),
+                         ("b2", 1184, 1216), ("W3", 1216, 1248), ("b3", 1248, 1249)):
+        ref = gr[lo:hi]
+        scale = np.abs(ref).max()
+        if scale == 0.0:
+            assert not g[lo:hi].any(), name
+            continue
+        e = np.abs(g[lo:hi] - ref).max() / scale
+        gb = g[lo:hi].astype(np.float64)
+        cos = float(gb @ ref / (np.linalg.norm(gb) * np.linalg.norm(ref)))
+        print(f"  {name}: rel err {e:.2e} cosine {cos:.9f}", flush=True)
+        assert e <= 1e-5, (name, e)
+        assert cos >= 1.0 - 1e-9, (name, cos)
 
 
 def test_slot_features_match_reference():
@@ -180,25 +193,52 @@ def test_warm_start_is_valid_and_reaches_the_same_optimum():
 
 def test_warm_start_gain_report():
     """What the trained network gains: sweeps and time to max violation
-    <= 1e-4 in FP32 on held-out graphs, learned start vs cold start."""
-    net, hist = small_trained_network(16)
-    rows = []
-    for seed in (2001, 2002):
+    <= 1e-4 in FP32 on held-out planted partitions (n = 300, the training
+    family), learned start vs cold start.  The shipped network (trained by
+    warmstart.train on 200 graphs with the library's own kernels) must save
+    at least a quarter of the sweeps and reach the same objective; a network
+    trained here on 16 graphs is reported beside it."""
+    import time
+    nets = {"shipped": W.load(), "16 graphs": small_trained_network(16)[0]}
+    for seed in (2001, 2002, 2003):
         inst = I.training_graph(seed)
         deg = W.degrees(inst)
         cold = C.Solver.from_instance(inst, b=16, prec="f32")
         rc, cc, tc = cold.solve(tol=1e-4, executor=C.CC_EXEC_DATAFLOW)
-        warm = C.Solver.from_instance(inst, b=16, prec="f32")
-        torch.cuda.synchronize()
-        import time
-        t0 = time.perf_counter()
+        assert cc
+        for name, net in nets.items():
+            warm = C.Solver.from_instance(inst, b=16, prec="f32")
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            info = W.warm_start(warm, net, deg)
+            rw, cw, _ = warm.solve(tol=1e-4, executor=C.CC_EXEC_DATAFLOW)
+            tw = time.perf_counter() - t0
+            print(f"seed {seed} {name}: accepted {info['accepted']} sweeps cold {cold.sweeps} "
+                  f"warm {warm.sweeps} time cold {tc:.4f} warm {tw:.4f} objective "
+                  f"{rc['primal_qp']:.6f} {rw['primal_qp']:.6f}", flush=True)
+            assert cw
+            assert abs(rw["primal_qp"] - rc["primal_qp"]) <= 1e-3 * abs(rc["primal_qp"])
+            if name == "shipped":
+                assert info["accepted"]
+                assert warm.sweeps <= 0.75 * cold.sweeps, (warm.sweeps, cold.sweeps)
+
+
+def test_gate_rejects_a_bad_prediction():
+    """A network whose output bias is huge predicts every dual far too
+    large: the dual objective falls, the gate rejects the prediction and the
+    state is the cold start, bit for bit, in both precisions."""
+    p = M.init_params(3)
+    p[1248] = 1.0e3                       # output bias: every prediction is huge
+    net = W.Network(params=p)
+    inst = I.training_graph(2001)
+    deg = W.degrees(inst)
+    for prec in ("f32", "f64"):
+        warm = C.Solver.from_instance(inst, b=16, prec=prec)
+        warm.sweep(2)                     # start from a state that is not the cold one
         info = W.warm_start(warm, net, deg)
-        rw, cw, tw = warm.solve(tol=1e-4, executor=C.CC_EXEC_DATAFLOW)
-        tw = time.perf_counter() - t0
-        rows.append((seed, info["accepted"], cold.sweeps, warm.sweeps, tc, tw,
-                     rc["primal_qp"], rw["primal_qp"]))
-        assert cc and cw
-        assert abs(rw["primal_qp"] - rc["primal_qp"]) <= 1e-3 * abs(rc["primal_qp"])
-    for r in rows:
-        print("seed %d accepted %s sweeps cold %d warm %d time cold %.4f warm %.4f "
-              "obj %.6f %.6f" % r, flush=True)
+        cold = C.Solver.from_instance(inst, b=16, prec=prec)
+        print(prec, info, flush=True)
+        assert not info["accepted"]
+        assert info["dual_warm"] < info["dual_cold"]
+        for a in ("x", "f", "y", "y_pair"):
+            assert torch.equal(getattr(warm, a), getattr(cold, a)), a

@@ -5,6 +5,7 @@ import pytest
 import oracle
 from conftest import gpu_available
 from paper_1901_10084_amd import instances as I
+from parity_helpers import U64, one_sided_bound, rel_err, tol_f32, union_duals
 
 pytestmark = pytest.mark.gpu
 
@@ -13,24 +14,7 @@ if gpu_available():
     from paper_1901_10084_amd import ccproj as C
 
 
-def rel_err(a, ref):
-    a = np.asarray(a, dtype=np.float64)
-    ref = np.asarray(ref, dtype=np.float64)
-    if ref.size == 0:
-        return 0.0
-    return float(np.abs(a - ref).max() / max(1.0, float(np.abs(ref).max())))
-
-
 TOL64 = 1e-10   # FP64 GPU vs FP64 oracle, relative to max(1, |ref|_inf)
-
-
-def nonzero_positions(t, chunk=1 << 28):
-    """Flat indices of the nonzeros of a 1-D tensor, in chunks (torch's
-    nonzero fails on tensors with more than 2^32 elements)."""
-    parts = []
-    for s in range(0, t.numel(), chunk):
-        parts.append(torch.nonzero(t[s:s + chunk]).flatten() + s)
-    return torch.cat(parts)
 
 
 def compare_state(gs, os_, tol, what=""):
@@ -102,37 +86,37 @@ def test_parity_workload1_three_sweeps():
     compare_state(g, o, TOL64, "workload1 K=3")
 
 
-@pytest.mark.parametrize("n,b,rounds", [(1500, 16, 3), (2000, 16, 2)])
-def test_prefix_parity_large(n, b, rounds):
-    """Large instances: sweep 1, then the first rounds of sweep 2, against
-    the oracle's sparse-dual prefix."""
+@pytest.mark.parametrize("n,b,rounds,executor", [(1500, 16, 3, "rounds"), (2000, 16, 2, "dataflow")])
+def test_prefix_parity_large(n, b, rounds, executor):
+    """Large instances: sweep 1, then the first rounds of sweep 2 (round by
+    round, or on the dataflow executor in its full-sweep launch shape),
+    against the oracle's sparse-dual prefix.  Duals are compared as dense
+    vectors over the union of both sides' nonzero positions, so a dual
+    nonzero on one side only must itself be within 1e-10; it must also be
+    within the clipping bound of one_sided_bound (a value within rounding of
+    zero)."""
     inst = I.workload(2) if n == 1500 else I.workload(3)
     g = C.Solver.from_instance(inst, b=b)
     g.sweep(1)
-    g.sweep_rounds(0, rounds)
+    if executor == "rounds":
+        g.sweep_rounds(0, rounds)
+    else:
+        g.sweep_metric_prefix(rounds)
     x, f, yp, t, o, y = oracle.second_sweep_prefix(n, b, inst.gamma, inst.w, inst.d, rounds)
-    assert rel_err(g.x.cpu().numpy(), x) <= TOL64
+    gx = g.x.cpu().numpy()
+    assert rel_err(gx, x) <= TOL64
     assert rel_err(g.f.cpu().numpy(), f) <= TOL64
     assert rel_err(g.y_pair.cpu().numpy(), yp) <= TOL64
-    nz = nonzero_positions(g.y)
-    lex = torch.empty_like(nz)
-    g.ctx.slots_to_lex(nz, lex)
-    lex = lex.cpu().numpy()
-    assert (lex >= 0).all()
-    vals = g.y[nz].cpu().numpy()
-    # Compare as dense vectors over the union of nonzero positions: a dual
-    # whose row sits within rounding of zero may be exactly zero on one side
-    # and a few ulps on the other.
-    gpos, opos = lex, 3 * t + o.astype(np.int64)
-    union = np.union1d(gpos, opos)
-    gv = np.zeros(union.size)
-    ov = np.zeros(union.size)
-    gv[np.searchsorted(union, gpos)] = vals
-    ov[np.searchsorted(union, opos)] = y
+    gpos, gval = g.nonzero_duals()
+    assert (gpos >= 0).all()
+    union, gv, ov, only = union_duals(gpos, gval, 3 * t + o.astype(np.int64), y)
     assert rel_err(gv, ov) <= TOL64
-    only = np.setxor1d(gpos, opos)
-    assert only.size <= 1e-3 * max(1, opos.size)
-    print(f"prefix n={n}: {len(t)} nonzero duals", flush=True)
+    bound = one_sided_bound(U64, float(np.abs(gx - x).max()), float(np.abs(y).max()),
+                            float(np.abs(x).max()), float(inst.w.max()) / (3.0 * inst.gamma))
+    worst = float(np.abs(gv - ov)[np.searchsorted(union, only)].max()) if only.size else 0.0
+    print(f"prefix n={n}: {len(t)} nonzero duals, {only.size} on one side only, largest "
+          f"{worst:.3e} (bound {bound:.3e})", flush=True)
+    assert worst <= bound
 
 
 @pytest.mark.parametrize("prec", ["f64", "f32"])
@@ -170,6 +154,32 @@ def test_x_from_y_dataflow(n, b, prec):
     tol = 1e-12 if prec == "f64" else 1e-5
     assert rel_err(x1.cpu().numpy(), xo) <= tol
     assert rel_err(f1.cpu().numpy(), fo) <= tol
+
+
+F32_CASES = [
+    # (instance, b, sweeps): the FP32 tile sizes of the larger workloads
+    (lambda: I.random_signed(130, seed=11, gamma=5.0, weighted=False), 16, 3),  # ragged tail of 2
+    (lambda: I.random_signed(300, seed=12, gamma=10.0, weighted=True), 32, 3),  # weighted, ragged
+    (lambda: I.workload(1), 16, 3),                                             # n = 500
+    (lambda: I.random_signed(200, seed=13, gamma=10.0, weighted=True), 32, 3),
+]
+
+
+@pytest.mark.parametrize("case", range(len(F32_CASES)))
+def test_sweep_parity_f32(case):
+    """FP32 sweeps (the arithmetic of the n = 1500..4000 workloads: b = 16
+    and 32, dataflow executor, W = diag(w)) against the FP64 oracle, element
+    by element, to the FP32 rounding model of tol_f32 with the visits a
+    variable gets (3 (n - 2) per sweep)."""
+    mk, b, K = F32_CASES[case]
+    inst = mk()
+    g = C.Solver.from_instance(inst, b=b, prec="f32")
+    o = oracle.State.from_instance(inst)
+    g.sweep(K, C.CC_EXEC_DATAFLOW)
+    o.sweep(K, b=b)
+    tol = tol_f32(3 * (inst.n - 2) * K)
+    print(f"f32 n={inst.n} b={b} K={K} tol {tol:.2e}", flush=True)
+    compare_state(g, o, tol, f"f32 n={inst.n} b={b} K={K}")
 
 
 def test_f32_close_to_oracle():
