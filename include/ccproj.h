@@ -288,6 +288,23 @@ int cc_dataflow_breakdown(cc_ctx *ctx, void *x, void *y, const void *g, double *
  * since the last check (CC_EHIP), else CC_OK. */
 int cc_status(cc_ctx *ctx);
 
+/* Allocation-free variant of cc_sweep with the dataflow executor, for
+ * callers that cannot allocate device memory (code under stream capture,
+ * tight serving loops, hosts that forbid hipMalloc): nsweeps full sweeps,
+ * the same kernels and the same results bit for bit as cc_sweep(ctx, ...,
+ * nsweeps, CC_EXEC_DATAFLOW).  The executor's scratch (a ticket counter, an
+ * abort flag and one touch counter per block of x) lives in a static device
+ * array of 4 MiB that each GPU holds until the process ends, instead of in
+ * the context; every call clears it first.  Limit: ceil(n/b) <= 255
+ * (n <= 8160 at b = 32, 4080 at b = 16), else CC_EINVAL before any work.
+ * Calls that overlap on one GPU (any context, any stream) share that GPU's
+ * array and race: serialise them.  Makes no hipMalloc or hipFree call.
+ * Synchronises the context's stream at the end and returns CC_EHIP if a
+ * dependency wait timed out (the state is then incomplete).  CC_EINVAL for a
+ * b without a dataflow kernel (8, 16, 24, 32) or nsweeps < 0. */
+int cc_sweep_noalloc(cc_ctx *ctx, void *x, void *f, void *y, void *y_pair, const void *g,
+                     const uint8_t *d, int32_t nsweeps);
+
 /* Metric rounds [first_round, first_round + nrounds) of one sweep, without
  * the pair pass (for checks against a prefix of the serial order). */
 int cc_sweep_rounds(cc_ctx *ctx, void *x, void *y, const void *g, int32_t first_round,

@@ -74,6 +74,7 @@ _sig("cc_init_cold", ctypes.c_int, _p, _p, _p, _p, _p, _dbl)
 _sig("cc_sweep", ctypes.c_int, _p, _p, _p, _p, _p, _p, _p, _i32, _i32)
 _sig("cc_sweep_rounds", ctypes.c_int, _p, _p, _p, _p, _i32, _i32)
 _sig("cc_sweep_metric_prefix", ctypes.c_int, _p, _p, _p, _p, _i32)
+_sig("cc_sweep_noalloc", ctypes.c_int, _p, _p, _p, _p, _p, _p, _p, _i32)
 _sig("cc_sweep_metric", ctypes.c_int, _p, _p, _p, _p, _i32)
 _sig("cc_status", ctypes.c_int, _p)
 _sig("cc_dataflow_breakdown", ctypes.c_int, _p, _p, _p, _p, ctypes.POINTER(_dbl))
@@ -121,7 +122,7 @@ _sig("cc_warm_start_mlp", ctypes.c_int, _p, _p, _p, _p, _p, _dbl, _p, _p, _p, _p
 
 EXPORTS = ["cc_last_error", "cc_num_metric_duals", "cc_create", "cc_destroy", "cc_dual_slots",
            "cc_num_rounds", "cc_prepare", "cc_init_cold", "cc_sweep", "cc_sweep_rounds",
-           "cc_sweep_metric_prefix", "cc_sweep_metric", "cc_status",
+           "cc_sweep_metric_prefix", "cc_sweep_metric", "cc_sweep_noalloc", "cc_status",
            "cc_pair_pass", "cc_residuals", "cc_x_from_y", "cc_duals_to_lex", "cc_slots_to_lex",
            "cc_dataflow_tables", "cc_widen", "cc_narrow", "cc_solve_cc_lp",
            "cc_nearness_init", "cc_nearness_residuals", "cc_dual_mask_bytes",
@@ -220,6 +221,12 @@ class Context:
 
     def sweep_metric_prefix(self, x, y, g, rounds):
         check(_L.cc_sweep_metric_prefix(self._h, _ptr(x), _ptr(y), _ptr(g), int(rounds)))
+
+    def sweep_noalloc(self, x, f, y, y_pair, g, d, nsweeps=1):
+        """cc_sweep_noalloc: dataflow sweeps with the library's static
+        scratch (no device allocation); synchronises."""
+        check(_L.cc_sweep_noalloc(self._h, _ptr(x), _ptr(f), _ptr(y), _ptr(y_pair), _ptr(g),
+                                  _ptr(d), int(nsweeps)))
 
     def sweep_metric(self, x, y, g, executor=None):
         check(_L.cc_sweep_metric(self._h, _ptr(x), _ptr(y), _ptr(g), self.executor(executor)))

@@ -3,6 +3,7 @@
 #include <chrono>
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -524,6 +525,9 @@ int cc_create(cc_ctx **out, int64_t n, int32_t b, int32_t prec, void *stream) {
         return fail(CC_EHIP, "copy of schedule tables failed");
     }
     rc = (prec == CC_F64) ? set_sweep_lds_limits<double>(b) : set_sweep_lds_limits<float>(b);
+    // the dataflow executor's tables, built here so that no later sweep
+    // allocates (cc_sweep_noalloc relies on it)
+    if (!rc && dataflow_b(b)) rc = ensure_dataflow(c);
     if (rc) {
         cc_destroy(c);
         return rc;
@@ -629,6 +633,95 @@ int cc_sweep(cc_ctx *c, void *x, void *f, void *y, void *yp, const void *g, cons
                                (const double *)g, d, nsweeps);
     return sweep_t<float>(c, (float *)x, (float *)f, (float *)y, (float *)yp, (const float *)g, d,
                           nsweeps);
+}
+
+}  // extern "C"
+
+// ----- allocation-free sweeps ----------------------------------------------
+// The dataflow executor's scratch (ticket counter, abort flag and one touch
+// counter per block of x) in a static device array instead of the context's
+// buffers: no allocation at all per call.  Each device holds its own copy;
+// its address is taken once per device (hipGetSymbolAddress) and only that
+// address reaches the kernels (the array's name in host code is a host-side
+// stand-in, not a device address).  Layout: words [0, 64) control ([0]
+// ticket, [1] abort flag), then kCntStride words per block.
+
+constexpr int64_t kNoallocScratchBytes = int64_t(4) << 20;
+constexpr int64_t kNoallocCtlWords = 64;
+constexpr int64_t kNoallocMaxBlocks =
+    (kNoallocScratchBytes / int64_t(sizeof(uint32_t)) - kNoallocCtlWords) / kCntStride;
+static __device__ __align__(256) uint32_t scratch[kNoallocScratchBytes / sizeof(uint32_t)];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+uint32_t *g_scratch_ptr[kMaxDevices] = {};
+
+// The device address of this device's copy of `scratch` (set-up on the
+// first call on each device, with that device current).
+int scratch_address(uint32_t **out) {
+    int dev = 0;
+    CCP_HIP_CHECK(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDevices) return fail(CC_EINVAL, "device index out of range");
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p)
+            return fail(CC_EHIP, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+        g_scratch_ptr[dev] = static_cast<uint32_t *>(p);
+    }
+    *out = g_scratch_ptr[dev];
+    return CC_OK;
+}
+
+template <typename T>
+int sweep_noalloc_t(cc_ctx *c, uint32_t *ws, T *x, T *f, T *y, T *yp, const T *g, const uint8_t *d,
+                    int nsweeps) {
+    uint32_t *const ctl = ws, *const cnt = ws + kNoallocCtlWords;
+    int rc;
+    // every call starts from zeroed counters and flags (a fill kernel)
+    if ((rc = launch_fill_u32(kNoallocCtlWords + c->nblocks * kCntStride, ws, c->stream))) return rc;
+    for (int s = 0; s < nsweeps; ++s) {
+        const DataflowArgs a{c->d_dtiles, int(c->ntiles), c->d_needs, c->d_K, cnt, ctl,
+                             uint32_t(s), c->wait_ticks, nullptr};
+        if ((rc = launch_sweep_dataflow<T>(a, df_grid(c, true), c->b, c->n, x, g, y, nullptr, nullptr,
+                                           c->stream)))
+            return rc;
+        if ((rc = launch_pair_pass<T>(num_pairs(c->n), x, f, yp, g, d, c->stream))) return rc;
+    }
+    uint32_t h[2] = {0u, 0u};
+    CCP_HIP_CHECK(hipMemcpyAsync(h, ctl, sizeof(h), hipMemcpyDeviceToHost, c->stream));
+    CCP_HIP_CHECK(hipStreamSynchronize(c->stream));
+    if (h[1]) return fail(CC_EHIP, "dataflow sweep aborted: a dependency wait timed out");
+    return CC_OK;
+}
+}  // namespace
+
+extern "C" {
+
+int cc_sweep_noalloc(cc_ctx *c, void *x, void *f, void *y, void *yp, const void *g, const uint8_t *d,
+                     int32_t nsweeps) {
+    int rc;
+    if ((rc = check_ctx(c)) || (rc = need(x, "x")) || (rc = need(f, "f")) || (rc = need(y, "y")) ||
+        (rc = need(yp, "y_pair")) || (rc = need(g, "g")) || (rc = need(d, "d")))
+        return rc;
+    if (nsweeps < 0) return fail(CC_EINVAL, "nsweeps must be >= 0");
+    if (!dataflow_b(c->b) || !c->d_dtiles)
+        return fail(CC_EINVAL, "cc_sweep_noalloc needs the dataflow executor (b = 8, 16, 24, 32)");
+    if (c->nblocks > kNoallocMaxBlocks)
+        return fail(CC_EINVAL, "cc_sweep_noalloc: " + std::to_string(c->nblocks) +
+                                   " blocks of x exceed its static scratch (" +
+                                   std::to_string(kNoallocMaxBlocks) + " blocks: ceil(n/b) <= 255)");
+    if ((int64_t(nsweeps) + 1) * c->kmax >= (int64_t(1) << 31))
+        return fail(CC_EINVAL, "cc_sweep_noalloc: too many sweeps in one call");
+    uint32_t *ws = nullptr;
+    if ((rc = scratch_address(&ws))) return rc;
+    if (c->prec == CC_F64)
+        return sweep_noalloc_t<double>(c, ws, (double *)x, (double *)f, (double *)y, (double *)yp,
+                                       (const double *)g, d, nsweeps);
+    return sweep_noalloc_t<float>(c, ws, (float *)x, (float *)f, (float *)y, (float *)yp,
+                                  (const float *)g, d, nsweeps);
 }
 
 int cc_sweep_metric(cc_ctx *c, void *x, void *y, const void *g, int32_t exec) {
