@@ -455,13 +455,19 @@ int cc_mlp_infer(cc_ctx *ctx, const float *params, const float *deg, const doubl
 /* Warm start: y = network prediction for every metric row (0 on padding),
  * y_pair = 0, (x, f) = v(y), then one pair pass (which gives the pair duals
  * their best values for this y: the two pair rows of a pair are
- * W-orthogonal).  The start is kept only if its dual objective is at least
- * the cold start's after its first pair pass; otherwise the state is reset
- * to the cold start.  *accepted (nullable) tells which; *dual_warm and
- * *dual_cold (nullable) return the two dual values.  g from cc_prepare. */
+ * W-orthogonal).  The gate compares the dual objective D of this start,
+ * D_warm, with the cold start's after its first pair pass, D_cold, against
+ * an upper bound U on the optimum (the objective at the best constant
+ * point x = c, f = |c - d|, which satisfies every row): the start is kept
+ * only if D_warm - D_cold >= 0.05 (U - D_cold), i.e. if it closes at least
+ * 5% of the gap a cold start faces; otherwise the state is reset to the
+ * cold start.  *accepted (nullable) tells which; *dual_warm, *dual_cold and
+ * *dual_bound (nullable) return D_warm, D_cold and U.  g from cc_prepare.
+ * Synchronises. */
 int cc_warm_start_mlp(cc_ctx *ctx, const float *params, const float *deg, const double *w,
                       const uint8_t *d, double gamma, void *x, void *f, void *y, void *y_pair,
-                      const void *g, int32_t *accepted, double *dual_warm, double *dual_cold);
+                      const void *g, int32_t *accepted, double *dual_warm, double *dual_cold,
+                      double *dual_bound);
 
 /* One-shot solve from host arrays (allocates its own device buffers).
  * w_host: double[N_p] > 0; d_host: uint8[N_p]; tol: stop when both max

@@ -118,7 +118,7 @@ _sig("cc_mlp_train_graph", ctypes.c_int, _p, _p, _p, _p, _p, _i64, ctypes.c_uint
 _sig("cc_mlp_slot_features", ctypes.c_int, _p, _p, _p, _p, _p, _i64, _p)
 _sig("cc_mlp_infer", ctypes.c_int, _p, _p, _p, _p, _p, _p)
 _sig("cc_warm_start_mlp", ctypes.c_int, _p, _p, _p, _p, _p, _dbl, _p, _p, _p, _p, _p,
-     ctypes.POINTER(_i32), ctypes.POINTER(_dbl), ctypes.POINTER(_dbl))
+     ctypes.POINTER(_i32), ctypes.POINTER(_dbl), ctypes.POINTER(_dbl), ctypes.POINTER(_dbl))
 
 EXPORTS = ["cc_last_error", "cc_num_metric_duals", "cc_create", "cc_destroy", "cc_dual_slots",
            "cc_num_rounds", "cc_prepare", "cc_init_cold", "cc_sweep", "cc_sweep_rounds",

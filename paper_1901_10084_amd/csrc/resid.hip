@@ -205,6 +205,26 @@ k_nearness_pair_resid(int64_t np, const T *__restrict__ x, const double *__restr
         for (int e = 0; e < 10; ++e) partial[int64_t(blockIdx.x) * 10 + e] = v[e];
 }
 
+// Weight of the positive and of the negative pairs, in k_pair_resid's
+// partial slots 1 (sum of w over d = 0) and 2 (sum of w over d = 1), the
+// others 0, so that k_final_reduce returns them as out[5] and out[6].
+__global__ void __launch_bounds__(256)
+k_weight_classes(int64_t np, const double *__restrict__ w, const uint8_t *__restrict__ d,
+                 double *__restrict__ partial) {
+    __shared__ double red[10 * 16];
+    double w0 = 0.0, w1 = 0.0;
+    for (int64_t p = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; p < np;
+         p += int64_t(gridDim.x) * blockDim.x) {
+        if (d[p]) w1 += w[p];
+        else w0 += w[p];
+    }
+    double v[10] = {0, w0, w1, 0, 0, 0, 0, 0, 0, 0};
+    const int op[10] = {1, 0, 0, 0, 1, 0, 0, 0, 1, 1};
+    block_reduce<10>(v, op, red);
+    if (threadIdx.x == 0)
+        for (int e = 0; e < 10; ++e) partial[int64_t(blockIdx.x) * 10 + e] = v[e];
+}
+
 // Fixed-order final reduction: out[0..3] from the metric partials, out[4..13]
 // from the pair partials.
 __global__ void __launch_bounds__(256)
@@ -407,6 +427,12 @@ int launch_final_reduce(const double *mpart, int64_t nm, const double *ppart, do
     hipLaunchKernelGGL(k_final_reduce, dim3(1), dim3(256), 0, s, mpart, nm, ppart,
                        int64_t(kPairBlocks), out);
     CCP_LAUNCH_CHECK("k_final_reduce");
+    return CC_OK;
+}
+
+int launch_weight_classes(int64_t np, const double *w, const uint8_t *d, double *partial, hipStream_t s) {
+    hipLaunchKernelGGL(k_weight_classes, dim3(kPairBlocks), dim3(256), 0, s, np, w, d, partial);
+    CCP_LAUNCH_CHECK("k_weight_classes");
     return CC_OK;
 }
 

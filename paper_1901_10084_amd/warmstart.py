@@ -108,15 +108,18 @@ def infer(solver, net: Network, deg, y_out):
 def warm_start(solver, net: Network, deg) -> dict:
     """Gated learned warm start of a Solver in place (see cc_warm_start_mlp)."""
     acc = ctypes.c_int32()
-    dw, dc = ctypes.c_double(), ctypes.c_double()
+    dw, dc, ub = ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
     C.check(C._L.cc_warm_start_mlp(solver.ctx.handle, net.params.data_ptr(), deg.data_ptr(),
                                    solver.w.data_ptr(), solver.d.data_ptr(), solver.gamma,
                                    solver.x.data_ptr(), solver.f.data_ptr(), solver.y.data_ptr(),
                                    solver.y_pair.data_ptr(), solver.g.data_ptr(),
-                                   ctypes.byref(acc), ctypes.byref(dw), ctypes.byref(dc)))
+                                   ctypes.byref(acc), ctypes.byref(dw), ctypes.byref(dc),
+                                   ctypes.byref(ub)))
     solver.invalidate_mask()
     solver.sweeps = 0
-    return {"accepted": bool(acc.value), "dual_warm": dw.value, "dual_cold": dc.value}
+    return {"accepted": bool(acc.value), "dual_warm": dw.value, "dual_cold": dc.value,
+            "dual_bound": ub.value,
+            "gap_share": (dw.value - dc.value) / (ub.value - dc.value)}
 
 
 def degrees(inst, device="cuda"):

@@ -242,3 +242,22 @@ def test_gate_rejects_a_bad_prediction():
         assert info["dual_warm"] < info["dual_cold"]
         for a in ("x", "f", "y", "y_pair"):
             assert torch.equal(getattr(warm, a), getattr(cold, a)), a
+
+
+def test_gate_bound_and_share():
+    """The gate's bound U is the objective of (qp) at the best constant point
+    x = c, f = |c - d| (every row holds there), found here by brute force
+    over c; it lies above the optimum the solve reaches, and the kept start
+    closes at least 5% of the gap U - D_cold."""
+    inst = I.training_graph(2002)
+    w, d, gam = inst.w.astype(np.float64), inst.d.astype(np.float64), inst.gamma
+    cs = np.linspace(0.0, 1.0, 20001)
+    P = [float(np.sum(w * np.abs(c - d)) + np.sum(w * (c * c + (c - d) ** 2)) / (2 * gam)) for c in cs]
+    s = C.Solver.from_instance(inst, b=16, prec="f64")
+    info = W.warm_start(s, W.load(), W.degrees(inst))
+    print(info, min(P), flush=True)
+    assert abs(info["dual_bound"] - min(P)) <= 1e-9 * min(P)
+    r, conv, _ = s.solve(tol=1e-8)
+    assert conv and r["primal_qp"] <= info["dual_bound"]
+    assert info["dual_cold"] <= info["dual_warm"] <= r["primal_qp"]
+    assert info["accepted"] and info["gap_share"] >= 0.05
