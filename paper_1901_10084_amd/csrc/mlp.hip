@@ -410,23 +410,26 @@ k_mlp_infer(GraphView G, const float *__restrict__ P, T *__restrict__ y) {
 
 // Inference-only form of the network: all three layers on
 // v_mfma_f32_16x16x32_bf16, biases entering as the accumulator input.
-//   layer 1: A = W1 with K padded from 4 to 32, the 4 real columns repeated
-//            in every lane group's K slots; B = the features of the pass's
-//            16 samples in the K slots of one lane group, zero elsewhere.
-//            Lane l receives units U_g of sample l % 16: layer 2's B operand.
-//   layer 2: as in forward().
-//   layer 3: A = W3 (permuted like K) on every row, so every row of the
-//            output is the sample's pre-activation.
 // A 64-slot group runs as four passes; in pass q the samples are those of
 // lane group q, and lane l of that group holds sample l itself.  Each lane
-// therefore computes the features of its own sample once and keeps the
-// output of its own sample.
+// puts its own sample's 4 features in its lane group's K slots (B operand),
+// computes them once and keeps its own sample's output.
+//   layer 1: A = W1 in the K slots of lane group q only (zero elsewhere),
+//            with K padded from 4 to 32, so pass q's product reads only
+//            group q's features.  Lane l receives units U_g of sample
+//            l % 16 of pass q: layer 2's B operand.
+//   layer 2: as in forward().
+//   layer 3: A = W3 (permuted like K) on the output rows of lane group q
+//            only, the four passes chained through the accumulator from b3:
+//            row group g collects pass g's output, so lane l ends with the
+//            output of its own sample, with no selects.  (The other passes
+//            add exact zeros to a row group: the same sums as one product.)
 struct InferNet {
-    bf16x8 a1[2];  // a1[t][c] = W1[16t + i][c] for c < 4, else 0 (c = K slot in the lane group)
-    bf16x8 a2[2];  // as LaneNet::a2
-    bf16x8 a3;     // a3[c] = W3[U_g[c]]
-    f32x4 c1[2];   // c1[t][r] = b1[16t + 4g + r]
-    f32x4 c2[2];   // c2[t][r] = b2[16t + 4g + r]
+    bf16x8 a1[4][2];  // a1[q][t][c] = W1[16t + i][c] if g == q and c < 4, else 0
+    bf16x8 a2[2];     // as LaneNet::a2
+    bf16x8 a3[4];     // a3[q][c] = W3[U_g[c]] if i / 4 == q, else 0
+    f32x4 c1[2];      // c1[t][r] = b1[16t + 4g + r]
+    f32x4 c2[2];      // c2[t][r] = b2[16t + 4g + r]
     float b3;
 };
 
@@ -436,7 +439,9 @@ __device__ __forceinline__ void load_infer_net(InferNet &N, const float *__restr
     for (int t = 0; t < 2; ++t) {
 #pragma unroll
         for (int c = 0; c < 8; ++c) {
-            N.a1[t][c] = tobf(c < 4 ? P[oW1 + (16 * t + i) * 4 + c] : 0.0f);
+            const float w1 = c < 4 ? P[oW1 + (16 * t + i) * 4 + c] : 0.0f;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) N.a1[q][t][c] = tobf(g == q ? w1 : 0.0f);
             N.a2[t][c] = tobf(P[oW2 + (16 * t + i) * 32 + unit_of(g, c)]);
         }
 #pragma unroll
@@ -446,7 +451,11 @@ __device__ __forceinline__ void load_infer_net(InferNet &N, const float *__restr
         }
     }
 #pragma unroll
-    for (int c = 0; c < 8; ++c) N.a3[c] = tobf(P[oW3 + unit_of(g, c)]);
+    for (int c = 0; c < 8; ++c) {
+        const float w3 = P[oW3 + unit_of(g, c)];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) N.a3[q][c] = tobf(i / 4 == q ? w3 : 0.0f);
+    }
     N.b3 = P[oB3];
 }
 
@@ -474,20 +483,17 @@ __device__ __forceinline__ bf16x8 relu_bf16(const f32x4 lo, const f32x4 hi) {
     return h;
 }
 
-// The four passes of a 64-row group, layer by layer: lane group q carries
-// pass q's features in x (zero in the other lane groups), and lane l of
-// group q receives row l's output.  The passes are independent, so running
-// them layer by layer puts one pass's VALU work in another's MFMA latency.
+// The four passes of a 64-row group, layer by layer: every lane carries its
+// own sample's features in feat, and lane l receives its own sample's
+// output.  The passes are independent until layer 3, so running them layer
+// by layer puts one pass's VALU work in another's MFMA latency.
 __device__ __forceinline__ float infer_group(const InferNet &N, const bf16x8 feat) {
-    const int g = (threadIdx.x & 63) >> 4;
-    const bf16x8 zero8 = {};
     f32x4 z[4][2];
     bf16x8 h[4];
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
-        const bf16x8 x = g == q ? feat : zero8;
-        z[q][0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(N.a1[0], x, N.c1[0], 0, 0, 0);
-        z[q][1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(N.a1[1], x, N.c1[1], 0, 0, 0);
+        z[q][0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(N.a1[q][0], feat, N.c1[0], 0, 0, 0);
+        z[q][1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(N.a1[q][1], feat, N.c1[1], 0, 0, 0);
     }
 #pragma unroll
     for (int q = 0; q < 4; ++q) h[q] = relu_bf16(z[q][0], z[q][1]);
@@ -498,14 +504,10 @@ __device__ __forceinline__ float infer_group(const InferNet &N, const bf16x8 fea
     }
 #pragma unroll
     for (int q = 0; q < 4; ++q) h[q] = relu_bf16(z[q][0], z[q][1]);
-    const f32x4 c3 = {N.b3, N.b3, N.b3, N.b3};
-    float out = 0.0f;
+    f32x4 z3 = {N.b3, N.b3, N.b3, N.b3};
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-        const f32x4 z3 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(N.a3, h[q], c3, 0, 0, 0);
-        if (g == q) out = z3[0];
-    }
-    return out > 0.0f ? out : 0.0f;
+    for (int q = 0; q < 4; ++q) z3 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(N.a3[q], h[q], z3, 0, 0, 0);
+    return z3[0] > 0.0f ? z3[0] : 0.0f;
 }
 
 // The inference for b = 8, 16, 32, walking the tile's segment in its own
@@ -522,8 +524,10 @@ k_mlp_infer_tiled(GraphView G, const float *__restrict__ P, T *__restrict__ y) {
     constexpr int b = B, bb = B * B;
     InferNet N;
     load_infer_net(N, P);
-    const int lane = threadIdx.x & 63, g = lane >> 4;
-    const int wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    const int lane = threadIdx.x & 63;
+    // wave-uniform, so that a group's sub-step, orientation and first slot
+    // sit in scalar registers and its feature selects are scalar
+    const int wave = __builtin_amdgcn_readfirstlane(int(threadIdx.x >> 6)), nw = blockDim.x >> 6;
     const int m0 = G.chunks[2 * int64_t(blockIdx.x) + 1];
     const Tile tl = G.tiles[G.chunks[2 * int64_t(blockIdx.x)]];
     const int Pb = tl.P, Qb = tl.Q;
@@ -533,7 +537,7 @@ k_mlp_infer_tiled(GraphView G, const float *__restrict__ P, T *__restrict__ y) {
     __shared__ float swA[bb], swB[bb], swC[bb], fA[bb], fB[bb], fC[bb], dP[b], dJ[b], dQ[b];
     const float md = G.mean_deg[0];
     const float den = 2.0f * md;
-    const float outscale = float(G.n - 2);
+    const float inv_scale = 1.0f / float(G.n - 2);
     auto sw = [&](int r, int c) {  // signed weight of pair (r, c), 0 if none
         if (!(r < c && c < nn)) return 0.0f;
         const int64_t p = pidx(r, c);
@@ -589,7 +593,7 @@ k_mlp_infer_tiled(GraphView G, const float *__restrict__ P, T *__restrict__ y) {
             feat[2] = f23[0];
             feat[3] = f23[1];
             const float out = infer_group(N, feat);
-            ytile[(int64_t(m) * b + t) * 3 * bb + o * bb + L] = T(ok ? out / outscale : 0.0f);
+            ytile[(int64_t(m) * b + t) * 3 * bb + o * bb + L] = T(ok ? out * inv_scale : 0.0f);
         }
     }
 }
