@@ -8,6 +8,7 @@
 #include <vector>
 
 #include "common.hpp"
+#include "dataflow.hpp"
 
 namespace ccp {
 
@@ -41,23 +42,7 @@ template <typename T> int launch_x_from_aty(int64_t, const double *, const T *, 
 template <typename T> int launch_to_lex(const Tile *, int64_t, int, int64_t, const T *, T *, hipStream_t);
 int launch_slots_to_lex(const Tile *, int64_t, int, int64_t, const int64_t *, int64_t, int64_t *, hipStream_t);
 
-struct DTile {
-    int32_t P, Q;
-    int64_t ybase;
-    int32_t jsbase;
-    uint32_t needC;
-};
-struct DataflowArgs {
-    const DTile *tiles;
-    int ntiles;
-    const uint32_t *needs;
-    const uint32_t *K;
-    uint32_t *cnt;
-    uint32_t *ctl;
-    uint32_t epoch;
-    uint64_t wait_ticks;
-    unsigned long long *prof;
-};
+
 void build_dataflow_tables(int64_t n, int b, std::vector<DTile> &tiles, std::vector<uint32_t> &needs,
                            std::vector<uint32_t> &K);
 template <typename T> int launch_sweep_dataflow(const DataflowArgs &, int, int, int64_t, T *, const T *, T *, void *, const CompactArgs<T> *, hipStream_t);
@@ -67,6 +52,10 @@ template <typename T> int launch_mask_build(int, int64_t, const T *, void *, hip
 template <typename T> int launch_sweep_colour(int64_t, T *, const T *, T *, hipStream_t);
 template <typename T> int dataflow_occupancy(int, int *);
 template <typename T> int launch_aty_dataflow(const DataflowArgs &, int, int, int64_t, const T *, double *, hipStream_t);
+int launch_dataflow_reset(uint32_t *, hipStream_t);
+template <typename T>
+int launch_infer_aty_dataflow(const DataflowArgs &, int, const GraphView &, const float *, T *, double *, hipStream_t);
+template <typename T> int infer_aty_occupancy(int, int *);
 template <typename T> int aty_dataflow_occupancy(int, int *);
 int launch_fill_u32(int64_t, uint32_t *, hipStream_t);
 
@@ -120,6 +109,7 @@ struct cc_ctx {
     int df_grid_sparse = 0;
     int df_grid_cap = 0;
     int aty_grid = 0;
+    int iad_grid = 0;  // workgroups of the fused inference + A'y launch
     uint64_t wait_ticks = 0;
     float *d_mean_deg = nullptr;  // warm-start features
     int32_t *d_chunks = nullptr;  // (tile, first step) per chunk of kChunkSteps tile steps
@@ -273,6 +263,10 @@ int ensure_dataflow(cc_ctx *c) {
     if (rc) return rc;
     if (per_cu < 1) return fail(CC_EHIP, "dataflow A'y kernel does not fit on a compute unit");
     c->aty_grid = int(std::min<int64_t>(c->ntiles, std::min<int64_t>(per_cu, need_per_cu) * cus));
+    rc = (c->prec == CC_F64) ? infer_aty_occupancy<double>(c->b, &per_cu) : infer_aty_occupancy<float>(c->b, &per_cu);
+    if (rc) return rc;
+    if (per_cu < 1) return fail(CC_EHIP, "fused inference kernel does not fit on a compute unit");
+    c->iad_grid = int(std::min<int64_t>(c->ntiles, std::min<int64_t>(per_cu, need_per_cu) * cus));
     c->wait_ticks = uint64_t(khz > 0 ? khz : 100000) * 1000ull * 10ull;  // 10 s per wait
     return CC_OK;
 }
@@ -1286,9 +1280,23 @@ int warm_start_t(cc_ctx *c, const float *P, const float *deg, const double *w, c
     int rc;
     if ((rc = graph_view(c, w, d, deg, G))) return rc;
     // predicted metric duals, pair duals 0, v = v(y), one pair pass
-    if ((rc = launch_mlp_infer<T>(G, P, y, c->stream))) return rc;
-    if ((rc = launch_init_cold<T>(np, c->slots, x, f, nullptr, yp, gamma, c->stream))) return rc;
-    if ((rc = x_from_y_t<T>(c, y, yp, w, gamma, x, f))) return rc;
+    if (dataflow_b(c->b) && c->iad_grid > 0) {
+        // inference fused with A'y: the predictions are summed into the
+        // pairs' accumulators as they are written, never read back
+        if ((rc = ensure_ax(c))) return rc;
+        CCP_HIP_CHECK(hipMemsetAsync(c->d_ax, 0, size_t(np) * sizeof(double), c->stream));
+        DataflowArgs a;
+        if ((rc = dataflow_args(c, nullptr, a)) || (rc = launch_dataflow_reset(a.ctl, c->stream)) ||
+            (rc = launch_infer_aty_dataflow<T>(a, c->iad_grid, G, P, y, c->d_ax, c->stream)))
+            return rc;
+        c->epoch++;
+        if ((rc = launch_init_cold<T>(np, c->slots, x, f, nullptr, yp, gamma, c->stream))) return rc;
+        if ((rc = launch_x_from_aty<T>(np, c->d_ax, yp, w, gamma, x, f, c->stream))) return rc;
+    } else {
+        if ((rc = launch_mlp_infer<T>(G, P, y, c->stream))) return rc;
+        if ((rc = launch_init_cold<T>(np, c->slots, x, f, nullptr, yp, gamma, c->stream))) return rc;
+        if ((rc = x_from_y_t<T>(c, y, yp, w, gamma, x, f))) return rc;
+    }
     if ((rc = launch_pair_pass<T>(np, x, f, yp, g, d, c->stream))) return rc;
     double Dw = 0.0, Dc = 0.0, Ub = 0.0;
     if ((rc = dual_value<T>(c, x, f, yp, w, d, c->d_ax, gamma, &Dw))) return rc;

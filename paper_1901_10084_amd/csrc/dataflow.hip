@@ -42,6 +42,7 @@
 #include <vector>
 
 #include "common.hpp"
+#include "dataflow.hpp"
 #include "project.hpp"
 
 namespace ccp {
@@ -89,14 +90,8 @@ __device__ __forceinline__ void buf_store(float v, __amdgpu_buffer_rsrc_t r, uin
     __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, v), r, int(off), 0, kBufNT);
 }
 
-struct DTile {
-    int32_t P, Q;
-    int64_t ybase;
-    int32_t jsbase;  // index of the tile's first step in the `needs` table
-    uint32_t needC;  // touches of block (P,Q) before this tile, per sweep
-};
 
-__host__ __device__ __forceinline__ int block_id(int A, int B) { return B * (B + 1) / 2 + A; }
+
 
 // ---------------------------------------------------------------------------
 // Host: dependency tables.  For tile step (tile, m) with middle block J the
@@ -142,52 +137,7 @@ void build_dataflow_tables(int64_t n, int b, std::vector<DTile> &tiles,
 // ---------------------------------------------------------------------------
 // Device.
 // ---------------------------------------------------------------------------
-struct DataflowArgs {
-    const DTile *tiles;
-    int ntiles;
-    const uint32_t *needs;
-    const uint32_t *K;
-    uint32_t *cnt;       // completed touches per block (cumulative over epochs), stride kCntStride
-    uint32_t *ctl;       // [0] ticket counter, [1] abort flag
-    uint32_t epoch;      // sweeps already run on these counters
-    uint64_t wait_ticks; // wall-clock limit of one wait
-    unsigned long long *prof;  // optional: wall-clock ticks per phase, summed
-};
 
-// Thread 0 only.  True once each of the three counters has reached its
-// need; false on time-out or abort.  The counters and the abort flag are
-// read in the same round trip; an unused slot reads the abort flag with
-// need 0, which it always meets (the flag is 0 or 1).
-__device__ __forceinline__ bool wait_counts(const uint32_t *c0, uint32_t n0, const uint32_t *c1, uint32_t n1,
-                                            const uint32_t *c2, uint32_t n2, uint32_t *abort_flag,
-                                            uint64_t ticks) {
-    const uint64_t start = wall_clock64();
-    bool res;
-    for (;;) {
-        const uint32_t v0 = __hip_atomic_load(c0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        const uint32_t v1 = __hip_atomic_load(c1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        const uint32_t v2 = __hip_atomic_load(c2, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        const uint32_t ab = __hip_atomic_load(abort_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        if (int32_t(v0 - n0) >= 0 && int32_t(v1 - n1) >= 0 && int32_t(v2 - n2) >= 0) {
-            res = true;
-            break;
-        }
-        if (ab) {
-            res = false;
-            break;
-        }
-        if (wall_clock64() - start > ticks) {
-            __hip_atomic_store(abort_flag, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            res = false;
-            break;
-        }
-        __builtin_amdgcn_s_sleep(1);
-    }
-    // No poll may stay in flight: a load pending at the step loop's head
-    // makes the compiler drain every wave's stores before the next loads.
-    __builtin_amdgcn_s_waitcnt(0);
-    return res;
-}
 
 template <typename T, int B, int D, bool SP, bool CP>
 __global__ void __launch_bounds__(B * B)
@@ -819,6 +769,12 @@ __global__ void k_dataflow_reset(uint32_t *ctl) {
     if (threadIdx.x == 0) {
         ctl[0] = 0u;
     }
+}
+
+int launch_dataflow_reset(uint32_t *ctl, hipStream_t s) {
+    hipLaunchKernelGGL(k_dataflow_reset, dim3(1), dim3(64), 0, s, ctl);
+    CCP_LAUNCH_CHECK("k_dataflow_reset");
+    return CC_OK;
 }
 
 __global__ void k_fill_u32(int64_t count, uint32_t *a) {

@@ -18,7 +18,11 @@
 // the D rows it receives are again units U_g, so every layer stays in
 // registers.  The weight gradient dW2 = sum over samples of delta2 h1^T is an
 // MFMA with K = 32 samples, fed through a small LDS transpose.
+#include <type_traits>
+
 #include "common.hpp"
+#include "dataflow.hpp"
+#include "project.hpp"
 
 namespace ccp {
 
@@ -510,6 +514,125 @@ __device__ __forceinline__ float infer_group(const InferNet &N, const bf16x8 fea
     return z3[0] > 0.0f ? z3[0] : 0.0f;
 }
 
+// The same network in fewer registers, for the fused kernel at b = 24 and
+// 32 (576 and 1024 lanes a workgroup leave 168 and 128 registers a lane):
+// one copy of W1 and W3 in every lane group, the features of pass q kept
+// only in lane group q's K slots and the output taken from pass q in lane
+// group q, two passes at a time.  The products and sums are those of
+// infer_group (the same nonzero products in the same K slots; the other
+// passes' rows add exact zeros there), so the outputs are the same bits.
+struct InferNetSmall {
+    bf16x8 a1[2];  // a1[t][c] = W1[16t + i][c] for c < 4, else 0
+    bf16x8 a2[2];
+    bf16x8 a3;     // a3[c] = W3[U_g[c]] on every row
+    f32x4 c1[2];
+    f32x4 c2[2];
+    float b3;
+};
+
+__device__ __forceinline__ void load_infer_net(InferNetSmall &N, const float *__restrict__ P) {
+    const int lane = threadIdx.x & 63, i = lane & 15, g = lane >> 4;
+#pragma unroll
+    for (int t = 0; t < 2; ++t) {
+#pragma unroll
+        for (int c = 0; c < 8; ++c) {
+            N.a1[t][c] = tobf(c < 4 ? P[oW1 + (16 * t + i) * 4 + c] : 0.0f);
+            N.a2[t][c] = tobf(P[oW2 + (16 * t + i) * 32 + unit_of(g, c)]);
+        }
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            N.c1[t][r] = P[oB1 + 16 * t + 4 * g + r];
+            N.c2[t][r] = P[oB2 + 16 * t + 4 * g + r];
+        }
+    }
+#pragma unroll
+    for (int c = 0; c < 8; ++c) N.a3[c] = tobf(P[oW3 + unit_of(g, c)]);
+    N.b3 = P[oB3];
+}
+
+__device__ __forceinline__ float infer_group(const InferNetSmall &N, const bf16x8 feat) {
+    const int g = (threadIdx.x & 63) >> 4;
+    const bf16x8 zero8 = {};
+    const f32x4 c3 = {N.b3, N.b3, N.b3, N.b3};
+    float out = 0.0f;
+#pragma unroll
+    for (int q0 = 0; q0 < 4; q0 += 2) {
+        f32x4 z[2][2];
+        bf16x8 h[2];
+#pragma unroll
+        for (int q = 0; q < 2; ++q) {
+            const bf16x8 x = g == q0 + q ? feat : zero8;
+            z[q][0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(N.a1[0], x, N.c1[0], 0, 0, 0);
+            z[q][1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(N.a1[1], x, N.c1[1], 0, 0, 0);
+        }
+#pragma unroll
+        for (int q = 0; q < 2; ++q) h[q] = relu_bf16(z[q][0], z[q][1]);
+#pragma unroll
+        for (int q = 0; q < 2; ++q) {
+            z[q][0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(N.a2[0], h[q], N.c2[0], 0, 0, 0);
+            z[q][1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(N.a2[1], h[q], N.c2[1], 0, 0, 0);
+        }
+#pragma unroll
+        for (int q = 0; q < 2; ++q) h[q] = relu_bf16(z[q][0], z[q][1]);
+#pragma unroll
+        for (int q = 0; q < 2; ++q) {
+            const f32x4 z3 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(N.a3, h[q], c3, 0, 0, 0);
+            if (g == q0 + q) out = z3[0];
+        }
+    }
+    return out > 0.0f ? out : 0.0f;
+}
+
+// The inference for b = 8, 16, 32, walking the tile's segment in its own
+// order instead of decoding every slot.  A workgroup takes one chunk of a
+// tile's steps.  Per tile step the signed weights of blocks (P,J), (J,Q),
+// (P,Q) and the degrees of the three vertex blocks sit in LDS, and a wave
+// takes 64 consecutive slots (one sub-step t, one orientation o, lanes
+// L0..L0+63), lane l computing the features and the output of slot L0 + l,
+// so the store is contiguous.  Features are those of k_mlp_infer bit for
+// bit; outputs differ only in fp32 summation order.
+// Signed weight of pair (r, c) rounded to bf16, 0 where (r, c) is no pair.
+__device__ __forceinline__ float signed_weight(const GraphView &G, int r, int c) {
+    if (!(r < c && c < int(G.n))) return 0.0f;
+    const int64_t p = pidx(r, c);
+    return bf16r(float(G.d[p] == 0 ? G.w[p] : -G.w[p]));
+}
+__device__ __forceinline__ float vertex_degree(const GraphView &G, int v) { return v < int(G.n) ? G.deg[v] : 0.0f; }
+// degree feature of a pair whose endpoints have degrees da, db
+__device__ __forceinline__ float degree_feature(float da, float db, float md) {
+    return bf16r(md > 0.0f ? (da + db) / (2.0f * md) : 0.0f);
+}
+
+// Features of slot (sub-step t, orientation o, lane L) of a tile step with
+// blocks P, J, Q, from the step's tables (signed weights and degree
+// features of blocks A = (P,J), B = (J,Q), C = (P,Q), [row * b + col]);
+// ok = the slot is a triplet (else the features are zero).
+template <int B>
+__device__ __forceinline__ bf16x8 step_features(const float *swA, const float *swB, const float *swC,
+                                                const float *fA, const float *fB, const float *fC, int t,
+                                                int o, int L, int P, int J, int Q, int nn, bool &ok) {
+    constexpr int b = B;
+    const int il = L / b, kl = L % b;
+    const int jl = mid_offset(t, il, kl, b);
+    const int i = P * b + il, j = J * b + jl, k = Q * b + kl;
+    ok = i < j && j < k && k < nn;
+    const int eA = il * b + jl, eC = il * b + kl, eB = jl * b + kl;
+    const float wij = swA[eA], wik = swC[eC], wjk = swB[eB];
+    // long side ij, ik or jk
+    const float p0 = o == 0 ? wij : (o == 1 ? wik : wjk);
+    const float p1 = o == 0 ? wik : wij;
+    const float p2 = o == 0 ? wjk : (o == 1 ? wjk : wik);
+    const float p3 = o == 0 ? fA[eA] : (o == 1 ? fC[eC] : fB[eB]);
+    const bf16x2 f01 = tobf2(ok ? p0 : 0.0f, ok ? p1 : 0.0f);
+    const bf16x2 f23 = tobf2(ok ? p2 : 0.0f, ok ? p3 : 0.0f);
+    bf16x8 feat = {};
+    feat[0] = f01[0];
+    feat[1] = f01[1];
+    feat[2] = f23[0];
+    feat[3] = f23[1];
+    return feat;
+}
+
 // The inference for b = 8, 16, 32, walking the tile's segment in its own
 // order instead of decoding every slot.  A workgroup takes one chunk of a
 // tile's steps.  Per tile step the signed weights of blocks (P,J), (J,Q),
@@ -536,65 +659,203 @@ k_mlp_infer_tiled(GraphView G, const float *__restrict__ P, T *__restrict__ y) {
     const int m1 = min(m0 + kChunkSteps, Qb - Pb + 1);  // this chunk's steps: [m0, m1)
     __shared__ float swA[bb], swB[bb], swC[bb], fA[bb], fB[bb], fC[bb], dP[b], dJ[b], dQ[b];
     const float md = G.mean_deg[0];
-    const float den = 2.0f * md;
     const float inv_scale = 1.0f / float(G.n - 2);
-    auto sw = [&](int r, int c) {  // signed weight of pair (r, c), 0 if none
-        if (!(r < c && c < nn)) return 0.0f;
-        const int64_t p = pidx(r, c);
-        return bf16r(float(G.d[p] == 0 ? G.w[p] : -G.w[p]));
-    };
-    auto degv = [&](int v) { return v < nn ? G.deg[v] : 0.0f; };
-    // degree feature of the pair of block entries (r, c)
-    auto fdeg = [&](float da, float db) { return bf16r(md > 0.0f ? (da + db) / den : 0.0f); };
     for (int e = threadIdx.x; e < b; e += blockDim.x) {
-        dP[e] = degv(Pb * b + e);
-        dQ[e] = degv(Qb * b + e);
+        dP[e] = vertex_degree(G, Pb * b + e);
+        dQ[e] = vertex_degree(G, Qb * b + e);
     }
     __syncthreads();
     for (int e = threadIdx.x; e < bb; e += blockDim.x) {
-        swC[e] = sw(Pb * b + e / b, Qb * b + e % b);
-        fC[e] = fdeg(dP[e / b], dQ[e % b]);
+        swC[e] = signed_weight(G, Pb * b + e / b, Qb * b + e % b);
+        fC[e] = degree_feature(dP[e / b], dQ[e % b], md);
     }
     T *const ytile = y + tl.ybase;
     constexpr int gps = 3 * bb / 64;  // 64-slot groups per sub-step
-    const bf16x8 zero8 = {};
     for (int m = m0; m < m1; ++m) {
         const int J = tile_J(Pb, Qb, m, desc);
         __syncthreads();  // the last step's readers are done
-        for (int e = threadIdx.x; e < b; e += blockDim.x) dJ[e] = degv(J * b + e);
+        for (int e = threadIdx.x; e < b; e += blockDim.x) dJ[e] = vertex_degree(G, J * b + e);
         __syncthreads();
         for (int e = threadIdx.x; e < bb; e += blockDim.x) {
-            swA[e] = sw(Pb * b + e / b, J * b + e % b);
-            swB[e] = sw(J * b + e / b, Qb * b + e % b);
-            fA[e] = fdeg(dP[e / b], dJ[e % b]);
-            fB[e] = fdeg(dJ[e / b], dQ[e % b]);
+            swA[e] = signed_weight(G, Pb * b + e / b, J * b + e % b);
+            swB[e] = signed_weight(G, J * b + e / b, Qb * b + e % b);
+            fA[e] = degree_feature(dP[e / b], dJ[e % b], md);
+            fB[e] = degree_feature(dJ[e / b], dQ[e % b], md);
         }
         __syncthreads();
         for (int grp = wave; grp < b * gps; grp += nw) {
             const int t = grp / gps, rem = grp - t * gps;
             const int o = rem / (bb / 64), L0 = (rem - o * (bb / 64)) * 64;
-            const int L = L0 + lane;
-            const int il = L / b, kl = L % b;
-            const int jl = mid_offset(t, il, kl, b);
-            const int i = Pb * b + il, j = J * b + jl, k = Qb * b + kl;
-            const bool ok = i < j && j < k && k < nn;
-            const int eA = il * b + jl, eC = il * b + kl, eB = jl * b + kl;
-            const float wij = swA[eA], wik = swC[eC], wjk = swB[eB];
-            // o is the same for the whole group: long side ij, ik or jk
-            const float p0 = o == 0 ? wij : (o == 1 ? wik : wjk);
-            const float p1 = o == 0 ? wik : wij;
-            const float p2 = o == 0 ? wjk : (o == 1 ? wjk : wik);
-            const float p3 = o == 0 ? fA[eA] : (o == 1 ? fC[eC] : fB[eB]);
-            const bf16x2 f01 = tobf2(ok ? p0 : 0.0f, ok ? p1 : 0.0f);
-            const bf16x2 f23 = tobf2(ok ? p2 : 0.0f, ok ? p3 : 0.0f);
-            bf16x8 feat = zero8;
-            feat[0] = f01[0];
-            feat[1] = f01[1];
-            feat[2] = f23[0];
-            feat[3] = f23[1];
+            bool ok;
+            const bf16x8 feat = step_features<B>(swA, swB, swC, fA, fB, fC, t, o, L0 + lane, Pb, J, Qb, nn, ok);
             const float out = infer_group(N, feat);
-            ytile[(int64_t(m) * b + t) * 3 * bb + o * bb + L] = T(ok ? out * inv_scale : 0.0f);
+            ytile[(int64_t(m) * b + t) * 3 * bb + o * bb + L0 + lane] = T(ok ? out * inv_scale : 0.0f);
         }
+    }
+}
+
+// Warm-start inference fused with A'y on the dataflow executor (b = 8, 16,
+// 24, 32): one workgroup of b^2 lanes per tile, as in the sweep.  Per tile
+// step and sub-step t, lane (il, kl) computes the network's predictions of
+// its triplet's three rows (one 64-row group per orientation per wave: the
+// wave's lanes are 64 consecutive slots, as in k_mlp_infer_tiled), writes
+// them to y, and adds them into the FP64 accumulators of the triplet's
+// pairs in LDS, in the order of k_aty_dataflow: the predictions equal
+// k_mlp_infer_tiled's bit for bit (same features, same network code) and
+// the sums equal A'y of those duals bit for bit, without reading y back.
+// ax must hold zeros on entry.
+template <typename T, int B>
+__global__ void __launch_bounds__(B * B)
+k_infer_aty_dataflow(DataflowArgs a, GraphView G, const float *__restrict__ P, T *__restrict__ y,
+                     double *__restrict__ ax) {
+    constexpr int b = B, bb = B * B;
+    typename std::conditional<(B >= 24), InferNetSmall, InferNet>::type N;
+    load_infer_net(N, P);
+    const int tid = threadIdx.x;
+    const int il = tid / b, kl = tid % b;
+    const int sr = tid % b, sc = tid / b;
+    const int nn = int(G.n), nb = (nn + b - 1) / b;
+    __shared__ double Abuf[bb], Bbuf[bb], Cs[bb];
+    __shared__ float swA[bb], swB[bb], swC[bb], fA[bb], fB[bb], fC[bb], dP[b], dJ[b], dQ[b];
+    __shared__ int s_tix, s_ok;
+    const float md = G.mean_deg[0];
+    const float inv_scale = 1.0f / float(G.n - 2);
+
+    if (tid == 0) s_tix = int(atomicAdd(&a.ctl[0], 1u));
+    __syncthreads();
+    for (;;) {
+        const int tix = __builtin_amdgcn_readfirstlane(s_tix);
+        if (tix >= a.ntiles) break;
+        const DTile tl = a.tiles[tix];
+        const int Pb = tl.P, Qb = tl.Q;
+        const bool desc = tile_desc(Pb, Qb, nb);
+        const int i = Pb * b + il, k = Qb * b + kl;
+        const int idC = block_id(Pb, Qb);
+
+        auto blk_ok = [&](int R, int S) {
+            const int ii = R * b + sr, jj = S * b + sc;
+            return ii < jj && jj < nn;
+        };
+        // ax is read and written with agent-scope atomic accesses, released
+        // as in the sweep: stores complete in every wave, then the counters.
+        auto blk_load = [&](int R, int S) {
+            return __hip_atomic_load(&ax[blk_ok(R, S) ? pidx(R * b + sr, S * b + sc) : 0], __ATOMIC_RELAXED,
+                                     __HIP_MEMORY_SCOPE_AGENT);
+        };
+        auto blk_store = [&](int R, int S, double v, double *X) { X[sr * b + sc] = blk_ok(R, S) ? v : 0.0; };
+        auto publish = [&](int R, int S, const double *X) {
+            if (blk_ok(R, S))
+                __hip_atomic_store(&ax[pidx(R * b + sr, S * b + sc)], X[sr * b + sc], __ATOMIC_RELAXED,
+                                   __HIP_MEMORY_SCOPE_AGENT);
+        };
+        auto step_ids = [&](int m, int &idA, int &idB) {
+            const int J = tile_J(Pb, Qb, m, desc);
+            idA = (J != Qb) ? block_id(Pb, J) : -1;
+            idB = (J != Pb) ? block_id(J, Qb) : -1;
+        };
+        // thread 0: wait for step m's blocks (and, with withC, for (P,Q))
+        auto wait_step = [&](int m, bool withC) {
+            int idA, idB;
+            step_ids(m, idA, idB);
+            const uint32_t *nd = a.needs + 2 * int64_t(tl.jsbase + m);
+            uint32_t *const none = &a.ctl[1];
+            return wait_counts(idA >= 0 ? &a.cnt[int64_t(idA) * kCntStride] : none,
+                               idA >= 0 ? a.epoch * a.K[idA] + nd[0] : 0u,
+                               idB >= 0 ? &a.cnt[int64_t(idB) * kCntStride] : none,
+                               idB >= 0 ? a.epoch * a.K[idB] + nd[1] : 0u,
+                               withC ? &a.cnt[int64_t(idC) * kCntStride] : none,
+                               withC ? a.epoch * a.K[idC] + tl.needC : 0u, &a.ctl[1], a.wait_ticks);
+        };
+
+        if (tid < b) {
+            dP[tid] = vertex_degree(G, Pb * b + tid);
+            dQ[tid] = vertex_degree(G, Qb * b + tid);
+        }
+        if (tid == 0) {
+            const bool ok = wait_step(0, true);
+            if (ok) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+            s_ok = ok;
+        }
+        __syncthreads();
+        if (!__builtin_amdgcn_readfirstlane(s_ok)) break;
+        blk_store(Pb, Qb, blk_load(Pb, Qb), Cs);
+        swC[tid] = signed_weight(G, Pb * b + tid / b, Qb * b + tid % b);
+        fC[tid] = degree_feature(dP[tid / b], dQ[tid % b], md);
+
+        bool aborted = false;
+        for (int m = 0; m <= Qb - Pb; ++m) {
+            const int J = tile_J(Pb, Qb, m, desc);
+            int idA, idB;
+            step_ids(m, idA, idB);
+            double *const Ab = (J == Qb) ? Cs : Abuf;
+            double *const Bb = (J == Pb) ? Cs : Bbuf;
+            // unconditional, as in the sweep (Abuf / Bbuf are idle where A
+            // or B is the resident block)
+            const double va = blk_load(Pb, J), vb = blk_load(J, Qb);
+            if (tid < b) dJ[tid] = vertex_degree(G, J * b + tid);
+            blk_store(Pb, J, va, Abuf);
+            blk_store(J, Qb, vb, Bbuf);
+            __syncthreads();  // dJ
+            swA[tid] = signed_weight(G, Pb * b + tid / b, J * b + tid % b);
+            swB[tid] = signed_weight(G, J * b + tid / b, Qb * b + tid % b);
+            fA[tid] = degree_feature(dP[tid / b], dJ[tid % b], md);
+            fB[tid] = degree_feature(dJ[tid / b], dQ[tid % b], md);
+            __syncthreads();
+            T *const ystep = y + tl.ybase + int64_t(m) * b * 3 * bb;
+#pragma unroll 1
+            for (int t = 0; t < b; ++t) {
+                // one copy of the network code per sub-step (the orientation
+                // loop is not unrolled: three copies would not fit the
+                // registers at b = 32)
+                double y0 = 0.0, y1 = 0.0, y2 = 0.0;
+#pragma unroll 1
+                for (int o = 0; o < 3; ++o) {
+                    bool ok;
+                    const bf16x8 feat = step_features<B>(swA, swB, swC, fA, fB, fC, t, o, tid, Pb, J, Qb, nn, ok);
+                    const float out = infer_group(N, feat);
+                    const T v = T(ok ? out * inv_scale : 0.0f);
+                    __builtin_nontemporal_store(v, &ystep[(t * 3 + o) * bb + tid]);
+                    if (o == 0) y0 = double(v);
+                    else if (o == 1) y1 = double(v);
+                    else y2 = double(v);
+                }
+                const int jl = mid_offset(t, il, kl, b);
+                const int j = J * b + jl;
+                if (i < j && j < k && k < nn) {
+                    Ab[il * b + jl] += (y0 - y1) - y2;  // pair (i,j)
+                    Cs[tid] += (y1 - y0) - y2;          // pair (i,k)
+                    Bb[jl * b + kl] += (y2 - y0) - y1;  // pair (j,k)
+                }
+                lds_barrier();
+            }
+
+            const bool last = (m == Qb - Pb);
+            if (idA >= 0) publish(Pb, J, Abuf);
+            if (idB >= 0) publish(J, Qb, Bbuf);
+            if (last) publish(Pb, Qb, Cs);
+            __builtin_amdgcn_s_waitcnt(0);
+            __syncthreads();
+            if (tid == 0) {
+                if (idA >= 0) __hip_atomic_fetch_add(&a.cnt[int64_t(idA) * kCntStride], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                if (idB >= 0) __hip_atomic_fetch_add(&a.cnt[int64_t(idB) * kCntStride], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                bool ok = true;
+                if (last) {
+                    __hip_atomic_fetch_add(&a.cnt[int64_t(idC) * kCntStride], uint32_t(Qb - Pb + 1), __ATOMIC_RELAXED,
+                                           __HIP_MEMORY_SCOPE_AGENT);
+                    s_tix = int(atomicAdd(&a.ctl[0], 1u));
+                } else {
+                    ok = wait_step(m + 1, false);
+                    if (ok) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+                }
+                s_ok = ok;
+            }
+            __syncthreads();
+            if (!__builtin_amdgcn_readfirstlane(s_ok)) {
+                aborted = true;
+                break;
+            }
+        }
+        if (aborted) break;
     }
 }
 
@@ -734,6 +995,40 @@ template int launch_mlp_train_graph<double>(const GraphView &, const double *, i
 template int launch_mlp_train_graph<float>(const GraphView &, const float *, int64_t, uint64_t,
                                            int64_t, float *, float *, float *, int, float, void *,
                                            float *, hipStream_t);
+template <typename T>
+int launch_infer_aty_dataflow(const DataflowArgs &a, int grid, const GraphView &G, const float *P, T *y,
+                              double *ax, hipStream_t s) {
+    switch (G.b) {
+        case 8: hipLaunchKernelGGL((k_infer_aty_dataflow<T, 8>), dim3(grid), dim3(64), 0, s, a, G, P, y, ax); break;
+        case 16: hipLaunchKernelGGL((k_infer_aty_dataflow<T, 16>), dim3(grid), dim3(256), 0, s, a, G, P, y, ax); break;
+        case 24: hipLaunchKernelGGL((k_infer_aty_dataflow<T, 24>), dim3(grid), dim3(576), 0, s, a, G, P, y, ax); break;
+        case 32: hipLaunchKernelGGL((k_infer_aty_dataflow<T, 32>), dim3(grid), dim3(1024), 0, s, a, G, P, y, ax); break;
+        default: return fail(CC_EINVAL, "the fused inference runs for b = 8, 16, 24, 32");
+    }
+    CCP_LAUNCH_CHECK("k_infer_aty_dataflow");
+    return CC_OK;
+}
+
+template <typename T>
+int infer_aty_occupancy(int b, int *blocks_per_cu) {
+    hipError_t e = hipSuccess;
+    switch (b) {
+        case 8: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, k_infer_aty_dataflow<T, 8>, 64, 0); break;
+        case 16: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, k_infer_aty_dataflow<T, 16>, 256, 0); break;
+        case 24: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, k_infer_aty_dataflow<T, 24>, 576, 0); break;
+        case 32: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, k_infer_aty_dataflow<T, 32>, 1024, 0); break;
+        default: *blocks_per_cu = 0; return CC_OK;
+    }
+    if (e != hipSuccess) return fail(CC_EHIP, std::string("fused inference occupancy: ") + hipGetErrorString(e));
+    return CC_OK;
+}
+
+template int launch_infer_aty_dataflow<double>(const DataflowArgs &, int, const GraphView &, const float *, double *,
+                                               double *, hipStream_t);
+template int launch_infer_aty_dataflow<float>(const DataflowArgs &, int, const GraphView &, const float *, float *,
+                                              double *, hipStream_t);
+template int infer_aty_occupancy<double>(int, int *);
+template int infer_aty_occupancy<float>(int, int *);
 template int launch_mlp_infer<double>(const GraphView &, const float *, double *, hipStream_t);
 template int launch_mlp_infer<float>(const GraphView &, const float *, float *, hipStream_t);
 

@@ -261,3 +261,40 @@ def test_gate_bound_and_share():
     assert conv and r["primal_qp"] <= info["dual_bound"]
     assert info["dual_cold"] <= info["dual_warm"] <= r["primal_qp"]
     assert info["accepted"] and info["gap_share"] >= 0.05
+
+
+@pytest.mark.parametrize("b,prec", [(8, "f32"), (16, "f32"), (32, "f32"), (16, "f64"), (24, "f32")])
+def test_fused_warm_start_equals_the_separate_passes(b, prec):
+    """For b = 8, 16, 24, 32 the warm start runs the network fused with A'y
+    on the dataflow executor.  Its duals equal cc_mlp_infer's bit for bit
+    (b = 8, 16, 32; b = 24 against the reference network), and its x, f and
+    pair duals equal those of cc_x_from_y on the same duals followed by one
+    pair pass, bit for bit: the fused sums are A'y's."""
+    inst = I.training_graph(2001)
+    net, deg = W.load(), W.degrees(inst)
+    s = C.Solver.from_instance(inst, b=b, prec=prec)
+    info = W.warm_start(s, net, deg)
+    assert info["accepted"]
+    r = C.Solver.from_instance(inst, b=b, prec=prec)
+    if b != 24:
+        W.infer(r, net, deg, r.y)
+        assert torch.equal(r.y, s.y)
+    else:
+        slots = torch.arange(s.ctx.slots, device="cuda", dtype=torch.int64)
+        lex = torch.empty_like(slots)
+        s.ctx.slots_to_lex(slots, lex)
+        yv, lex = s.y.cpu().numpy().astype(np.float64), lex.cpu().numpy()
+        valid = lex >= 0
+        assert not yv[~valid].any()
+        i, j, k = colex_triplets(lex[valid] // 3)
+        yr, _ = M.forward(net.host_params(), M.features(inst.d, inst.w, inst.deg, i, j, k, lex[valid] % 3))
+        e = np.abs(yv[valid] - yr / (inst.n - 2)) / np.abs(yr / (inst.n - 2)).max()
+        assert np.quantile(e, 0.999) <= 1e-3 and e.max() <= 2e-2
+    r.y.copy_(s.y)
+    r.y_pair.zero_()
+    x, f = r.x_from_y()
+    r.x.copy_(x)
+    r.f.copy_(f)
+    r.pair_pass()
+    for a in ("x", "f", "y_pair"):
+        assert torch.equal(getattr(r, a), getattr(s, a)), a
