@@ -641,6 +641,8 @@ def polish_report(config=2, b=16):
         g.sweep(5, C.CC_EXEC_DATAFLOW)
         g.status()
         res[f"ms_per_sweep_{prec}"] = (time.perf_counter() - t0) / 5 * 1e3
+        nbytes = metric_sweep_bytes(inst, 8 if prec == "f64" else 4)
+        res[f"hbm_frac_{prec}"] = nbytes / (res[f"ms_per_sweep_{prec}"] / 1e3) / 1e9 / HBM_PEAK_GBS
         del g
         torch.cuda.empty_cache()
     C.solve_cc_lp(inst.n, inst.w, inst.d, inst.gamma, tol=1e-6, b=b, mode=C.CC_MODE_F32_POLISH,
@@ -847,6 +849,37 @@ def n500_sweep(steps=20, warmup=3):
     return out
 
 
+def n60_solve(b=8, tol=1e-6):
+    """The n = 60 Erdos-Renyi workload (p = 0.1, seed 0, gamma = 1), FP64,
+    solved to max violation 1e-6 on the GPU and by the oracle (one host
+    core, the same schedule): sweeps, times, rate, and the largest
+    difference of the converged x, f and duals."""
+    import numpy as np
+    import torch
+    import oracle
+    from paper_1901_10084_amd import ccproj as C
+    from paper_1901_10084_amd import instances as I
+    inst = I.workload(0)
+    g = C.Solver.from_instance(inst, b=b, prec="f64")
+    g.solve(tol=tol, max_sweeps=1)  # untimed: first launches
+    g.init_cold()
+    gpu = solve_leg(g, tol)
+    o = oracle.State.from_instance(inst)
+    t0 = time.perf_counter()
+    o.solve(tol=tol, b=b, max_sweeps=20000)
+    t_o = time.perf_counter() - t0
+    err = max(float(np.abs(g.x.cpu().numpy() - o.x).max()), float(np.abs(g.f.cpu().numpy() - o.f).max()),
+              float(np.abs(g.duals_lex().cpu().numpy() - o.y).max()))
+    out = {"workload": inst.name, "n": inst.n, "b": b, "tol": tol, "gpu": gpu,
+           "gpu_triplet_projections_per_s": inst.num_constraints * gpu["sweeps"] / gpu["seconds"],
+           "oracle": {"seconds": t_o, "sweeps": o.sweeps, "cores": 1},
+           "max_abs_diff_vs_oracle": err}
+    log(f"n = 60: {out}")
+    del g
+    torch.cuda.empty_cache()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -1046,6 +1079,7 @@ def main():
         out["n2000_warm_start"] = warm_report(3, 16)
         out["n1500_polish"] = polish_report()
         out["n500_sweep"] = n500_sweep()
+        out["n60_solve"] = n60_solve()
         out["sparse"] = sparse_report(cases=((3, 16, "f32"),))
         out["stream_ceilings"] = stream_ceilings()
         log(f"stream ceilings: {out['stream_ceilings']}")
