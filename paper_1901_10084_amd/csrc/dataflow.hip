@@ -428,9 +428,14 @@ k_sweep_dataflow(DataflowArgs a, int64_t n, T *__restrict__ x, const T *__restri
                         y1 = yq[d][1];
                         y2 = yq[d][2];
                     }
+                    // The x reads go out first: they head the sub-step's
+                    // dependent chain, and the reciprocal of q (x-independent)
+                    // then runs in their latency instead of ahead of them.
+                    const int jl = mid_offset(t, il, kl, b);
+                    T xa = Ax[il * b + jl], xb = Bx[jl * b + kl], xc = Cx[tid];
+                    __builtin_amdgcn_sched_barrier(0);
                     const T q = qn, ga = gan, gb = gbn;
                     if (t + 1 < b) qn = gq(t + 1, gan, gbn);
-                    const int jl = mid_offset(t, il, kl, b);
                     const int j = J * b + jl;
                     {
                         // Every lane runs the step; a lane whose (i,j,k) is
@@ -442,10 +447,9 @@ k_sweep_dataflow(DataflowArgs a, int64_t n, T *__restrict__ x, const T *__restri
                         // middle block is P or Q, the A or B block is the
                         // resident (P,Q) block, and a padding lane's entry can
                         // be a triplet lane's entry of the same sub-step.
-                        const bool ok = i < j && j < k && k < nn;
+                        const bool ok = (i < j) & (j < k) & (k < nn);
                         const T qm = ok ? q : T(0);
                         const T floor_ = ok ? T(0) : T(-__builtin_huge_val());
-                        T xa = Ax[il * b + jl], xb = Bx[jl * b + kl], xc = Cx[tid];
                         project_lo(xa, xc, xb, ga, gC, gb, qm, floor_, y0);
                         project_lo(xc, xa, xb, gC, ga, gb, qm, floor_, y1);
                         project_lo(xb, xa, xc, gb, ga, gC, qm, floor_, y2);
