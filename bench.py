@@ -73,6 +73,53 @@ def recorded_traffic(kernel, inst, b, prec):
     return rec["traffic_bytes_per_launch"]
 
 
+TRAFFIC_SOURCES = ["paper_1901_10084_amd/csrc/dataflow.hip", "paper_1901_10084_amd/csrc/dataflow.hpp",
+                   "paper_1901_10084_amd/csrc/project.hpp", "paper_1901_10084_amd/csrc/common.hpp"]
+
+
+def write_traffic_record(fetch_dir, write_dir, inst, b, prec, skip):
+    """profiles/k_sweep_dataflow_<workload>_<prec>.traffic.json from two
+    rocprofv3 --pmc runs of this script (FETCH_SIZE, then WRITE_SIZE, each
+    with --copy-calibration 1024): the dense sweep kernel's mean KiB per
+    dispatch after the first `skip`, each scaled by what the counter reads
+    for the 1 GiB calibration add (1 GiB read, 1 GiB written), with a hash
+    of the kernel's sources.  Reads only the two CSV files; no GPU."""
+    import csv
+    import hashlib
+    tname = "double" if prec == "f64" else "float"
+
+    def read(d):
+        rows = list(csv.DictReader(open(os.path.join(d, "pmc_counter_collection.csv"))))
+        ks = sorted((int(r["Dispatch_Id"]), float(r["Counter_Value"]), r["Kernel_Name"]) for r in rows
+                    if f"k_sweep_dataflow<{tname}, {b}," in r["Kernel_Name"]
+                    and ", false, false>" in r["Kernel_Name"])
+        cal = [float(r["Counter_Value"]) for r in rows if "CUDAFunctorOnSelf_add<double" in r["Kernel_Name"]]
+        if len(ks) <= skip or not cal:
+            raise SystemExit(f"{d}: {len(ks)} sweep dispatches, {len(cal)} calibration dispatches")
+        return ks[skip:], sum(cal) / len(cal)
+
+    fk, fcal = read(fetch_dir)
+    wk, wcal = read(write_dir)
+    gib_kib = 1024.0 * 1024.0
+    f = sum(v for _, v, _ in fk) / len(fk)
+    w = sum(v for _, v, _ in wk) / len(wk)
+    h = hashlib.sha256()
+    for src in TRAFFIC_SOURCES:
+        h.update(open(os.path.join(ROOT, src), "rb").read())
+    rec = {"kernel": fk[0][2].split("(")[0].replace("void ccp::", ""), "workload": inst.name, "b": b,
+           "prec": prec, "sources": TRAFFIC_SOURCES, "source_sha256": h.hexdigest(),
+           "fetch_kib_per_launch": round(f, 1), "fetch_scale": round(gib_kib / fcal, 4),
+           "write_kib_per_launch": round(w, 1), "write_scale": round(gib_kib / wcal, 4),
+           "dispatches": len(fk),
+           "traffic_bytes_per_launch": int(round(f * (gib_kib / fcal) * 1024 + w * (gib_kib / wcal) * 1024))}
+    wl = {"sbm_n500_k10": "sbm_n500", "chunglu_n4000_b2.2": "chunglu_n4000"}.get(inst.name, inst.name)
+    path = os.path.join(ROOT, "profiles", f"k_sweep_dataflow_{wl}_{prec}.traffic.json")
+    with open(path, "w") as fh:
+        json.dump(rec, fh, indent=1)
+        fh.write("\n")
+    print(json.dumps(rec, indent=1))
+
+
 def warm_report(config, b, tol=1e-4, sparse=False):
     """Time to max violation <= tol: FP64 plain cold solve vs FP32 cold vs
     FP32 + learned warm start.  Workload 3: the n = 2000 planted partition
@@ -923,7 +970,17 @@ def main():
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MiB",
                     help="after the timed region, add 1 to a buffer of this size (reference "
                          "kernel for the HBM byte counters)")
+    ap.add_argument("--traffic-record", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
+                    help="write the PMC traffic record of the dense sweep for --config/--b/--prec "
+                         "from two rocprofv3 --pmc output folders (no GPU run)")
+    ap.add_argument("--traffic-skip", type=int, default=1,
+                    help="sweep dispatches to skip (warm-up) in --traffic-record")
     args = ap.parse_args()
+    if args.traffic_record:
+        from paper_1901_10084_amd import instances as I
+        write_traffic_record(*args.traffic_record, I.workload(args.config), args.b, args.prec,
+                             args.traffic_skip)
+        return
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
