@@ -77,7 +77,7 @@ TRAFFIC_SOURCES = ["paper_1901_10084_amd/csrc/dataflow.hip", "paper_1901_10084_a
                    "paper_1901_10084_amd/csrc/project.hpp", "paper_1901_10084_amd/csrc/common.hpp"]
 
 
-def write_traffic_record(fetch_dir, write_dir, inst, b, prec, skip):
+def write_traffic_record(fetch_dir, write_dir, inst, b, prec, skip, out_dir=None):
     """profiles/k_sweep_dataflow_<workload>_<prec>.traffic.json from two
     rocprofv3 --pmc runs of this script (FETCH_SIZE, then WRITE_SIZE, each
     with --copy-calibration 1024): the dense sweep kernel's mean KiB per
@@ -113,11 +113,12 @@ def write_traffic_record(fetch_dir, write_dir, inst, b, prec, skip):
            "dispatches": len(fk),
            "traffic_bytes_per_launch": int(round(f * (gib_kib / fcal) * 1024 + w * (gib_kib / wcal) * 1024))}
     wl = {"sbm_n500_k10": "sbm_n500", "chunglu_n4000_b2.2": "chunglu_n4000"}.get(inst.name, inst.name)
-    path = os.path.join(ROOT, "profiles", f"k_sweep_dataflow_{wl}_{prec}.traffic.json")
+    path = os.path.join(out_dir or os.path.join(ROOT, "profiles"), f"k_sweep_dataflow_{wl}_{prec}.traffic.json")
     with open(path, "w") as fh:
         json.dump(rec, fh, indent=1)
         fh.write("\n")
     print(json.dumps(rec, indent=1))
+    return path
 
 
 def warm_report(config, b, tol=1e-4, sparse=False):
