@@ -317,12 +317,22 @@ int dataflow_args(cc_ctx *c, unsigned long long *prof, DataflowArgs &a) {
     return CC_OK;
 }
 
+// The FP64 dense dataflow sweep (like the sparse one) addresses a tile's
+// duals, at most ceil(n/b) steps of 3 b^3, with 31-bit byte offsets.
+int check_tile_offsets(const cc_ctx *c) {
+    if (c->prec == CC_F64 && int64_t(c->nb) * 3 * c->b * c->b * c->b * int64_t(elem_size(c)) >= (int64_t(1) << 31))
+        return fail(CC_EINVAL, "the FP64 dataflow sweep addresses a tile's duals with 31-bit offsets: n too large for b");
+    return CC_OK;
+}
+
 template <typename T>
 int sweep_metric_t(cc_ctx *c, T *x, T *y, const T *g, int exec, unsigned long long *prof,
                    void *mask) {
     if (exec == CC_EXEC_ROUNDS) return sweep_rounds_t<T>(c, x, y, g, 0, c->nrounds);
+    int rc = check_tile_offsets(c);
+    if (rc) return rc;
     DataflowArgs a;
-    int rc = dataflow_args(c, prof, a);
+    rc = dataflow_args(c, prof, a);
     if (rc) return rc;
     if ((rc = launch_sweep_dataflow<T>(a, df_grid(c, mask == nullptr), c->b, c->n, x, g, y, mask, nullptr,
                                        c->stream)))
@@ -337,8 +347,10 @@ int sweep_metric_t(cc_ctx *c, T *x, T *y, const T *g, int exec, unsigned long lo
 // The counters then hold a partial epoch and are cleared.
 template <typename T>
 int sweep_prefix_t(cc_ctx *c, T *x, T *y, const T *g, int rounds) {
+    int rc = check_tile_offsets(c);
+    if (rc) return rc;
     DataflowArgs a;
-    int rc = dataflow_args(c, nullptr, a);
+    rc = dataflow_args(c, nullptr, a);
     if (rc) return rc;
     a.ntiles = int(c->round_start[rounds]);
     if (a.ntiles > 0 &&
@@ -674,7 +686,8 @@ template <typename T>
 int sweep_noalloc_t(cc_ctx *c, uint32_t *ws, T *x, T *f, T *y, T *yp, const T *g, const uint8_t *d,
                     int nsweeps) {
     uint32_t *const ctl = ws, *const cnt = ws + kNoallocCtlWords;
-    int rc;
+    int rc = check_tile_offsets(c);
+    if (rc) return rc;
     // every call starts from zeroed counters and flags (a fill kernel)
     if ((rc = launch_fill_u32(kNoallocCtlWords + c->nblocks * kCntStride, ws, c->stream))) return rc;
     for (int s = 0; s < nsweeps; ++s) {
