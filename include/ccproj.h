@@ -143,7 +143,10 @@ int cc_init_cold(cc_ctx *ctx, void *x, void *f, void *y, void *y_pair, double ga
  * (no host synchronisation).  A dataflow wait longer than 10 s aborts the
  * sweep (the state is then incomplete); no wait can block forever.  Such an
  * abort is reported as CC_EHIP by the next cc_status or cc_residuals call
- * on the context. */
+ * on the context.  The FP64 dataflow sweep (and every sparse sweep)
+ * addresses one tile's duals, ceil(n/b) steps of 3 b^3, with 31-bit byte
+ * offsets: CC_EINVAL where they do not fit (n above about 87,000 at b = 32
+ * in FP64, far beyond what the dual array allows). */
 int cc_sweep(cc_ctx *ctx, void *x, void *f, void *y, void *y_pair, const void *g,
              const uint8_t *d, int32_t nsweeps, int32_t exec);
 
