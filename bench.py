@@ -565,7 +565,7 @@ def l1_report(n=2000, b=16, solve_n=500, gamma=1.0, solve_tol=1e-3, oracle_sweep
     o.sweep(oracle_sweeps, b=b)
     dt = time.perf_counter() - t0
     srows = 3 * solve_n * (solve_n - 1) * (solve_n - 2) // 6
-    res["cpu_baseline"] = {"value": oracle_sweeps * srows / dt, "unit": "constraint-projections/s",
+    res["cpu_baseline"] = {"value": oracle_sweeps * srows / dt, "unit": "triplet-projections/s",
                            "cores": 1, "kind": "oracle",
                            "sample": f"{oracle_sweeps} FP64 l1 sweeps at n = {solve_n} from the cold start, "
                                      f"{dt:.2f} s"}
@@ -657,7 +657,7 @@ def nearness_report(n=2000, b=16, solve_n=500, solve_tol=1e-4, oracle_sweeps=3):
     t0 = time.perf_counter()
     o.sweep(oracle_sweeps, b=b)
     dt = time.perf_counter() - t0
-    res["cpu_baseline"] = {"value": oracle_sweeps * srows / dt, "unit": "constraint-projections/s",
+    res["cpu_baseline"] = {"value": oracle_sweeps * srows / dt, "unit": "triplet-projections/s",
                            "cores": 1, "kind": "oracle",
                            "sample": f"{oracle_sweeps} FP64 nearness sweeps at n = {solve_n} "
                                      f"from x = d, {dt:.2f} s"}
@@ -758,7 +758,7 @@ def cpu_baseline(inst, b, budget_s):
     t0 = time.perf_counter()
     s.sweep(k, b=b)
     dt = time.perf_counter() - t0
-    return {"value": inst.num_constraints * k / dt, "unit": "constraint-projections/s",
+    return {"value": inst.num_constraints * k / dt, "unit": "triplet-projections/s",
             "cores": 1, "kind": "oracle",
             "sample": f"{k} FP64 sweeps of the same instance (after 1 untimed), serial C oracle, "
                       f"{dt:.1f} s, host {cpu_model()}, nproc {os.cpu_count()}"}
