@@ -897,6 +897,25 @@ def n500_sweep(steps=20, warmup=3):
     return out
 
 
+def n2000_f64_sweep(steps=10, warmup=3):
+    """The n = 2000 planted-partition workload in FP64 (b = 16): per-sweep
+    time and HBM fraction of the plain dense sweep at a size where HBM is
+    the bound (64 GB of duals)."""
+    import torch
+    from paper_1901_10084_amd import ccproj as C
+    from paper_1901_10084_amd import instances as I
+    inst = I.workload(3)
+    g = C.Solver.from_instance(inst, b=16, prec="f64")
+    wall, metric_ms = timed_sweeps(g, steps, warmup, C.CC_EXEC_DATAFLOW)
+    out = {"workload": inst.name, "n": inst.n, "b": 16, "prec": "f64",
+           "ms_per_step": wall * 1e3 / steps,
+           "triplet_projections_per_s": inst.num_constraints * steps / wall,
+           "roofline": roofline(inst, 8, metric_ms / steps, 16, "f64")}
+    del g
+    torch.cuda.empty_cache()
+    return out
+
+
 def n60_solve(b=8, tol=1e-6):
     """The n = 60 Erdos-Renyi workload (p = 0.1, seed 0, gamma = 1), FP64,
     solved to max violation 1e-6 on the GPU and by the oracle (one host
@@ -1137,6 +1156,7 @@ def main():
         out["n2000_warm_start"] = warm_report(3, 16)
         out["n1500_polish"] = polish_report()
         out["n500_sweep"] = n500_sweep()
+        out["n2000_f64_sweep"] = n2000_f64_sweep()
         out["n60_solve"] = n60_solve()
         out["sparse"] = sparse_report(cases=((3, 16, "f32"),))
         out["stream_ceilings"] = stream_ceilings()
