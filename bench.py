@@ -158,7 +158,9 @@ def warm_report(config, b, tol=1e-4, sparse=False):
                "max_viol": max(r["max_viol_metric"], r["max_viol_pair"])}
         if info:
             out.update(accepted=info["accepted"], dual_warm=info["dual_warm"],
-                       dual_cold=info["dual_cold"], warm_start_seconds=t_warm)
+                       dual_cold=info["dual_cold"], warm_start_seconds=t_warm,
+                       sample_rejected=info["sample_rejected"], sample_drawn=info["sample_drawn"],
+                       sample_gain=info["sample_gain"], sample_std_error=info["sample_std_error"])
         del s
         torch.cuda.empty_cache()
         return out

@@ -80,7 +80,8 @@ typedef struct {
     int32_t sweeps;          /* sweeps run (all phases)                       */
     int32_t sweeps_f32;      /* of which in FP32                              */
     int32_t warm_accepted;   /* 1 if the learned warm start was kept          */
-    int32_t reserved;
+    int32_t warm_sampled;    /* 1 if the sampled gate rejected it (no full
+                                inference ran; see cc_set_gate_sample)       */
     double wall_s;           /* wall time of the whole call                   */
     cc_resid resid;          /* final residuals                               */
 } cc_info;
@@ -466,11 +467,53 @@ int cc_mlp_infer(cc_ctx *ctx, const float *params, const float *deg, const doubl
  * 5% of the gap a cold start faces; otherwise the state is reset to the
  * cold start.  *accepted (nullable) tells which; *dual_warm, *dual_cold and
  * *dual_bound (nullable) return D_warm, D_cold and U.  g from cc_prepare.
- * Synchronises. */
+ * For large n a sampled gate runs first (cc_set_gate_sample): when it
+ * rejects the start, no full inference runs and *dual_warm is D_cold plus
+ * the sample's estimate of D_warm - D_cold.  Synchronises. */
 int cc_warm_start_mlp(cc_ctx *ctx, const float *params, const float *deg, const double *w,
                       const uint8_t *d, double gamma, void *x, void *f, void *y, void *y_pair,
                       const void *g, int32_t *accepted, double *dual_warm, double *dual_cold,
                       double *dual_bound);
+
+/* Terms of the warm-start gate for `count` pairs given by packed index
+ * (pairs: device int64[count], 0 <= p < N_p, repeats allowed; an index out
+ * of range gives NaN).  aty_out[s] (device double[count]) is the pair's
+ * metric part of A'y at the network's predicted duals: the sum, over every
+ * third vertex, of the three rows' predictions, +1 for the row whose long
+ * side is the pair and -1 for the other two (the predictions cc_mlp_infer
+ * writes, summed in FP64).  delta_out[s] (device double[count], nullable)
+ * is the pair's term of D_warm - D_cold.  Once the pair rows have had
+ * their pass, the dual objective of (qp) is a sum of one term per pair
+ * (the metric rows have b = 0 and W is diagonal), so N_p times the mean of
+ * delta_out over a uniform sample estimates the gate's gain without the
+ * full inference.  Synchronises. */
+int cc_warm_gate_terms(cc_ctx *ctx, const float *params, const float *deg, const double *w,
+                       const uint8_t *d, double gamma, const void *g, const int64_t *pairs,
+                       int64_t count, double *aty_out, double *delta_out);
+
+/* The sampled gate of cc_warm_start_mlp (and of cc_solve_cc_lp's warm
+ * start).  Before the full inference, D_warm - D_cold is estimated from
+ * part of the pairs (cc_warm_gate_terms), with its standard error: the
+ * terms of every positive pair (d = 0; few, and where the largest terms
+ * sit) are summed exactly, and those of the negative pairs are estimated
+ * from `count` of them drawn uniformly with replacement (splitmix64, a
+ * fixed seed).  The start is rejected without the full inference when the
+ * estimate plus four standard errors stays below the gate's least gain, 5%
+ * of U - D_cold, and the estimate below half of it; every other start goes
+ * to the exact gate.  The estimate runs only when its pairs' rows are at
+ * most 1/8 of all metric rows: 24 (positive pairs + count) <= N_p.  A gain
+ * concentrated on few negative pairs can escape the sample; the cost of
+ * such a rejection is sweeps, not the result.  count: 0 turns the estimate
+ * off; default 16384. */
+int cc_set_gate_sample(cc_ctx *ctx, int64_t count);
+
+/* What the last cc_warm_start_mlp on this context drew (nullable outputs):
+ * pairs whose terms were computed (positive pairs plus draws; 0 if the
+ * estimate did not run), the estimate of
+ * D_warm - D_cold, its standard error, and 1 if the sample rejected the
+ * start. */
+int cc_last_gate_sample(const cc_ctx *ctx, int64_t *drawn, double *gain, double *std_error,
+                        int32_t *rejected);
 
 /* One-shot solve from host arrays (allocates its own device buffers).
  * w_host: double[N_p] > 0; d_host: uint8[N_p]; tol: stop when both max

@@ -262,11 +262,62 @@ def colour_order(n: int) -> np.ndarray:
 
 def pair_pass(n, gamma, w, d, x, f, y_pair):
     """One pass over the pair constraints, in place."""
-    rc = lib().orc_pair_pass(int(n), float(gamma), _ptr(_f64(w)),
-                             _ptr(np.ascontiguousarray(d, dtype=np.uint8)),
+    w, d = _f64(w), np.ascontiguousarray(d, dtype=np.uint8)   # alive through the call
+    rc = lib().orc_pair_pass(int(n), float(gamma), _ptr(w), _ptr(d),
                              _ptr(x), _ptr(f), _ptr(y_pair))
     if rc != 0:
         raise MemoryError
+
+
+def colex_triplets(n):
+    """(i, j, k) of every triplet i < j < k in colex order (arrays)."""
+    n = int(n)
+    parts = [(np.arange(j), np.full(j, j), np.full(j, k)) for k in range(2, n) for j in range(1, k)]
+    if not parts:
+        z = np.zeros(0, dtype=np.int64)
+        return z, z, z
+    return tuple(np.concatenate([q[e] for q in parts]).astype(np.int64) for e in range(3))
+
+
+def gate_pair_terms(n, gamma, w, d, y):
+    """Per-pair terms of the warm-start gate for the metric duals y (colex
+    order, three rows per triplet: long side ij, ik, jk).
+
+    A start takes x = x(y) with zero pair duals (Algorithm 1's primal point
+    of a dual vector, Sec. II-B), then one pass over the pair rows.  With
+    b = 0 on every metric row and W diagonal, the dual of (qp) is then a sum
+    of one term per pair p:
+        -d_p (y1 - y2) - (gamma / 2) ((A'y)_p + y1 - y2)^2 + (w_p - y1 - y2)^2) / w_p,
+    (A'y)_p being the metric rows' part: +1 for a row whose long side is p,
+    -1 for a row where p is one of the two short sides.  Returns per-pair
+    arrays: aty (that part, from its definition), term_warm (the start from
+    y), term_cold (the start from y = 0), and the pair duals of both starts
+    after their pass."""
+    n = int(n)
+    w = _f64(w)
+    d = np.ascontiguousarray(d, dtype=np.uint8)
+    npairs = num_pairs(n)
+    yv = np.asarray(y, dtype=np.float64).reshape(-1, 3)
+    assert yv.shape[0] == num_triplets(n)
+    i, j, k = colex_triplets(n)
+    pij, pik, pjk = j * (j - 1) // 2 + i, k * (k - 1) // 2 + i, k * (k - 1) // 2 + j
+    aty = np.zeros(npairs)
+    np.add.at(aty, pij, yv[:, 0] - yv[:, 1] - yv[:, 2])
+    np.add.at(aty, pik, yv[:, 1] - yv[:, 0] - yv[:, 2])
+    np.add.at(aty, pjk, yv[:, 2] - yv[:, 0] - yv[:, 1])
+    dv = d.astype(np.float64)
+    out = {"aty": aty}
+    for name, ax in (("warm", aty), ("cold", np.zeros(npairs))):
+        s = State(n, gamma, w, d, dense_duals=False)   # the cold start
+        if name == "warm":
+            s.y = np.ascontiguousarray(yv.ravel())
+            s.x, s.f = s.x_from_y()
+        pair_pass(n, gamma, w, d, s.x, s.f, s.y_pair)
+        y1, y2 = s.y_pair[0::2], s.y_pair[1::2]
+        out["term_" + name] = -(dv * y1 - dv * y2) - 0.5 * float(gamma) * (
+            (ax + y1 - y2) ** 2 + (w - y1 - y2) ** 2) / w
+        out["y_pair_" + name] = s.y_pair.copy()
+    return out
 
 
 def second_sweep_prefix(n, b, gamma, w, d, rounds, cap=None):

@@ -53,7 +53,7 @@ class NResid(ctypes.Structure):
 
 class Info(ctypes.Structure):
     _fields_ = [("sweeps", _i32), ("sweeps_f32", _i32), ("warm_accepted", _i32),
-                ("reserved", _i32), ("wall_s", _dbl), ("resid", Resid)]
+                ("warm_sampled", _i32), ("wall_s", _dbl), ("resid", Resid)]
 
 
 def _sig(name, res, *args):
@@ -119,6 +119,10 @@ _sig("cc_mlp_slot_features", ctypes.c_int, _p, _p, _p, _p, _p, _i64, _p)
 _sig("cc_mlp_infer", ctypes.c_int, _p, _p, _p, _p, _p, _p)
 _sig("cc_warm_start_mlp", ctypes.c_int, _p, _p, _p, _p, _p, _dbl, _p, _p, _p, _p, _p,
      ctypes.POINTER(_i32), ctypes.POINTER(_dbl), ctypes.POINTER(_dbl), ctypes.POINTER(_dbl))
+_sig("cc_warm_gate_terms", ctypes.c_int, _p, _p, _p, _p, _p, _dbl, _p, _p, _i64, _p, _p)
+_sig("cc_set_gate_sample", ctypes.c_int, _p, _i64)
+_sig("cc_last_gate_sample", ctypes.c_int, _p, ctypes.POINTER(_i64), ctypes.POINTER(_dbl),
+     ctypes.POINTER(_dbl), ctypes.POINTER(_i32))
 
 EXPORTS = ["cc_last_error", "cc_num_metric_duals", "cc_create", "cc_destroy", "cc_dual_slots",
            "cc_num_rounds", "cc_prepare", "cc_init_cold", "cc_sweep", "cc_sweep_rounds",
@@ -257,6 +261,18 @@ class Context:
         check(_L.cc_set_dataflow_workgroups(self._h, int(workgroups), ctypes.byref(eff)))
         return int(eff.value)
 
+    def set_gate_sample(self, count):
+        """Pairs the sampled warm-start gate draws (0: off)."""
+        check(_L.cc_set_gate_sample(self._h, int(count)))
+
+    def last_gate_sample(self):
+        drawn, rej = _i64(0), _i32(0)
+        gain, se = _dbl(0.0), _dbl(0.0)
+        check(_L.cc_last_gate_sample(self._h, ctypes.byref(drawn), ctypes.byref(gain),
+                                     ctypes.byref(se), ctypes.byref(rej)))
+        return {"drawn": int(drawn.value), "gain": gain.value, "std_error": se.value,
+                "rejected": bool(rej.value)}
+
     def dataflow_breakdown(self, x, y, g):
         out = (_dbl * 8)()
         check(_L.cc_dataflow_breakdown(self._h, _ptr(x), _ptr(y), _ptr(g), out))
@@ -323,7 +339,8 @@ def solve_cc_lp(n, w, d, gamma, tol=1e-6, max_sweeps=100000, b=16, mode=CC_MODE_
                            None if ylex is None else ylex.ctypes.data, ctypes.byref(info))
     check(rc, allow_notconv=True)
     out = dict(sweeps=info.sweeps, sweeps_f32=info.sweeps_f32, wall_s=info.wall_s,
-               warm_accepted=info.warm_accepted, resid=info.resid.as_dict())
+               warm_accepted=info.warm_accepted, warm_sampled=info.warm_sampled,
+               resid=info.resid.as_dict())
     return rc, x, ylex, out
 
 

@@ -878,6 +878,66 @@ __global__ void k_mlp_slot_features(GraphView G, const int64_t *__restrict__ slo
     }
 }
 
+// The sampled warm-start gate.  Workgroup s takes the pair pairs[s] = (a, c),
+// a < c, given by its packed index.  It sums, over every third vertex v, the
+// predictions of the three rows of the triplet {a, c, v}: +1 for the row
+// whose long side is (a, c), -1 for the other two.  That sum is the pair's
+// metric part of A'y at the predicted duals.  Each prediction is the value
+// the full inference writes for that row: the features of row_features, the
+// same network code, the same scaling and rounding to T.  Only the FP64
+// summation order differs from the full A'y.  An index outside [0, N_p)
+// gives NaN.
+template <typename T>
+__global__ void __launch_bounds__(256)
+k_gate_sample_aty(GraphView G, const float *__restrict__ P, const int64_t *__restrict__ pairs,
+                  double *__restrict__ aty) {
+    InferNet N;
+    load_infer_net(N, P);
+    __shared__ double red[256];
+    const int64_t p = pairs[blockIdx.x];
+    if (p < 0 || p >= G.n * (G.n - 1) / 2) {  // no pair: NaN (the whole workgroup leaves)
+        if (threadIdx.x == 0) aty[blockIdx.x] = __builtin_nan("");
+        return;
+    }
+    int64_t c = int64_t(0.5 * (1.0 + sqrt(1.0 + 8.0 * double(p))));
+    while (c * (c - 1) / 2 > p) --c;
+    while ((c + 1) * c / 2 <= p) ++c;
+    const int64_t a = p - c * (c - 1) / 2;
+    const int64_t n = G.n;
+    const float inv_scale = 1.0f / float(n - 2);
+    double acc = 0.0;
+    // the same trip count in every lane: the network's MFMAs need the whole wave
+    for (int64_t v0 = 0; v0 < n; v0 += blockDim.x) {
+        const int64_t v = v0 + threadIdx.x;
+        const bool ok = v < n && v != a && v != c;
+        // the triplet in order, and the side (a, c) takes in it: ij, ik or jk
+        const int64_t i = v < a ? v : a;
+        const int64_t j = v < a ? a : (v < c ? v : c);
+        const int64_t k = v < c ? c : v;
+        const int side = v < a ? 2 : (v < c ? 1 : 0);
+        double s = 0.0;
+#pragma unroll
+        for (int o = 0; o < 3; ++o) {
+            float phi[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+            if (ok) row_features(G, i, j, k, o, phi);
+            bf16x8 feat = {};
+#pragma unroll
+            for (int e = 0; e < 4; ++e) feat[e] = tobf(phi[e]);
+            const float out = infer_group(N, feat);
+            const double yv = double(T(ok ? out * inv_scale : 0.0f));
+            s += o == side ? yv : -yv;
+        }
+        acc += s;
+    }
+    red[threadIdx.x] = acc;
+    __syncthreads();
+    for (int h = blockDim.x / 2; h > 0; h >>= 1) {
+        if (threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) aty[blockIdx.x] = red[0];
+}
+
 __global__ void k_mean_deg(const float *__restrict__ deg, int64_t n, float *__restrict__ out) {
     __shared__ double red[256];
     double s = 0.0;
@@ -982,6 +1042,20 @@ int launch_mlp_slot_features(const GraphView &G, const int64_t *slots, int64_t c
     CCP_LAUNCH_CHECK("k_mlp_slot_features");
     return CC_OK;
 }
+
+template <typename T>
+int launch_gate_sample_aty(const GraphView &G, const float *P, const int64_t *pairs, int64_t count,
+                           double *aty, hipStream_t s) {
+    if (count <= 0) return CC_OK;
+    if (count > int64_t(INT32_MAX)) return fail(CC_EINVAL, "too many sampled pairs");
+    hipLaunchKernelGGL(k_gate_sample_aty<T>, dim3(unsigned(count)), dim3(256), 0, s, G, P, pairs, aty);
+    CCP_LAUNCH_CHECK("k_gate_sample_aty");
+    return CC_OK;
+}
+template int launch_gate_sample_aty<double>(const GraphView &, const float *, const int64_t *, int64_t,
+                                            double *, hipStream_t);
+template int launch_gate_sample_aty<float>(const GraphView &, const float *, const int64_t *, int64_t,
+                                           double *, hipStream_t);
 
 int launch_mean_deg(const float *deg, int64_t n, float *out, hipStream_t s) {
     hipLaunchKernelGGL(k_mean_deg, dim3(1), dim3(256), 0, s, deg, n, out);

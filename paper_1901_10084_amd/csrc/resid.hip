@@ -324,6 +324,51 @@ __global__ void k_x_from_aty(int64_t np, const double *__restrict__ ax, const T 
     }
 }
 
+// The sampled warm-start gate: weights, labels and g of the drawn pairs, in
+// draw order, so that the pair kernels run on the sample as on all pairs.
+// An index outside [0, np) gets NaN weights.
+template <typename T>
+__global__ void k_gate_gather(int64_t np, int64_t count, const int64_t *__restrict__ pairs,
+                              const double *__restrict__ w, const uint8_t *__restrict__ d,
+                              const T *__restrict__ g, double *__restrict__ ws,
+                              uint8_t *__restrict__ ds, T *__restrict__ gs) {
+    for (int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; e < count;
+         e += int64_t(gridDim.x) * blockDim.x) {
+        const int64_t p = pairs[e];
+        const bool ok = p >= 0 && p < np;
+        ws[e] = ok ? w[p] : __builtin_nan("");
+        ds[e] = ok ? d[p] : 0;
+        gs[e] = ok ? g[p] : T(__builtin_nan(""));
+    }
+}
+
+// Each drawn pair's term of D_warm - D_cold.  With the pair rows at their
+// values after one pair pass, the dual objective of k_pair_resid,
+// D = -b'y - (gamma/2) sum (c + A'y)^2 / w, is a sum of one term per pair:
+// -d (y1 - y2) - (gamma/2) ((A'y_metric + y1 - y2)^2 + (w - y1 - y2)^2) / w.
+// ypw: the pair duals of the predicted start, whose metric part of A'y is
+// aty; ypc: those of the cold start, whose metric part is 0.
+template <typename T>
+__global__ void k_gate_delta(int64_t count, const double *__restrict__ aty,
+                             const T *__restrict__ ypw, const T *__restrict__ ypc,
+                             const double *__restrict__ ws, const uint8_t *__restrict__ ds,
+                             double gamma, double *__restrict__ delta) {
+    for (int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; e < count;
+         e += int64_t(gridDim.x) * blockDim.x) {
+        const double wv = ws[e], dv = double(ds[e]);
+        double term[2];
+#pragma unroll
+        for (int s = 0; s < 2; ++s) {
+            const T *yp = s == 0 ? ypw : ypc;
+            const double y1 = double(yp[2 * e]), y2 = double(yp[2 * e + 1]);
+            const double gx = (s == 0 ? aty[e] : 0.0) + (y1 - y2);
+            const double gf = wv + (-y1 - y2);
+            term[s] = -(dv * y1 - dv * y2) - 0.5 * gamma * ((gx * gx + gf * gf) / wv);
+        }
+        delta[e] = term[0] - term[1];
+    }
+}
+
 // ---------------------------------------------------------------------------
 // Layout conversion: schedule order -> colex order.
 // ---------------------------------------------------------------------------
@@ -478,6 +523,34 @@ int launch_slots_to_lex(const Tile *tiles, int64_t ntiles, int b, int64_t n,
     return CC_OK;
 }
 
+template <typename T>
+int launch_gate_pairs(int64_t np, int64_t count, const int64_t *pairs, const double *w, const uint8_t *d,
+                      const T *g, double *ws, uint8_t *ds, T *gs, hipStream_t s) {
+    if (count <= 0) return CC_OK;
+    hipLaunchKernelGGL(k_gate_gather<T>, dim3(grid_of(count, 256)), dim3(256), 0, s, np, count, pairs,
+                       w, d, g, ws, ds, gs);
+    CCP_LAUNCH_CHECK("k_gate_gather");
+    return CC_OK;
+}
+
+template <typename T>
+int launch_gate_delta(int64_t count, const double *aty, const T *ypw, const T *ypc, const double *ws,
+                      const uint8_t *ds, double gamma, double *delta, hipStream_t s) {
+    if (count <= 0) return CC_OK;
+    hipLaunchKernelGGL(k_gate_delta<T>, dim3(grid_of(count, 256)), dim3(256), 0, s, count, aty, ypw,
+                       ypc, ws, ds, gamma, delta);
+    CCP_LAUNCH_CHECK("k_gate_delta");
+    return CC_OK;
+}
+
+template int launch_gate_pairs<double>(int64_t, int64_t, const int64_t *, const double *, const uint8_t *,
+                                       const double *, double *, uint8_t *, double *, hipStream_t);
+template int launch_gate_pairs<float>(int64_t, int64_t, const int64_t *, const double *, const uint8_t *,
+                                      const float *, double *, uint8_t *, float *, hipStream_t);
+template int launch_gate_delta<double>(int64_t, const double *, const double *, const double *,
+                                       const double *, const uint8_t *, double, double *, hipStream_t);
+template int launch_gate_delta<float>(int64_t, const double *, const float *, const float *,
+                                      const double *, const uint8_t *, double, double *, hipStream_t);
 template int launch_nearness_pair_resid<double>(int64_t, const double *, const double *,
                                                 const double *, const double *, double *,
                                                 hipStream_t);

@@ -117,9 +117,26 @@ def warm_start(solver, net: Network, deg) -> dict:
                                    ctypes.byref(ub)))
     solver.invalidate_mask()
     solver.sweeps = 0
+    smp = solver.ctx.last_gate_sample()
     return {"accepted": bool(acc.value), "dual_warm": dw.value, "dual_cold": dc.value,
             "dual_bound": ub.value,
-            "gap_share": (dw.value - dc.value) / (ub.value - dc.value)}
+            "gap_share": (dw.value - dc.value) / (ub.value - dc.value),
+            "sample_drawn": smp["drawn"], "sample_gain": smp["gain"],
+            "sample_std_error": smp["std_error"], "sample_rejected": smp["rejected"]}
+
+
+def gate_terms(solver, net: Network, deg, pairs, want_delta=True):
+    """Terms of the warm-start gate for the given pairs (packed indices, a
+    device int64 tensor): their metric A'y at the predicted duals and their
+    terms of D_warm - D_cold (cc_warm_gate_terms)."""
+    pairs = pairs.to(device="cuda", dtype=torch.int64).contiguous()
+    aty = torch.empty(pairs.numel(), device="cuda", dtype=torch.float64)
+    delta = torch.empty_like(aty) if want_delta else None
+    C.check(C._L.cc_warm_gate_terms(solver.ctx.handle, net.params.data_ptr(), deg.data_ptr(),
+                                    solver.w.data_ptr(), solver.d.data_ptr(), solver.gamma,
+                                    solver.g.data_ptr(), pairs.data_ptr(), pairs.numel(),
+                                    aty.data_ptr(), None if delta is None else delta.data_ptr()))
+    return aty, delta
 
 
 def degrees(inst, device="cuda"):

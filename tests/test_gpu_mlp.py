@@ -298,3 +298,127 @@ def test_fused_warm_start_equals_the_separate_passes(b, prec):
     r.pair_pass()
     for a in ("x", "f", "y_pair"):
         assert torch.equal(getattr(r, a), getattr(s, a)), a
+
+
+# --------------------------------------------------------------------------
+# The sampled gate: per-pair terms of D_warm - D_cold (cc_warm_gate_terms)
+# and the early rejection it allows (cc_set_gate_sample).
+# --------------------------------------------------------------------------
+def _oracle_predictions(inst, params):
+    """The reference network's dual for every metric row, colex order."""
+    i, j, k = oracle.colex_triplets(inst.n)
+    y = np.zeros((i.size, 3))
+    for o in range(3):
+        phi = M.features(inst.d, inst.w, inst.deg, i, j, k, np.full(i.size, o))
+        y[:, o] = M.forward(params, phi)[0] / (inst.n - 2)
+    return y.ravel()
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_gate_terms_match_the_oracle(prec):
+    """Every pair's metric A'y at the predicted duals and its term of
+    D_warm - D_cold, against the oracle's on its own reference predictions.
+    The network differs from the reference only where a hidden value sits
+    on a bf16 rounding boundary (see test_inference_matches_reference); a
+    wrong coefficient, side or row moves a pair's sum by whole predictions."""
+    inst = I.planted_partition(60, 3, 0.25, 0.05, seed=3, gamma=5.0)
+    net, deg = W.load(), W.degrees(inst)
+    ref = oracle.gate_pair_terms(inst.n, inst.gamma, inst.w, inst.d,
+                                 _oracle_predictions(inst, net.host_params()))
+    s = C.Solver.from_instance(inst, b=16, prec=prec)
+    npairs = inst.n * (inst.n - 1) // 2
+    rng = np.random.default_rng(0)
+    pairs = np.concatenate([np.arange(npairs), rng.integers(0, npairs, 200)])
+    aty, delta = W.gate_terms(s, net, deg, torch.as_tensor(pairs))
+    aty, delta = aty.cpu().numpy(), delta.cpu().numpy()
+    ra, rd = ref["aty"][pairs], (ref["term_warm"] - ref["term_cold"])[pairs]
+    ea = np.abs(aty - ra) / np.abs(ra).max()
+    ed = np.abs(delta - rd) / np.abs(rd).max()
+    print(f"{prec}: A'y rel err max {ea.max():.3g} median {np.median(ea):.3g}; "
+          f"delta rel err max {ed.max():.3g} median {np.median(ed):.3g}", flush=True)
+    assert ea.max() <= 1e-2 and np.median(ea) <= 1e-4
+    assert ed.max() <= 1e-2 and np.median(ed) <= 1e-4
+    # repeats of a pair give the same bits
+    for e in range(npairs, pairs.size):
+        assert aty[e] == aty[pairs[e]] and delta[e] == delta[pairs[e]]
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_gate_terms_sum_to_the_exact_gate(prec):
+    """Over all pairs the terms add up to the exact gate's D_warm - D_cold,
+    and each pair's A'y is the full inference's (x(y) of the predicted duals
+    with zero pair duals is -gamma A'y / w).  Only the FP64 summation order of
+    A'y differs, and in FP32 the rounding of x = x(y) that follows it."""
+    inst = I.training_graph(2001)
+    net, deg = W.load(), W.degrees(inst)
+    s = C.Solver.from_instance(inst, b=16, prec=prec)
+    s.ctx.set_gate_sample(0)
+    info = W.warm_start(s, net, deg)
+    assert info["sample_drawn"] == 0 and info["accepted"]
+    npairs = inst.n * (inst.n - 1) // 2
+    r = C.Solver.from_instance(inst, b=16, prec=prec)
+    aty, delta = W.gate_terms(r, net, deg, torch.arange(npairs))
+    gap = info["dual_bound"] - info["dual_cold"]
+    got, want = float(delta.sum()), info["dual_warm"] - info["dual_cold"]
+    print(f"{prec}: sum of terms {got:.9g}, exact gain {want:.9g}, gap {gap:.6g}", flush=True)
+    assert abs(got - want) <= (1e-10 if prec == "f64" else 1e-6) * gap
+    if prec == "f64":
+        W.infer(r, net, deg, r.y)
+        r.y_pair.zero_()
+        x, _ = r.x_from_y()
+        full = -x.double() * r.w / inst.gamma
+        assert float((aty - full).abs().max()) <= 1e-13 * float(full.abs().max())
+
+
+def test_sampled_gate_rejects_a_bad_start_early():
+    """A network that predicts every dual far too large: the sample alone
+    rejects it, the state is the cold start bit for bit, and the estimate
+    lies within a few standard errors of the exact gain."""
+    p = M.init_params(3)
+    p[1248] = 1.0e3
+    net = W.Network(params=p)
+    inst = I.planted_partition(600, 4, 0.1, 0.005, seed=11, gamma=5.0)
+    deg = W.degrees(inst)
+    edges = int((inst.d == 0).sum())
+    assert 24 * (edges + 1024) <= inst.n * (inst.n - 1) // 2   # the estimate runs
+    for prec in ("f32", "f64"):
+        s = C.Solver.from_instance(inst, b=16, prec=prec)
+        s.sweep(2)
+        s.ctx.set_gate_sample(1024)
+        info = W.warm_start(s, net, deg)
+        print(prec, info, flush=True)
+        assert info["sample_drawn"] == edges + 1024
+        assert info["sample_rejected"] and not info["accepted"]
+        cold = C.Solver.from_instance(inst, b=16, prec=prec)
+        for a in ("x", "f", "y", "y_pair"):
+            assert torch.equal(getattr(s, a), getattr(cold, a)), a
+        e = C.Solver.from_instance(inst, b=16, prec=prec)
+        e.ctx.set_gate_sample(0)
+        exact = W.warm_start(e, net, deg)
+        assert exact["sample_drawn"] == 0 and not exact["accepted"]
+        assert exact["dual_cold"] == info["dual_cold"] and exact["dual_bound"] == info["dual_bound"]
+        est, se = info["sample_gain"], info["sample_std_error"]
+        true_gain = exact["dual_warm"] - exact["dual_cold"]
+        assert info["dual_warm"] == info["dual_cold"] + est
+        assert abs(est - true_gain) <= 5.0 * se, (est, se, true_gain)
+
+
+def test_sampled_gate_keeps_a_good_start():
+    """The trained network on a graph of its family (100-node blocks, the
+    training graphs' densities): the estimate does not reject, and the exact
+    gate's start is the same, bit for bit, as with the estimate turned off."""
+    inst = I.planted_partition(1000, 10, 0.25, 0.01, seed=12, gamma=5.0)
+    net, deg = W.load(), W.degrees(inst)
+    edges = int((inst.d == 0).sum())
+    assert 24 * (edges + 1024) <= inst.n * (inst.n - 1) // 2
+    states = []
+    for count in (1024, 0):
+        s = C.Solver.from_instance(inst, b=16, prec="f32")
+        s.ctx.set_gate_sample(count)
+        info = W.warm_start(s, net, deg)
+        print(count, info, flush=True)
+        assert info["accepted"] and not info["sample_rejected"]
+        assert info["sample_drawn"] == (edges + count if count else 0)
+        states.append(s)
+    for a in ("x", "f", "y", "y_pair"):
+        assert torch.equal(getattr(states[0], a), getattr(states[1], a)), a

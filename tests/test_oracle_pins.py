@@ -419,3 +419,50 @@ def test_second_sweep_prefix_matches_dense(n, b):
     dense = np.zeros_like(s.y)
     dense[3 * t + o] = y
     assert np.array_equal(dense, s.y)
+
+
+# --------------------------------------------------------------------------
+# The warm-start gate's per-pair terms: once the pair rows have had their
+# pass, the dual of (qp) (Sec. II-B) is a sum of one term per pair, because
+# b = 0 on every metric row and W is diagonal.
+# --------------------------------------------------------------------------
+def test_gate_terms_single_triplet():
+    """n = 3: the metric part of A'y, written out for the one triplet's rows
+    (long side 01, 02, 12)."""
+    a, b, c = 0.3, 0.05, 0.7
+    inst = I.random_signed(3, seed=1, gamma=2.0)
+    t = oracle.gate_pair_terms(3, inst.gamma, inst.w, inst.d, np.array([a, b, c]))
+    assert np.allclose(t["aty"], [a - b - c, b - a - c, c - a - b], rtol=0, atol=1e-15)
+
+
+@pytest.mark.parametrize("n,seed", [(9, 0), (25, 4)])
+def test_gate_terms_sum_to_the_dual_objective(n, seed):
+    inst = I.random_signed(n, seed=seed, gamma=2.0, weighted=True)
+    rng = np.random.default_rng(seed)
+    nt = oracle.num_triplets(n)
+    y = rng.exponential(0.05, 3 * nt) * (rng.random(3 * nt) < 0.3)
+    t = oracle.gate_pair_terms(n, inst.gamma, inst.w, inst.d, y)
+    lib = oracle.lib()
+    # the arrays stay referenced across the calls that read them
+    w64, d8, y0 = np.ascontiguousarray(inst.w, dtype=np.float64), np.ascontiguousarray(inst.d, dtype=np.uint8), np.zeros_like(y)
+    ypw, ypc = t["y_pair_warm"], t["y_pair_cold"]
+    Dw = lib.orc_dual_objective(n, inst.gamma, w64.ctypes.data, d8.ctypes.data, y.ctypes.data, ypw.ctypes.data)
+    Dc = lib.orc_dual_objective(n, inst.gamma, w64.ctypes.data, d8.ctypes.data, y0.ctypes.data, ypc.ctypes.data)
+    assert abs(t["term_warm"].sum() - Dw) <= 1e-12 * abs(Dw)
+    assert abs(t["term_cold"].sum() - Dc) <= 1e-12 * abs(Dc)
+    # A'y from its definition against the oracle's x(y) = -gamma W^-1 (c + A'y)
+    s = oracle.State.from_instance(inst)
+    s.y[:] = y
+    x, _ = s.x_from_y()
+    assert np.abs(t["aty"] + x * inst.w / inst.gamma).max() <= 1e-13 * max(1.0, np.abs(t["aty"]).max())
+    # after the pass, each pair's duals maximise its term over y1, y2 >= 0
+    w, dv, g = inst.w, inst.d.astype(np.float64), inst.gamma
+    for name, ax in (("warm", t["aty"]), ("cold", np.zeros_like(t["aty"]))):
+        yp = t["y_pair_" + name]
+        y1, y2 = yp[0::2], yp[1::2]
+        term = lambda a1, a2: -(dv * a1 - dv * a2) - 0.5 * g * ((ax + a1 - a2) ** 2 + (w - a1 - a2) ** 2) / w
+        base = term(y1, y2)
+        assert np.allclose(base, t["term_" + name], rtol=1e-14, atol=1e-14)
+        for e1, e2 in ((1e-4, 0), (0, 1e-4), (-1e-4, 0), (0, -1e-4)):
+            a1, a2 = np.maximum(y1 + e1, 0.0), np.maximum(y2 + e2, 0.0)
+            assert (term(a1, a2) <= base + 1e-12 * np.abs(base).max()).all()
