@@ -1623,11 +1623,14 @@ int cc_warm_gate_terms(cc_ctx *c, const float *params, const float *deg, const d
     if (c->n < 3) return fail(CC_EINVAL, "no pairs to sample");
     GraphView G;
     if ((rc = graph_view(c, w, d, deg, G))) return rc;
-    if (c->prec == CC_F64)
-        return gate_terms_t<double>(c, G, params, w, d, gamma, (const double *)g, pairs, count, aty_out,
-                                    delta_out);
-    return gate_terms_t<float>(c, G, params, w, d, gamma, (const float *)g, pairs, count, aty_out,
-                               delta_out);
+    rc = (c->prec == CC_F64)
+             ? gate_terms_t<double>(c, G, params, w, d, gamma, (const double *)g, pairs, count, aty_out,
+                                    delta_out)
+             : gate_terms_t<float>(c, G, params, w, d, gamma, (const float *)g, pairs, count, aty_out,
+                                   delta_out);
+    if (rc) return rc;
+    CCP_HIP_CHECK(hipStreamSynchronize(c->stream));
+    return CC_OK;
 }
 
 }  // extern "C"

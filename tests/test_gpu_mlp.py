@@ -422,3 +422,20 @@ def test_sampled_gate_keeps_a_good_start():
         states.append(s)
     for a in ("x", "f", "y", "y_pair"):
         assert torch.equal(getattr(states[0], a), getattr(states[1], a)), a
+
+
+def test_gate_terms_edge_cases():
+    """An index outside [0, N_p) gives NaN and leaves its neighbours' values
+    alone; no pairs is a no-op; n = 3 has one pair per side of its triplet."""
+    inst = I.random_signed(3, seed=2, gamma=2.0)
+    net, deg = W.load(), W.degrees(inst)
+    s = C.Solver.from_instance(inst, b=8, prec="f64")
+    aty, delta = W.gate_terms(s, net, deg, torch.tensor([-1, 3, 0, 1, 2]))
+    aty, delta = aty.cpu().numpy(), delta.cpu().numpy()
+    assert np.isnan(aty[:2]).all() and np.isnan(delta[:2]).all()
+    assert np.isfinite(aty[2:]).all() and np.isfinite(delta[2:]).all()
+    ref = oracle.gate_pair_terms(3, inst.gamma, inst.w, inst.d, _oracle_predictions(inst, net.host_params()))
+    scale = max(1e-30, np.abs(ref["aty"]).max())
+    assert np.abs(aty[2:] - ref["aty"]).max() <= 1e-2 * scale
+    e, _ = W.gate_terms(s, net, deg, torch.zeros(0, dtype=torch.int64))
+    assert e.numel() == 0

@@ -51,3 +51,15 @@ def test_null_pointers_rejected():
     assert C._L.cc_sweep(None, None, None, None, None, None, None, 1, 0) == C.CC_EINVAL
     assert C._L.cc_destroy(None) == C.CC_OK
     assert C._L.cc_widen(None, None, -1, None) == C.CC_EINVAL
+
+
+def test_gate_entry_points_reject_bad_arguments():
+    """The sampled gate's entry points check their arguments before any GPU
+    call: a null context, a negative or oversized count."""
+    import ctypes
+    from paper_1901_10084_amd import ccproj as C
+    assert C._L.cc_set_gate_sample(None, 16) == C.CC_EINVAL
+    assert C._L.cc_last_gate_sample(None, None, None, None, None) == C.CC_EINVAL
+    assert C._L.cc_warm_gate_terms(None, None, None, None, None, 1.0, None, None, 1, None,
+                                   None) == C.CC_EINVAL
+    assert C.last_error()
