@@ -439,3 +439,38 @@ def test_gate_terms_edge_cases():
     assert np.abs(aty[2:] - ref["aty"]).max() <= 1e-2 * scale
     e, _ = W.gate_terms(s, net, deg, torch.zeros(0, dtype=torch.int64))
     assert e.numel() == 0
+
+
+def test_one_shot_solve_with_the_warm_start():
+    """cc_solve_cc_lp with CC_WARM_MLP, both branches of the gate.
+    The shipped network on a held-out graph of its family is kept (FP32):
+    fewer sweeps to 1e-4 than the cold start and the same objective.  A
+    network with a huge output bias at n = 600 is rejected by the estimate
+    (FP64, where the estimate runs): the solve is the cold one, bit for bit."""
+    inst = I.training_graph(2002)
+    net = W.load()
+    params, deg = net.host_params().astype(np.float32), inst.deg.astype(np.float32)
+    rc0, x0, _, i0 = C.solve_cc_lp(inst.n, inst.w, inst.d, inst.gamma, tol=1e-4, b=16,
+                                   mode=C.CC_MODE_F32)
+    rc1, x1, _, i1 = C.solve_cc_lp(inst.n, inst.w, inst.d, inst.gamma, tol=1e-4, b=16,
+                                   mode=C.CC_MODE_F32, mlp_weights=params, deg=deg)
+    print("kept:", i0["sweeps"], i1["sweeps"], i1["warm_accepted"], i1["warm_sampled"], flush=True)
+    assert rc0 == C.CC_OK and rc1 == C.CC_OK
+    assert i1["warm_accepted"] == 1 and i1["warm_sampled"] == 0
+    assert i1["sweeps"] < i0["sweeps"]
+    p0, p1 = i0["resid"]["primal_qp"], i1["resid"]["primal_qp"]
+    assert abs(p1 - p0) <= 1e-3 * abs(p0)
+
+    bad = M.init_params(3)
+    bad[1248] = 1.0e3
+    inst = I.planted_partition(600, 4, 0.1, 0.005, seed=11, gamma=5.0)
+    deg = inst.deg.astype(np.float32)
+    rc0, x0, _, i0 = C.solve_cc_lp(inst.n, inst.w, inst.d, inst.gamma, tol=1e-3, b=16,
+                                   mode=C.CC_MODE_F64)
+    rc1, x1, _, i1 = C.solve_cc_lp(inst.n, inst.w, inst.d, inst.gamma, tol=1e-3, b=16,
+                                   mode=C.CC_MODE_F64, mlp_weights=bad.astype(np.float32), deg=deg)
+    print("rejected:", i0["sweeps"], i1["sweeps"], i1["warm_accepted"], i1["warm_sampled"], flush=True)
+    assert rc0 == C.CC_OK and rc1 == C.CC_OK
+    assert i1["warm_accepted"] == 0 and i1["warm_sampled"] == 1
+    assert i1["sweeps"] == i0["sweeps"]
+    assert np.array_equal(x0, x1)
