@@ -162,6 +162,7 @@ F32_CASES = [
     (lambda: I.random_signed(300, seed=12, gamma=10.0, weighted=True), 32, 3),  # weighted, ragged
     (lambda: I.workload(1), 16, 3),                                             # n = 500
     (lambda: I.random_signed(200, seed=13, gamma=10.0, weighted=True), 32, 3),
+    (lambda: I.random_signed(75, seed=14, gamma=3.0, weighted=True), 24, 3),   # b = 24, tail of 3
 ]
 
 
