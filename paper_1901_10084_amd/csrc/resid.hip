@@ -124,6 +124,87 @@ k_metric_resid(const Tile *__restrict__ tiles, const int32_t *__restrict__ chunk
         for (int e = 0; e < 4; ++e) partial[int64_t(blockIdx.x) * 4 + e] = v[e];
 }
 
+// Metric rows, violations only (no duals read): the maximum of
+// k_metric_resid, bit for bit, in fewer operations.  A read-only pass needs
+// no conflict-free order, so each lane walks its middle offsets jl in order
+// over the range where (i, j, k) is a triplet (i < j < k < n); a step whose
+// middle block lies strictly inside the tile and whose blocks are whole
+// (every lane valid for every jl) runs without any test.  The three
+// negated slacks are those of k_metric_resid (a - b = -(b - a) exactly).
+// The finiteness check is taken on the x values as they are staged: every
+// pair lies in some triplet, and a slack of finite values overflows only
+// for |x| above DBL_MAX / 2.  partial[chunk*4 + 0..3] = {max violation, 0,
+// 0, non-finite flag}, the layout of k_metric_resid.
+template <typename T, int B>
+__global__ void __launch_bounds__(B ? B * B : 1024)
+k_metric_viol(const Tile *__restrict__ tiles, const int32_t *__restrict__ chunks, int b_rt, int64_t n,
+              const T *__restrict__ x, double *__restrict__ partial) {
+    const int b = B ? B : b_rt;
+    const int tid = threadIdx.x;
+    const int il = tid / b, kl = tid - (tid / b) * b;
+    const Tile tl = tiles[chunks[2 * int64_t(blockIdx.x)]];
+    const int m0 = chunks[2 * int64_t(blockIdx.x) + 1];
+    const int P = tl.P, Q = tl.Q;
+    const int m1 = min(m0 + kChunkSteps, Q - P + 1);  // this chunk's tile steps: [m0, m1)
+    __shared__ double As[1024], Bs[1024], Cs[1024];
+    __shared__ double red[4 * 16];
+    const int64_t i = int64_t(P) * b + il, k = int64_t(Q) * b + kl;
+    const bool lane_ok = i < k && k < n;
+    double bad = 0.0;
+    const double xc = lane_ok ? double(x[pidx(i, k)]) : 0.0;
+    if (!finite(xc)) bad = 1.0;
+    Cs[tid] = xc;
+    double vmax = 0.0;
+    const int nb = int((n + b - 1) / b);
+    const bool desc = tile_desc(P, Q, nb);
+    const bool q_whole = int64_t(Q + 1) * b <= n;
+    for (int m = m0; m < m1; ++m) {
+        const int J = tile_J(P, Q, m, desc);
+        if (J != Q) {
+            const int64_t ii = int64_t(P) * b + il, jj = int64_t(J) * b + kl;
+            const double v = (ii < jj && jj < n) ? double(x[pidx(ii, jj)]) : 0.0;
+            if (!finite(v)) bad = 1.0;
+            As[tid] = v;
+        }
+        if (J != P) {
+            const int64_t jj = int64_t(J) * b + il, kk = int64_t(Q) * b + kl;
+            const double v = (jj < kk && kk < n) ? double(x[pidx(jj, kk)]) : 0.0;
+            if (!finite(v)) bad = 1.0;
+            Bs[tid] = v;
+        }
+        __syncthreads();
+        const double *Ab = (J == Q) ? Cs : As;
+        const double *Bb = (J == P) ? Cs : Bs;
+        if (P < J && J < Q && q_whole) {
+            // every (i, j, k) of the step is a triplet
+            const double *arow = Ab + il * b;
+#pragma unroll
+            for (int jl = 0; jl < (B ? B : 32); ++jl) {
+                if (!B && jl >= b) break;
+                const double xa = arow[jl], xb = Bb[jl * b + kl];
+                vmax = fmax(vmax, fmax(xa - (xc + xb), fmax(xc - (xa + xb), xb - (xa + xc))));
+            }
+        } else if (lane_ok) {
+            // i < j: jl > il in the tile's own first block; j < k: jl < kl
+            // in its last; j < n
+            const int lo = (J == P) ? il + 1 : 0;
+            int hi = (J == Q) ? kl : b;
+            const int64_t room = n - int64_t(J) * b;
+            if (room < hi) hi = int(room);
+            for (int jl = lo; jl < hi; ++jl) {
+                const double xa = Ab[il * b + jl], xb = Bb[jl * b + kl];
+                vmax = fmax(vmax, fmax(xa - (xc + xb), fmax(xc - (xa + xb), xb - (xa + xc))));
+            }
+        }
+        __syncthreads();
+    }
+    double v[4] = {vmax, 0.0, 0.0, bad};
+    const int op[4] = {1, 0, 1, 1};
+    block_reduce<4>(v, op, red);
+    if (tid == 0)
+        for (int e = 0; e < 4; ++e) partial[int64_t(blockIdx.x) * 4 + e] = v[e];
+}
+
 // ---------------------------------------------------------------------------
 // Pair rows and the objective sums.  partial[block*10 + e]:
 //  0 max pair violation   1 sum w f          2 sum w (x^2 + f^2)
@@ -438,6 +519,16 @@ template <typename T>
 int launch_metric_resid(const Tile *tiles, const int32_t *chunks, int64_t nchunks, int b, int64_t n,
                         const T *x, const T *y, double *partial, hipStream_t s) {
     const dim3 grid = dim3(unsigned(nchunks));
+    if (!y) {
+        switch (b) {
+            case 8: hipLaunchKernelGGL((k_metric_viol<T, 8>), grid, dim3(64), 0, s, tiles, chunks, b, n, x, partial); break;
+            case 16: hipLaunchKernelGGL((k_metric_viol<T, 16>), grid, dim3(256), 0, s, tiles, chunks, b, n, x, partial); break;
+            case 32: hipLaunchKernelGGL((k_metric_viol<T, 32>), grid, dim3(1024), 0, s, tiles, chunks, b, n, x, partial); break;
+            default: hipLaunchKernelGGL((k_metric_viol<T, 0>), grid, dim3(b * b), 0, s, tiles, chunks, b, n, x, partial); break;
+        }
+        CCP_LAUNCH_CHECK("k_metric_viol");
+        return CC_OK;
+    }
     switch (b) {
         case 8: hipLaunchKernelGGL((k_metric_resid<T, 8>), grid, dim3(64), 0, s, tiles, chunks, b, n, x, y, partial); break;
         case 16: hipLaunchKernelGGL((k_metric_resid<T, 16>), grid, dim3(256), 0, s, tiles, chunks, b, n, x, y, partial); break;

@@ -137,6 +137,35 @@ def test_residuals_and_x_from_y(prec):
     assert rel_err(f.cpu().numpy(), fo) <= (1e-12 if prec == "f64" else 1e-5)
 
 
+@pytest.mark.parametrize("n,b,prec", [(3, 1, "f64"), (5, 8, "f64"), (13, 4, "f64"), (37, 8, "f32"),
+                                      (50, 24, "f64"), (70, 32, "f64"), (130, 16, "f32"),
+                                      (100, 16, "f64"), (300, 32, "f32")])
+def test_violation_check_matches_the_full_residuals(n, b, prec):
+    """The violation-only check (cc_residuals with CC_RESID_VIOL, the solve's
+    stop test) walks each lane's triplets in order rather than the
+    conflict-free order; its maximum is the full residual pass's, bit for
+    bit, and the oracle's.  A non-finite x is reported by both."""
+    inst = I.random_signed(n, seed=n + 3 * b, gamma=2.0, weighted=True)
+    g = C.Solver.from_instance(inst, b=b, prec=prec)
+    o = oracle.State.from_instance(inst)
+    g.sweep(2)
+    o.sweep(2, b=b)
+    rv = g.residuals(C.CC_RESID_VIOL)
+    ra = g.residuals(C.CC_RESID_ALL)
+    ro = o.residuals()
+    print(n, b, prec, rv["max_viol_metric"], ra["max_viol_metric"], ro["max_viol_metric"], flush=True)
+    assert rv["max_viol_metric"] == ra["max_viol_metric"]
+    assert rv["max_viol_pair"] == ra["max_viol_pair"]
+    tol = 1e-12 if prec == "f64" else 1e-5
+    assert abs(rv["max_viol_metric"] - ro["max_viol_metric"]) <= tol * max(1.0, ro["max_viol_metric"])
+    for bad in (float("nan"), float("inf")):
+        h = C.Solver.from_instance(inst, b=b, prec=prec)
+        h.sweep(1)
+        h.x[h.x.numel() // 2] = bad
+        assert h.residuals(C.CC_RESID_VIOL, raise_nonfinite=False).get("nonfinite")
+        assert h.residuals(C.CC_RESID_ALL, raise_nonfinite=False).get("nonfinite")
+
+
 @pytest.mark.parametrize("n,b,prec", [(45, 8, "f64"), (70, 16, "f64"), (100, 32, "f64"),
                                       (70, 16, "f32"), (73, 24, "f64")])
 def test_x_from_y_dataflow(n, b, prec):
