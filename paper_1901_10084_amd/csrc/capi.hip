@@ -4,6 +4,7 @@
 #include <cmath>
 #include <cstring>
 #include <mutex>
+#include <new>
 #include <string>
 #include <vector>
 
@@ -1356,21 +1357,36 @@ constexpr uint64_t kGateSeed = 0x5EED5A3D1E9A7Eull;
 // the standard error 30-fold against a uniform sample of all pairs of the
 // same size.  *ran is false when the sample would cost more than 1/8 of the
 // full inference, i.e. when 24 (edges + gate_sample) > N_p (each pair
-// takes 3 (n - 2) rows of the 3 C(n,3)), or when gate_sample is 0.
+// takes 3 (n - 2) rows of the 3 C(n,3)), when gate_sample is 0, or when the
+// host cannot hold the labels and the pair list.
 template <typename T>
 int gate_estimate_t(cc_ctx *c, const GraphView &G, const float *P, const double *w, const uint8_t *d,
                     double gamma, const T *g, bool *ran, double *est, double *se) {
     *ran = false;
     const int64_t S = c->gate_sample, np = num_pairs(c->n);
     if (S <= 0 || 24.0 * double(S) > double(np)) return CC_OK;
-    std::vector<uint8_t> hd(static_cast<size_t>(np), 0);
+    // host room for the labels and the pair list, else the exact gate alone
+    // decides (the estimate only saves time)
+    std::vector<uint8_t> hd;
+    std::vector<int64_t> pairs;
+    std::vector<double> hdl;
+    try {
+        hd.assign(static_cast<size_t>(np), 0);
+    } catch (const std::bad_alloc &) {
+        return CC_OK;
+    }
     CCP_HIP_CHECK(hipMemcpyAsync(hd.data(), d, size_t(np), hipMemcpyDeviceToHost, c->stream));
     CCP_HIP_CHECK(hipStreamSynchronize(c->stream));
-    std::vector<int64_t> pairs;
+    const int64_t E = int64_t(std::count(hd.begin(), hd.end(), uint8_t(0))), Nn = np - E;
+    if (24.0 * double(E + S) > double(np)) return CC_OK;
+    try {
+        pairs.reserve(static_cast<size_t>(E + S));
+        hdl.assign(static_cast<size_t>(E + S), 0.0);
+    } catch (const std::bad_alloc &) {
+        return CC_OK;
+    }
     for (int64_t p = 0; p < np; ++p)
         if (hd[size_t(p)] == 0) pairs.push_back(p);
-    const int64_t E = int64_t(pairs.size()), Nn = np - E;
-    if (24.0 * double(E + S) > double(np)) return CC_OK;
     // the negative pairs: uniform draws over all pairs, positive ones redrawn
     uint64_t st = kGateSeed;
     for (int64_t k = 0; k < S;) {
@@ -1388,7 +1404,6 @@ int gate_estimate_t(cc_ctx *c, const GraphView &G, const float *P, const double 
     double *aty = reinterpret_cast<double *>(dp + M), *delta = aty + M;
     CCP_HIP_CHECK(hipMemcpyAsync(dp, pairs.data(), size_t(M) * sizeof(int64_t), hipMemcpyHostToDevice, c->stream));
     if ((rc = gate_terms_t<T>(c, G, P, w, d, gamma, g, dp, M, aty, delta))) return rc;
-    std::vector<double> hdl(static_cast<size_t>(M), 0.0);
     CCP_HIP_CHECK(hipMemcpyAsync(hdl.data(), delta, size_t(M) * sizeof(double), hipMemcpyDeviceToHost, c->stream));
     CCP_HIP_CHECK(hipStreamSynchronize(c->stream));
     double exact = 0.0, mean = 0.0, var = 0.0;
