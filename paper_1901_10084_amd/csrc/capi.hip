@@ -231,7 +231,11 @@ int ensure_dataflow(cc_ctx *c) {
     if (!dataflow_b(c->b)) return fail(CC_EINVAL, "the dataflow executor supports b = 8, 16, 24 and 32");
     std::vector<DTile> tiles;
     std::vector<uint32_t> needs, K;
-    build_dataflow_tables(c->n, c->b, tiles, needs, K);
+    try {
+        build_dataflow_tables(c->n, c->b, tiles, needs, K);
+    } catch (const std::bad_alloc &) {
+        return fail(CC_ENOMEM, "no host memory for the dataflow tables");
+    }
     c->nblocks = int64_t(K.size());
     c->kmax = 1;
     for (uint32_t v : K) c->kmax = std::max(c->kmax, v);
@@ -521,13 +525,18 @@ int cc_create(cc_ctx **out, int64_t n, int32_t b, int32_t prec, void *stream) {
     c->nb = int((n + b - 1) / b);
     c->nrounds = 2 * c->nb - 1;
     std::vector<Tile> tiles;
-    build_schedule(c, tiles);
     std::vector<int32_t> chunks;
-    for (size_t t = 0; t < tiles.size(); ++t)
-        for (int m0 = 0; m0 <= tiles[t].Q - tiles[t].P; m0 += kChunkSteps) {
-            chunks.push_back(int32_t(t));
-            chunks.push_back(m0);
-        }
+    try {
+        build_schedule(c, tiles);
+        for (size_t t = 0; t < tiles.size(); ++t)
+            for (int m0 = 0; m0 <= tiles[t].Q - tiles[t].P; m0 += kChunkSteps) {
+                chunks.push_back(int32_t(t));
+                chunks.push_back(m0);
+            }
+    } catch (const std::bad_alloc &) {
+        cc_destroy(c);
+        return fail(CC_ENOMEM, "no host memory for the schedule");
+    }
     c->nchunks = int64_t(chunks.size() / 2);
     int rc = CC_OK;
     if (hipMalloc(&c->d_tiles, tiles.size() * sizeof(Tile)) != hipSuccess ||
@@ -934,8 +943,14 @@ int cc_compact_init(cc_ctx *c, int64_t capacity) {
     // tile of every step, for export
     std::vector<DTile> tiles;
     std::vector<uint32_t> needs, K;
-    build_dataflow_tables(c->n, c->b, tiles, needs, K);
-    std::vector<int32_t> st(size_t(ns), 0);
+    std::vector<int32_t> st;
+    try {
+        build_dataflow_tables(c->n, c->b, tiles, needs, K);
+        st.assign(size_t(ns), 0);
+    } catch (const std::bad_alloc &) {
+        compact_free(c);
+        return fail(CC_ENOMEM, "no host memory for the step table");
+    }
     for (size_t t = 0; t < tiles.size(); ++t)
         for (int m = 0; m <= tiles[t].Q - tiles[t].P; ++m) st[size_t(tiles[t].jsbase) + m] = int32_t(t);
     CCP_HIP_CHECK(hipMemcpy(c->cp_step_tile, st.data(), st.size() * sizeof(int32_t), hipMemcpyHostToDevice));
@@ -1210,7 +1225,11 @@ int cc_dataflow_tables(int64_t n, int32_t b, int64_t *ntiles, int64_t *nsteps, i
     if (n < 3 || b < 1 || b > 32) return fail(CC_EINVAL, "bad n or b");
     std::vector<DTile> tiles;
     std::vector<uint32_t> nd, kk;
-    build_dataflow_tables(n, b, tiles, nd, kk);
+    try {
+        build_dataflow_tables(n, b, tiles, nd, kk);
+    } catch (const std::bad_alloc &) {
+        return fail(CC_ENOMEM, "no host memory for the dataflow tables");
+    }
     if (ntiles) *ntiles = int64_t(tiles.size());
     if (nsteps) *nsteps = int64_t(nd.size() / 2);
     if (nblocks) *nblocks = int64_t(kk.size());
