@@ -52,3 +52,17 @@ def test_noalloc_rejects_sizes_beyond_its_scratch():
     assert "static scratch" in C.last_error()
     small = C.Context(64, 8, "f32")
     assert C._L.cc_sweep_noalloc(small.handle, *args, -1) == C.CC_EINVAL
+
+
+def test_noalloc_at_its_largest_size():
+    """ceil(n/b) = 255 blocks per side (n = 2040, b = 8: 32,640 blocks of x,
+    the most the 4 MiB array holds): equal to cc_sweep bit for bit."""
+    inst = I.random_signed(2040, seed=23, gamma=2.0, weighted=True)
+    ref, new = _pair(inst, 8, "f32")
+    ref.ctx.sweep(ref.x, ref.f, ref.y, ref.y_pair, ref.g, ref.d, 1, C.CC_EXEC_DATAFLOW)
+    ref.status()
+    new.ctx.sweep_noalloc(new.x, new.f, new.y, new.y_pair, new.g, new.d, 1)
+    for a in ("x", "f", "y", "y_pair"):
+        assert torch.equal(getattr(ref, a), getattr(new, a)), a
+    del ref, new
+    torch.cuda.empty_cache()
