@@ -528,7 +528,8 @@ int cc_last_gate_sample(const cc_ctx *ctx, int64_t *drawn, double *gain, double 
  * mask allocated and built per phase); warm: CC_WARM_NONE
  * or CC_WARM_MLP (then mlp_weights_host must point to cc_mlp_num_params()
  * floats and deg_host to n floats; see cc_warm_start_mlp for the gate;
- * info->warm_accepted tells whether the start was kept).  x_out_host: double[N_p] or NULL;
+ * info->warm_accepted tells whether the start was kept, info->warm_sampled
+ * whether the gate's estimate rejected it before the full inference).  x_out_host: double[N_p] or NULL;
  * y_lex_out_host: double[3 C(n,3)] or NULL.  Returns CC_OK, CC_ENOTCONV
  * (info filled, outputs written), or an error. */
 int cc_solve_cc_lp(int64_t n, const double *w_host, const uint8_t *d_host, double gamma,
