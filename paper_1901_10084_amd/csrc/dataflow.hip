@@ -877,8 +877,10 @@ size_t dataflow_lds_bytes(int b) {
 // VGPRs a lane; a ring of 8 sub-steps) nor at b = 32 in FP64 (1024
 // threads, at most 128; a ring of 4), so those keep 4 and 2.
 template <typename T, int B, int D> constexpr int sparse_ring() {
-    return B == 24 ? 4 : (B == 32 && sizeof(T) == 8 ? 2 : D);
+    return B == 24 ? 4 : (B == 32 ? (sizeof(T) == 8 ? 2 : 4) : D);
 }
+// Ring depth of the dense sweep at b = 32.
+template <typename T> constexpr int kDenseRing32 = sizeof(T) == 4 ? 8 : 4;
 
 template <typename T, int B, int D>
 static int launch_df_t(const DataflowArgs &a, int grid, int64_t n, T *x, const T *g, T *y,
@@ -922,7 +924,9 @@ int launch_sweep_dataflow(const DataflowArgs &a, int grid, int b, int64_t n, T *
         case 8: return launch_df_t<T, 8, 4>(a, grid, n, x, g, y, mask, cp, s);
         case 16: return launch_df_t<T, 16, 8>(a, grid, n, x, g, y, mask, cp, s);
         case 24: return launch_df_t<T, 24, 8>(a, grid, n, x, g, y, mask, cp, s);
-        case 32: return launch_df_t<T, 32, 4>(a, grid, n, x, g, y, mask, cp, s);
+        // b = 32: a ring of 8 sub-steps in FP32 (127 registers a lane, no
+        // spill; n = 4000 48.9 against 49.9 ms with 4), 4 in FP64 (8 spills)
+        case 32: return launch_df_t<T, 32, kDenseRing32<T>>(a, grid, n, x, g, y, mask, cp, s);
         default: return fail(CC_EINVAL, "the dataflow executor supports b = 8, 16, 24, 32");
     }
 }
@@ -1019,9 +1023,9 @@ int dataflow_occupancy(int b, int *blocks_per_cu) {
             if (e == hipSuccess) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, k_sweep_dataflow<T, 24, 8, false, false>, 576, lds);
             break;
         case 32:
-            e = hipFuncSetAttribute((const void *)k_sweep_dataflow<T, 32, 4, false, false>, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
-            if (e == hipSuccess) e = hipFuncSetAttribute((const void *)k_sweep_dataflow<T, 32, sparse_ring<T, 32, 4>(), true, false>, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
-            if (e == hipSuccess) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, k_sweep_dataflow<T, 32, 4, false, false>, 1024, lds);
+            e = hipFuncSetAttribute((const void *)k_sweep_dataflow<T, 32, kDenseRing32<T>, false, false>, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+            if (e == hipSuccess) e = hipFuncSetAttribute((const void *)k_sweep_dataflow<T, 32, sparse_ring<T, 32, kDenseRing32<T>>(), true, false>, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+            if (e == hipSuccess) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, k_sweep_dataflow<T, 32, kDenseRing32<T>, false, false>, 1024, lds);
             break;
         default:
             *blocks_per_cu = 0;
