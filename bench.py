@@ -949,6 +949,76 @@ def n60_solve(b=8, tol=1e-6):
     return out
 
 
+def train_report(graphs=4, reps=20):
+    """The network's training (a9) on the GPU: one Adam step on explicit
+    samples at three batch sizes (HIP events, median of `reps` steps),
+    the step on rows drawn from a solved graph (batch 8192, the shipped
+    training's, its loss read included), and the whole pipeline on `graphs`
+    training graphs (n = 300 planted partitions: FP64 solve to 1e-6, then 40
+    steps).  Useful work per sample: the forward pass (1,184 MACs), then
+    dW3 and delta2 (32 each), dW2 and delta1 (1,024 each), dW1 (128):
+    3,424 MACs = 6,848 flops."""
+    import numpy as np
+    import torch
+    from paper_1901_10084_amd import ccproj as C
+    from paper_1901_10084_amd import instances as I
+    from paper_1901_10084_amd import warmstart as W
+    flops_per_sample = 2 * (1184 + 32 + 32 + 1024 + 1024 + 128)
+    out = {"flops_per_sample": flops_per_sample, "explicit": []}
+    rng = np.random.default_rng(7)
+    net = W.Network(seed=1)
+
+    def timed(fn):
+        fn()
+        torch.cuda.synchronize()
+        ts = []
+        for _ in range(reps):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            fn()
+            e1.record()
+            torch.cuda.synchronize()
+            ts.append(e0.elapsed_time(e1))
+        return float(np.median(ts))
+
+    for batch in (8192, 65536, 1 << 20):
+        phi = torch.as_tensor(rng.normal(0, 1, (batch, 4)).astype(np.float32)).cuda()
+        tgt = torch.as_tensor(np.maximum(rng.normal(0, 1, batch), 0).astype(np.float32)).cuda()
+        ms = timed(lambda: net.train_step(phi, tgt, lr=1e-3))
+        out["explicit"].append({"batch": batch, "ms_per_step": ms, "samples_per_s": batch / ms * 1e3,
+                                "bf16_tflops": batch * flops_per_sample / ms / 1e9})
+        log(f"train step, batch {batch}: {out['explicit'][-1]}")
+    inst = I.training_graph(1000)
+    s = C.Solver.from_instance(inst, b=16, prec="f64")
+    s.solve(tol=1e-6, max_sweeps=20000, executor=C.CC_EXEC_DATAFLOW)
+    deg = W.degrees(inst)
+    ms = timed(lambda: net.train_on_graph(s, s.y, deg, 8192, 1, 1e-3, 3))
+    out["graph_step_batch_8192_ms"] = ms
+    del s
+    torch.cuda.synchronize()
+    t_solve = t_train = 0.0
+    net2 = W.Network(seed=0)
+    for seed in range(1000, 1000 + graphs):
+        inst = I.training_graph(seed)
+        s = C.Solver.from_instance(inst, b=16, prec="f64")
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        s.solve(tol=1e-6, max_sweeps=20000, executor=C.CC_EXEC_DATAFLOW)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        net2.train_on_graph(s, s.y, W.degrees(inst), 8192, 40, 2e-3, seed)
+        torch.cuda.synchronize()
+        t_solve += t1 - t0
+        t_train += time.perf_counter() - t1
+        del s
+    out["pipeline"] = {"graphs": graphs, "solve_s_per_graph": t_solve / graphs,
+                       "train_s_per_graph": t_train / graphs,
+                       "note": "per graph: FP64 solve to 1e-6 (n = 300), then 40 Adam steps of 8192 rows"}
+    log(f"training pipeline: {out['pipeline']}")
+    torch.cuda.empty_cache()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -985,6 +1055,8 @@ def main():
                     help="l1 metric nearness ((mn1) with real d) at n = 2000 and 500")
     ap.add_argument("--nearness-report", action="store_true",
                     help="l2 metric nearness at n = 2000 (FP64 and FP32) beside the oracle")
+    ap.add_argument("--train-report", action="store_true",
+                    help="the network's training steps and pipeline on the GPU")
     ap.add_argument("--polish-report", action="store_true",
                     help="n = 1500 Chung-Lu: FP32 sweeps + FP64 polish vs the FP64-only solve")
     ap.add_argument("--warm-config", type=int, default=3, choices=[3, 4],
@@ -1179,6 +1251,8 @@ def main():
         out["l1_nearness"] = l1_report()
     if args.nearness_report:
         out["nearness"] = nearness_report()
+    if args.train_report:
+        out["train"] = train_report()
     if args.polish_report:
         out["polish"] = polish_report()
     if args.warm_report:

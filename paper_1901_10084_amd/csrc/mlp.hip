@@ -340,14 +340,32 @@ k_mlp_grad(Src src, int64_t count, float inv_norm, const float *__restrict__ P,
     }
 }
 
-__global__ void k_mlp_reduce(const float *__restrict__ partial, int nparts, float *__restrict__ grad,
-                             float *__restrict__ loss_out, float loss_scale) {
-    const int e = blockIdx.x * blockDim.x + threadIdx.x;
-    if (e > kNParam) return;
+// Sum of the per-workgroup partial gradients and losses.  Workgroup g takes
+// entries 64g..64g+63 (lane = entry, so every load is 64 consecutive
+// floats); wave w of its 16 sums the partials p = w, w + 16, ..., and the 16
+// wave sums are added in wave order.  The order is fixed, so the result is
+// deterministic.  (One thread per entry looping over every partial, as
+// before, left 20 waves on the chip and took 60 us at 1024 partials.)
+constexpr int kReduceWaves = 16;
+__global__ void __launch_bounds__(64 * kReduceWaves)
+k_mlp_reduce(const float *__restrict__ partial, int nparts, float *__restrict__ grad,
+             float *__restrict__ loss_out, float loss_scale) {
+    __shared__ float wsum[kReduceWaves][64];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int e = blockIdx.x * 64 + lane;
     float s = 0.0f;
-    for (int p = 0; p < nparts; ++p) s += partial[int64_t(p) * (kNParam + 1) + e];
-    if (e < kNParam) grad[e] = s;
-    else loss_out[0] = s * loss_scale;
+    if (e <= kNParam) {
+#pragma unroll 8
+        for (int p = w; p < nparts; p += kReduceWaves) s += partial[int64_t(p) * (kNParam + 1) + e];
+    }
+    wsum[w][lane] = s;
+    __syncthreads();
+    if (w == 0 && e <= kNParam) {
+        float t = 0.0f;
+        for (int k = 0; k < kReduceWaves; ++k) t += wsum[k][lane];
+        if (e < kNParam) grad[e] = t;
+        else loss_out[0] = t * loss_scale;
+    }
 }
 
 __global__ void k_adam(float *__restrict__ P, float *__restrict__ m, float *__restrict__ v,
@@ -955,6 +973,9 @@ __global__ void k_mean_deg(const float *__restrict__ deg, int64_t n, float *__re
 // Launchers.
 // ---------------------------------------------------------------------------
 int mlp_num_params() { return kNParam; }
+// One-wave workgroups, 32 samples a chunk, at most 1024 of them: 4096
+// (4 waves a SIMD) was slower at batches of 64K and 1M samples, the partials
+// to reduce growing with them.
 int mlp_grad_blocks(int64_t count) {
     int64_t c = (count + 31) / 32;
     return int(c < 1 ? 1 : (c > 1024 ? 1024 : c));
@@ -968,7 +989,7 @@ static int finish_step(float *partial, int nparts, float *P, float *m, float *v,
                        float *grad_out, float *ws_grad, float *loss_dev, float loss_scale,
                        hipStream_t s) {
     float *grad = grad_out ? grad_out : ws_grad;
-    hipLaunchKernelGGL(k_mlp_reduce, dim3((kNParam + 1 + 255) / 256), dim3(256), 0, s, partial,
+    hipLaunchKernelGGL(k_mlp_reduce, dim3((kNParam + 1 + 63) / 64), dim3(64 * kReduceWaves), 0, s, partial,
                        nparts, grad, loss_dev, loss_scale);
     CCP_LAUNCH_CHECK("k_mlp_reduce");
     if (lr > 0.0f && m && v) {
