@@ -476,3 +476,23 @@ def test_one_shot_solve_with_the_warm_start():
     assert i1["warm_accepted"] == 0 and i1["warm_sampled"] == 1
     assert i1["sweeps"] == i0["sweeps"]
     assert np.array_equal(x0, x1)
+
+
+def test_one_shot_warm_start_with_sparse_dual_access():
+    """CC_WARM_MLP with CC_MODE_SPARSE: the mask is built from the kept
+    start, and the solve is the dense one's, bit for bit (FP32 sweeps to
+    1e-4, then FP64 polish to 1e-6)."""
+    inst = I.training_graph(2003)
+    params = W.load().host_params().astype(np.float32)
+    deg = inst.deg.astype(np.float32)
+    out = {}
+    for flag in (0, C.CC_MODE_SPARSE):
+        rc, x, y, info = C.solve_cc_lp(inst.n, inst.w, inst.d, inst.gamma, tol=1e-6, b=16,
+                                       mode=C.CC_MODE_F32_POLISH | flag, mlp_weights=params, deg=deg,
+                                       want_duals=True)
+        assert rc == C.CC_OK and info["warm_accepted"] == 1
+        out[flag] = (x, y, info["sweeps"], info["sweeps_f32"])
+    print("sweeps", out[0][2:], out[C.CC_MODE_SPARSE][2:], flush=True)
+    assert out[0][2:] == out[C.CC_MODE_SPARSE][2:]
+    assert np.array_equal(out[0][0], out[C.CC_MODE_SPARSE][0])
+    assert np.array_equal(out[0][1], out[C.CC_MODE_SPARSE][1])
