@@ -140,19 +140,34 @@ def test_n4000_dataflow_prefix_matches_the_oracle(prec):
 def test_n4000_gate_rejects_the_chunglu_network():
     """On the largest workload (n = 4000 Chung-Lu, FP32, b = 32) the network
     trained on n = 300 Chung-Lu graphs raises the dual objective by a sliver
-    of the gap (it would then cost sweeps: 75 against 70 to 1e-4), so the
-    gate keeps the cold start, bit for bit."""
+    of the gap (it would then cost sweeps: 75 against 70 to 1e-4).  The
+    gate's estimate rejects it before the full inference, within four
+    standard errors of the exact gain; the exact gate (estimate off) rejects
+    it too; both times the state is the cold start, bit for bit."""
     from paper_1901_10084_amd import warmstart as W
     inst = I.workload(4)
+    net, deg = W.load(W.weights_path("chunglu300")), W.degrees(inst)
     torch.cuda.empty_cache()
     s = C.Solver.from_instance(inst, b=32, prec="f32")
-    info = W.warm_start(s, W.load(W.weights_path("chunglu300")), W.degrees(inst))
-    print(info, flush=True)
-    assert not info["accepted"]
-    assert 0.0 <= info["gap_share"] < 0.05
-    assert sum(int(torch.count_nonzero(s.y[i:i + CHUNK])) for i in range(0, s.y.numel(), CHUNK)) == 0
-    x, f, yp = s.x.clone(), s.f.clone(), s.y_pair.clone()
-    s.init_cold()
-    assert torch.equal(x, s.x) and torch.equal(f, s.f) and torch.equal(yp, s.y_pair)
-    del s, x, f, yp
+
+    def is_cold():
+        assert sum(int(torch.count_nonzero(s.y[i:i + CHUNK])) for i in range(0, s.y.numel(), CHUNK)) == 0
+        x, f, yp = s.x.clone(), s.f.clone(), s.y_pair.clone()
+        s.init_cold()
+        assert torch.equal(x, s.x) and torch.equal(f, s.f) and torch.equal(yp, s.y_pair)
+
+    est = W.warm_start(s, net, deg)
+    print(est, flush=True)
+    assert not est["accepted"] and est["sample_rejected"]
+    is_cold()
+    s.ctx.set_gate_sample(0)
+    exact = W.warm_start(s, net, deg)
+    print(exact, flush=True)
+    assert not exact["accepted"] and not exact["sample_rejected"]
+    assert 0.0 <= exact["gap_share"] < 0.05
+    assert exact["dual_cold"] == est["dual_cold"] and exact["dual_bound"] == est["dual_bound"]
+    gain = exact["dual_warm"] - exact["dual_cold"]
+    assert abs(est["sample_gain"] - gain) <= 4.0 * est["sample_std_error"]
+    is_cold()
+    del s
     torch.cuda.empty_cache()
