@@ -307,8 +307,9 @@ k_weight_classes(int64_t np, const double *__restrict__ w, const uint8_t *__rest
 }
 
 // Fixed-order final reduction: out[0..3] from the metric partials, out[4..13]
-// from the pair partials.
-__global__ void __launch_bounds__(256)
+// from the pair partials.  One workgroup of 1024 lanes: at n = 4000, b = 32
+// there are 86,336 metric partials, which 256 lanes took 94 us to walk.
+__global__ void __launch_bounds__(1024)
 k_final_reduce(const double *__restrict__ mpart, int64_t nm, const double *__restrict__ ppart,
                int64_t npb, double *__restrict__ out) {
     __shared__ double red[14 * 16];
@@ -560,7 +561,7 @@ int launch_pair_resid(int64_t np, const T *x, const T *f, const T *yp, const dou
 
 int launch_final_reduce(const double *mpart, int64_t nm, const double *ppart, double *out,
                         hipStream_t s) {
-    hipLaunchKernelGGL(k_final_reduce, dim3(1), dim3(256), 0, s, mpart, nm, ppart,
+    hipLaunchKernelGGL(k_final_reduce, dim3(1), dim3(1024), 0, s, mpart, nm, ppart,
                        int64_t(kPairBlocks), out);
     CCP_LAUNCH_CHECK("k_final_reduce");
     return CC_OK;
