@@ -522,7 +522,9 @@ int cc_last_gate_sample(const cc_ctx *ctx, int64_t *drawn, double *gain, double 
  * gap_tol max(1, |primal|) (evaluated in FP64, with A'y, only once the
  * violations are below tol; gap_tol <= 0: violations only); mode:
  * CC_MODE_F64, CC_MODE_F32 (FP32 sweeps to tol)
- * or CC_MODE_F32_POLISH (FP32 sweeps to max(tol, 1e-4), then duals widened,
+ * or CC_MODE_F32_POLISH (FP32 sweeps to max(tol, 1e-5), or, within a
+ * factor of 100 of it, until 20 sweeps bring no new least violation, then
+ * duals widened,
  * x recomputed from them in FP64 and FP64 sweeps to tol), or-ed with
  * CC_MODE_SPARSE for sparse dual access (b = 8, 16, 24, 32; same results, the
  * mask allocated and built per phase); warm: CC_WARM_NONE

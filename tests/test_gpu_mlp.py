@@ -481,7 +481,7 @@ def test_one_shot_solve_with_the_warm_start():
 def test_one_shot_warm_start_with_sparse_dual_access():
     """CC_WARM_MLP with CC_MODE_SPARSE: the mask is built from the kept
     start, and the solve is the dense one's, bit for bit (FP32 sweeps to
-    1e-4, then FP64 polish to 1e-6)."""
+    1e-5, then FP64 polish to 1e-6)."""
     inst = I.training_graph(2003)
     params = W.load().host_params().astype(np.float32)
     deg = inst.deg.astype(np.float32)
